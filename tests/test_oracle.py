@@ -1,0 +1,395 @@
+"""Pins for the CPU oracle: brute force, closed forms, the paper's worked example
+and independent library routines.  CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+
+import graphgen as gg
+import oracle as orc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TILES = (4, 8, 16, 32)
+UNR = orc.UNREACHED
+
+
+def tiny_graphs(count=60, seed0=0):
+    out = []
+    for s in range(count):
+        r = gg.rng(10_000 + s)
+        n = int(r.integers(1, 65))
+        p = float(r.choice([0.02, 0.08, 0.2, 0.5, 0.9]))
+        out.append(gg.random_graph_tiny(n, p, seed0 + s))
+    return out
+
+
+TINY = tiny_graphs()
+
+
+# ---------------------------------------------------------------- B2SR by definition
+
+def decode_b2sr(n, T, trp, tci, bits):
+    """Independent decode of B2SR arrays into a dense 0/1 matrix."""
+    a = np.zeros((len(trp) - 1) * T, dtype=np.uint8)
+    a = np.zeros((a.size, a.size if a.size else 0), dtype=np.uint8)
+    for I in range(len(trp) - 1):
+        for t in range(int(trp[I]), int(trp[I + 1])):
+            J = int(tci[t])
+            for r in range(T):
+                w = int(bits[t * T + r])
+                for c in range(T):
+                    if (w >> c) & 1:
+                        a[I * T + r, J * T + c] = 1
+    return a[:n, :n]
+
+
+@pytest.mark.parametrize("T", TILES)
+def test_b2sr_build_brute_force(T):
+    for g in TINY[:40]:
+        for lower in (False, True):
+            trp, tci, bits = orc.b2sr_build(g, T, lower_only=lower)
+            dense = g.dense()
+            if lower:
+                dense = np.tril(dense, -1)
+            ii, jj = np.nonzero(dense)
+            pairs = np.unique(np.stack([ii // T, jj // T], 1), axis=0) if ii.size else np.zeros((0, 2))
+            assert len(tci) == len(pairs) == orc.b2sr_count_tiles(g, T, lower)
+            assert trp[0] == 0 and np.all(np.diff(trp.astype(np.int64)) >= 0)
+            ntr = (g.n + T - 1) // T
+            assert len(trp) == ntr + 1
+            # tile columns strictly ascending inside each tile-row, and equal to the pair set
+            got = []
+            for I in range(ntr):
+                cols = tci[trp[I]:trp[I + 1]]
+                assert np.all(np.diff(cols.astype(np.int64)) > 0)
+                got += [(I, int(c)) for c in cols]
+            assert got == [tuple(map(int, p)) for p in pairs]
+            assert np.array_equal(decode_b2sr(g.n, T, trp, tci, bits), dense)
+            # padding bits beyond n are zero (decode above cut them; check directly)
+            if T == 4:
+                assert np.all(bits < 16)
+
+
+def test_mycielskian12_storage_matches_paper():
+    """Sec. III-C worked example: CSR and B2SR-4/8/16/32 byte sizes of mycielskian12."""
+    with open(os.path.join(GOLDEN, "mycielskian12_storage.json")) as f:
+        gold = json.load(f)
+    g = gg.mycielski(12)
+    assert g.n == 3071 and g.edges == 203600
+    assert round(orc.csr_bytes(g.nnz, g.n) / 2**20, 2) == gold["csr_MB"]
+    for T in TILES:
+        nt = orc.b2sr_count_tiles(g, T)
+        kib = orc.b2sr_bytes(nt, g.n, T) / 1024
+        assert round(kib, 2) == pytest.approx(gold["b2sr_KB"][str(T)], abs=1e-9), T
+
+
+def test_mycielski_edge_recurrence_and_triangle_free():
+    e, n = 1, 2
+    for k in range(2, 11):
+        g = gg.mycielski(k)
+        assert (g.n, g.edges) == (n, e)
+        e, n = 3 * e + n, 2 * n + 1
+    for k in (4, 6, 9):
+        g = gg.mycielski(k)
+        assert orc.tc(g) == 0
+        assert orc.masked_sum(orc.tril(g), orc.tril(g), orc.tril(g)) == 0
+        assert np.all(orc.cc(g) == 0)
+
+
+def test_tile_count_against_numpy_pairs_medium():
+    g = gg.er_gnm(3000, 9000, seed=5)
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    for T in TILES:
+        key = (rows // T) * ((g.n + T - 1) // T) + g.colind // T
+        assert orc.b2sr_count_tiles(g, T) == np.unique(key).size
+
+
+# ---------------------------------------------------------------- products vs brute force
+
+@pytest.mark.parametrize("complement", [False, True])
+def test_spmv_or_count_brute_force(complement):
+    for s, g in enumerate(TINY):
+        r = gg.rng(s)
+        x = r.random(g.n) < 0.3
+        m = r.random(g.n) < 0.5
+        A = g.dense().astype(np.int64)
+        keep = ~m if complement else m
+        cnt = A @ x.astype(np.int64)
+        assert np.array_equal(orc.spmv_or(g, x, m, complement), (cnt > 0) & keep)
+        assert np.array_equal(orc.spmv_count(g, x, m, complement), np.where(keep, cnt, 0))
+        assert np.array_equal(orc.spmv_or(g, x), cnt > 0)
+        assert np.array_equal(orc.spmv_count(g, x), cnt)
+
+
+def test_spmv_invariants_all_ones():
+    g = gg.er_gnm(2000, 5000, seed=3)
+    ones = np.ones(g.n, dtype=bool)
+    assert np.array_equal(orc.spmv_count(g, ones), g.degrees())
+    assert np.array_equal(orc.spmv_or(g, ones), g.degrees() > 0)
+
+
+def test_spmv_plus_brute_force():
+    for s, g in enumerate(TINY):
+        r = gg.rng(100 + s)
+        # integer-valued inputs make every sum exact, so the comparison is exact
+        x = r.integers(-50, 50, g.n).astype(np.float64)
+        sc = r.integers(1, 5, g.n).astype(np.float64)
+        A = g.dense().astype(np.float64)
+        assert np.array_equal(orc.spmv_plus(g, x), A @ x)
+        assert np.array_equal(orc.spmv_plus(g, x, sc), A @ (x * sc))
+        m = r.random(g.n) < 0.5
+        assert np.array_equal(orc.spmv_plus(g, x, None, m, True), np.where(~m, A @ x, 0.0))
+
+
+def test_spmv_plus_scipy_medium():
+    g = gg.er_gnm(4096, 16384, seed=1)
+    x = gg.rng(7).random(g.n)
+    ref = g.to_scipy().astype(np.float64) @ x
+    np.testing.assert_allclose(orc.spmv_plus(g, x), ref, rtol=1e-13, atol=0)
+
+
+def test_spmv_min_plus_brute_force():
+    for s, g in enumerate(TINY):
+        r = gg.rng(200 + s)
+        x = r.integers(0, 20, g.n).astype(np.float64)
+        x[r.random(g.n) < 0.2] = np.inf
+        A = g.dense().astype(bool)
+        for w in (0.0, 1.0, 2.5):
+            cand = np.where(A, x[None, :] + w, np.inf)
+            best = cand.min(axis=1) if g.n else cand.sum(axis=1)
+            assert np.array_equal(orc.spmv_min_plus(g, x, w, False), best)
+            assert np.array_equal(orc.spmv_min_plus(g, x, w, True), np.minimum(best, x))
+        m = r.random(g.n) < 0.5
+        got = orc.spmv_min_plus(g, x, 1.0, True, m, False)
+        ref = np.where(m, np.minimum(np.where(A, x[None, :] + 1, np.inf).min(axis=1, initial=np.inf), x), np.inf)
+        assert np.array_equal(got, ref)
+
+
+def test_spmv_or64_brute_force():
+    for s, g in enumerate(TINY[:30]):
+        r = gg.rng(300 + s)
+        x = r.integers(0, 2**63, g.n, dtype=np.uint64) & r.integers(0, 2**63, g.n, dtype=np.uint64)
+        v = r.integers(0, 2**63, g.n, dtype=np.uint64)
+        A = g.dense().astype(bool)
+        ref = np.array([np.bitwise_or.reduce(x[A[i]]) if A[i].any() else 0 for i in range(g.n)],
+                       dtype=np.uint64)
+        assert np.array_equal(orc.spmv_or64(g, x), ref)
+        assert np.array_equal(orc.spmv_or64(g, x, v), ref & ~v)
+        # bit b of the 64-wide product equals the Boolean product of bit b
+        for b in (0, 17, 63):
+            xb = ((x >> np.uint64(b)) & np.uint64(1)).astype(bool)
+            yb = ((ref >> np.uint64(b)) & np.uint64(1)).astype(bool)
+            assert np.array_equal(orc.spmv_or(g, xb), yb)
+
+
+def directed_csr(dense):
+    """CSR of an arbitrary (non-symmetric) 0/1 matrix, columns ascending."""
+    n = dense.shape[0]
+    rows, cols = np.nonzero(dense)
+    rp = np.zeros(n + 1, dtype=np.uint32)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return gg.Csr(n, rp, cols.astype(np.uint32), "directed")
+
+
+def test_masked_sum_brute_force():
+    for s in range(40):
+        r = gg.rng(900 + s)
+        n = int(r.integers(1, 50))
+        A, B, M = ((r.random((n, n)) < p).astype(np.int64) for p in (0.3, 0.25, 0.4))
+        a, bt, m = directed_csr(A), directed_csr(B.T), directed_csr(M)
+        P = A @ B
+        assert orc.masked_sum(a, bt, m) == int((P * M).sum())
+        assert orc.masked_sum(a, bt) == int(P.sum())
+    for g in TINY[:30]:
+        A = g.dense().astype(np.int64)
+        assert orc.masked_sum(g, g, g) == int(np.trace(A @ A @ A))
+
+
+def test_masked_sum_closed_forms():
+    for n in (3, 5, 12, 33):
+        K = gg.complete(n)
+        L = orc.tril(K)
+        assert orc.masked_sum(L, L, L) == math.comb(n, 3)
+        assert orc.masked_sum(K, K, K) == 6 * math.comb(n, 3)
+        assert orc.masked_sum(K, K) == n * (n - 1) ** 2
+    g = gg.mycielski(8)
+    deg = g.degrees().astype(np.int64)
+    assert orc.masked_sum(g, g) == int((deg ** 2).sum())
+
+
+def test_tc_closed_forms_and_brute_force():
+    for n in (3, 4, 10, 40):
+        assert orc.tc(gg.complete(n)) == math.comb(n, 3)
+    for R, C in ((2, 2), (3, 7), (20, 31)):
+        assert orc.tc(gg.king_grid(R, C)) == 4 * (R - 1) * (C - 1)
+    for g in (gg.path(50), gg.star(40), gg.grid4(9, 11), gg.cycle(30)):
+        assert orc.tc(g) == 0
+    assert orc.tc(gg.cycle(3)) == 1
+    for g in TINY:
+        A = g.dense().astype(np.int64)
+        assert orc.tc(g) == int(np.trace(A @ A @ A)) // 6
+        L = orc.tril(g)
+        assert orc.masked_sum(L, L, L) == orc.tc(g)
+
+
+# ---------------------------------------------------------------- algorithms
+
+def bfs_dense(g, src):
+    A = g.dense().astype(bool)
+    lv = np.full(g.n, UNR, dtype=np.uint32)
+    lv[src] = 0
+    front = np.zeros(g.n, dtype=bool)
+    front[src] = True
+    seen = front.copy()
+    k = 0
+    while front.any():
+        k += 1
+        nxt = (A[:, front].any(axis=1)) & ~seen
+        lv[nxt] = k
+        seen |= nxt
+        front = nxt
+    return lv
+
+
+def test_bfs_brute_force_and_sssp_equals_bfs():
+    for s, g in enumerate(TINY):
+        if g.n == 0:
+            continue
+        src = int(gg.rng(s).integers(0, g.n))
+        lv = orc.bfs(g, src)
+        assert np.array_equal(lv, bfs_dense(g, src))
+        assert np.array_equal(orc.sssp_unit(g, src), lv)
+
+
+def test_bfs_closed_forms():
+    n = 57
+    assert np.array_equal(orc.bfs(gg.path(n), 13), np.abs(np.arange(n) - 13).astype(np.uint32))
+    st = gg.star(20)
+    assert np.array_equal(orc.bfs(st, 0), np.r_[0, np.ones(19)].astype(np.uint32))
+    lv = orc.bfs(st, 5)
+    assert lv[5] == 0 and lv[0] == 1 and np.all(np.delete(lv, [0, 5]) == 2)
+    R, C = 13, 17
+    r, c = np.divmod(np.arange(R * C), C)
+    s = 4 * C + 9
+    assert np.array_equal(orc.bfs(gg.grid4(R, C), s), (np.abs(r - 4) + np.abs(c - 9)).astype(np.uint32))
+    assert np.array_equal(orc.bfs(gg.king_grid(R, C), s),
+                          np.maximum(np.abs(r - 4), np.abs(c - 9)).astype(np.uint32))
+    assert np.array_equal(orc.sssp_unit(gg.king_grid(R, C), s),
+                          np.maximum(np.abs(r - 4), np.abs(c - 9)).astype(np.uint32))
+    K = orc.bfs(gg.complete(9), 3)
+    assert K[3] == 0 and np.all(np.delete(K, 3) == 1)
+    u = gg.disjoint_union(gg.path(5), gg.path(4))
+    assert np.all(orc.bfs(u, 0)[5:] == UNR)
+
+
+def test_bfs_scipy_medium():
+    g = gg.er_gnm(4096, 16384, seed=1)
+    d = csg.shortest_path(g.to_scipy(), unweighted=True, indices=[0, 77])
+    for k, src in enumerate((0, 77)):
+        ref = np.where(np.isinf(d[k]), UNR, d[k]).astype(np.uint32)
+        assert np.array_equal(orc.bfs(g, src), ref)
+    multi = orc.bfs_multi(g, np.array([0, 77], dtype=np.uint32))
+    assert np.array_equal(multi[1], orc.bfs(g, 77))
+
+
+def cc_dense(g):
+    A = g.dense().astype(bool) | np.eye(g.n, dtype=bool)
+    R = A.copy()
+    while True:
+        R2 = (R.astype(np.int64) @ R.astype(np.int64)) > 0
+        if np.array_equal(R2, R):
+            break
+        R = R2
+    return np.array([np.flatnonzero(R[i]).min() for i in range(g.n)], dtype=np.uint32)
+
+
+def test_cc_brute_force_and_unions():
+    for g in TINY:
+        assert np.array_equal(orc.cc(g), cc_dense(g))
+    u = gg.disjoint_union(gg.path(5), gg.complete(4), gg.star(3), gg.cycle(6))
+    lab = orc.cc(u)
+    assert np.array_equal(lab, np.r_[[0] * 5, [5] * 4, [9] * 3, [12] * 6].astype(np.uint32))
+
+
+def test_cc_scipy_medium():
+    g = gg.rmat(12, 4, seed=3)
+    ncomp, lab = csg.connected_components(g.to_scipy(), directed=False)
+    mins = np.full(ncomp, g.n, dtype=np.int64)
+    np.minimum.at(mins, lab, np.arange(g.n))
+    assert np.array_equal(orc.cc(g), mins[lab].astype(np.uint32))
+
+
+def pagerank_dense(g, d, iters):
+    A = g.dense().astype(np.float64)
+    deg = A.sum(axis=1)
+    inv = np.divide(1.0, deg, out=np.zeros_like(deg), where=deg > 0)
+    r = np.full(g.n, 1.0 / g.n)
+    for _ in range(iters):
+        r = (1 - d) / g.n + d * (A @ (r * inv))
+    return r
+
+
+def test_pagerank_brute_force():
+    for g in TINY:
+        if g.n == 0:
+            continue
+        np.testing.assert_allclose(orc.pagerank(g, 0.85, 20), pagerank_dense(g, 0.85, 20),
+                                   rtol=1e-12, atol=1e-15)
+
+
+def test_pagerank_regular_graphs_stay_uniform():
+    for g in (gg.cycle(100), gg.complete(31), gg.torus(8, 12)):
+        for k in (1, 7, 20):
+            np.testing.assert_allclose(orc.pagerank(g, 0.85, k), 1.0 / g.n, rtol=1e-13)
+
+
+def test_pagerank_mass_invariant_with_dangling():
+    g = gg.disjoint_union(gg.rmat(10, 4, seed=2), gg.path(1), gg.path(1))
+    deg = g.degrees()
+    d = 0.85
+    for k in (1, 2, 5):
+        r_prev = orc.pagerank(g, d, k - 1)
+        r = orc.pagerank(g, d, k)
+        np.testing.assert_allclose(r.sum(), (1 - d) + d * r_prev[deg > 0].sum(), rtol=1e-13)
+
+
+def test_thread_count_independence():
+    g = gg.rmat(13, 8, seed=4)
+    t0 = orc.num_threads()
+    try:
+        orc.set_num_threads(1)
+        a = (orc.pagerank(g, 0.85, 5), orc.tc(g), orc.spmv_count(g, np.ones(g.n, bool)))
+        orc.set_num_threads(max(2, t0))
+        b = (orc.pagerank(g, 0.85, 5), orc.tc(g), orc.spmv_count(g, np.ones(g.n, bool)))
+    finally:
+        orc.set_num_threads(t0)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1] and np.array_equal(a[2], b[2])
+
+
+# ---------------------------------------------------------------- planted mistakes fail the pins
+
+def test_pins_catch_planted_mistakes():
+    """Each pin above is sensitive: a plausibly wrong variant of the definition,
+    planted here on the CPU, disagrees with it."""
+    g = gg.complete(10)
+    # dropping the self term in min-plus changes SSSP fixpoints on a path
+    p = gg.path(6)
+    x = np.array([0, np.inf, np.inf, np.inf, np.inf, np.inf])
+    assert not np.array_equal(orc.spmv_min_plus(p, x, 1.0, False), orc.spmv_min_plus(p, x, 1.0, True))
+    # counting nonzero output entries instead of summing products breaks K_n
+    A = g.dense().astype(np.int64)
+    L = np.tril(A, -1)
+    boolean_count = int(((L @ L.T) > 0).astype(np.int64)[L > 0].sum())
+    assert boolean_count != math.comb(10, 3) == orc.tc(g)
+    # passing B instead of its transpose changes a non-symmetric product
+    r = gg.rng(5)
+    A = (r.random((30, 30)) < 0.3).astype(np.int64)
+    B = (r.random((30, 30)) < 0.3).astype(np.int64)
+    M = (r.random((30, 30)) < 0.5).astype(np.int64)
+    right = orc.masked_sum(directed_csr(A), directed_csr(B.T), directed_csr(M))
+    wrong = orc.masked_sum(directed_csr(A), directed_csr(B), directed_csr(M))
+    assert right == int(((A @ B) * M).sum()) != wrong
