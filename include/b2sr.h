@@ -1,0 +1,267 @@
+/*
+ * b2sr.h - C ABI of libb2sr.so: the Bit-Block Compressed Sparse Row (B2SR)
+ * format and the bit-level GraphBLAS kernels on it, for AMD Instinct MI355X
+ * (gfx950, wave64).
+ *
+ * The operations follow Bit-GraphBLAS (Chen, Sung, Shen, Tallent, Barker, Li;
+ * IPDPS 2022, arXiv 2201.08560):
+ *   - the format:                Sec. III-A (tile indexing), Sec. III-B and
+ *                                Table II (bit packing);
+ *   - matrix-vector schemes:     Sec. IV, Table III (bmv_bin_bin_bin,
+ *                                bmv_bin_bin_full, bmv_bin_full_full and their
+ *                                masked forms);
+ *   - matrix-matrix schemes:     Sec. IV, Table IV (bmm_bin_bin_sum[_masked]);
+ *   - semirings and algorithms:  Sec. V, Table V (Boolean, arithmetic and
+ *                                tropical min-plus; BFS, SSSP, PR, CC, TC).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is a DEVICE pointer to memory the caller
+ *   allocated and owns (unless documented as a host pointer).  The library
+ *   never allocates or frees caller-visible memory.  Scratch memory, where a
+ *   call needs any, is a caller-supplied workspace whose size is returned by a
+ *   *_workspace_bytes query; the workspace's contents on entry do not matter.
+ * Streams.  Every call enqueues its kernels on `stream` (0 = the null stream)
+ *   and returns without synchronising, except where documented (tile counting
+ *   and the iterative algorithm drivers, which read a device flag back).
+ * Errors.  Calls return B2SR_OK (0) or a negative status; arguments are
+ *   validated on the host before any work is enqueued, so an error return
+ *   means nothing was launched (B2SR_EHIP excepted).  No exception crosses
+ *   the ABI.  b2sr_strerror() names a status; b2sr_last_hip_error() gives the
+ *   text of the last HIP failure seen by the calling thread.
+ * Threads.  There is no global mutable state besides that per-thread error
+ *   text: calls on different streams may run concurrently.
+ *
+ * Matrix layout (the B2SR format)
+ * -------------------------------
+ * An n x n binary matrix A is cut into T x T tiles, T in {4, 8, 16, 32};
+ * nTR = ceil(n / T) tile-rows.  Only non-empty tiles are stored:
+ *   tile_rowptr[nTR + 1]  exclusive prefix count of non-empty tiles per
+ *                         tile-row (tile_rowptr[0] = 0; tiles of tile-row I
+ *                         are [tile_rowptr[I], tile_rowptr[I+1]) );
+ *   tile_colind[ntiles]   tile-column index of each tile, strictly ascending
+ *                         within a tile-row;
+ *   bits[ntiles * T]      T bit-rows per tile, in tile order.  Bit-row r of
+ *                         tile t is the word bits[t*T + r]; its bit c (least
+ *                         significant bit first) is A[I*T + r][J*T + c].
+ *                         Word type (Table II): uint8_t for T = 4 (low nibble
+ *                         used) and T = 8, uint16_t for T = 16, uint32_t for
+ *                         T = 32.  Bits for rows or columns >= n are zero.
+ * Indices are 32-bit: n, nnz and ntiles must be < 2^32.
+ *
+ * Vector layout
+ * -------------
+ * A bit vector over n entries is ceil(n / 32) uint32_t words; entry v is bit
+ * (v % 32) of word v / 32.  On input the bits >= n must be zero; on output they
+ * are written zero.  The same layout serves every T: the T-bit segment of
+ * tile-column J is bits [J*T, J*T + T).
+ * A full vector is n elements of the semiring's value type.
+ */
+#ifndef B2SR_H
+#define B2SR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define B2SR_OK 0
+#define B2SR_EINVAL (-1)  /* bad argument: tile size, NULL pointer, flags   */
+#define B2SR_ERANGE (-2)  /* a size does not fit the 32-bit index space     */
+#define B2SR_ENOSPC (-3)  /* workspace smaller than the query returned      */
+#define B2SR_EHIP (-4)    /* a HIP runtime call failed                      */
+#define B2SR_ENOTSUP (-5) /* unsupported semiring or combination            */
+
+/* ---- flags ---------------------------------------------------------------- */
+/* Build: keep only the strictly lower triangle (j < i) of the CSR input.  This
+ * forms L for triangle counting (Sec. V, TC). */
+#define B2SR_BUILD_LOWER 0x1u
+
+/* Products. */
+#define B2SR_MASK_COMPLEMENT 0x1u /* keep rows whose mask bit is 0 (BFS: not visited)    */
+#define B2SR_OUT_COUNT 0x2u       /* spmv_bin_bin: y is uint32_t[n] counts (bin_bin_full)  */
+#define B2SR_ACCUMULATE 0x4u      /* combine with the existing y (or *d_sum) instead of     */
+                                  /* overwriting it                                          */
+#define B2SR_SELF 0x8u            /* min-plus: the diagonal is a real zero (Sec. V, SSSP)   */
+
+/* Semirings for spmv_bin_full (Table V). */
+#define B2SR_PLUS_TIMES_F32 1 /* arithmetic, float x / y                           */
+#define B2SR_MIN_PLUS_F32 2   /* tropical min-plus, float x / y, +inf = unreachable */
+#define B2SR_MIN_PLUS_U32 3   /* tropical min-plus, uint32_t x / y, 0xFFFFFFFF = inf,
+                                 saturating addition                                */
+#define B2SR_OR_U64 4         /* Boolean on 64 vectors at once: uint64_t x / y,
+                                 y_i = OR_{A_ij = 1} x_j (multi-source BFS frontier) */
+
+/* A non-owning view of a B2SR matrix in device memory (layout above). */
+typedef struct b2sr_matrix {
+    uint32_t n;      /* rows = columns                         */
+    uint32_t tile;   /* T: 4, 8, 16 or 32                      */
+    uint32_t ntiles; /* number of non-empty tiles              */
+    uint32_t reserved; /* must be 0                            */
+    const uint32_t *tile_rowptr; /* device, nTR + 1 entries    */
+    const uint32_t *tile_colind; /* device, ntiles entries     */
+    const void *bits;            /* device, ntiles * T words   */
+} b2sr_matrix;
+
+/* ---- errors ------------------------------------------------------------- */
+const char *b2sr_strerror(int status);
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char *b2sr_last_hip_error(void);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int b2sr_version(void);
+
+/* ---- format construction (Sec. III-A, III-B; Table II) -------------------
+ * Conversion from CSR takes two calls, because the caller allocates the output
+ * arrays once the tile count is known.
+ *
+ * b2sr_count_tiles: counts the non-empty T x T tiles of the CSR matrix
+ *   (rowptr[n + 1], colind[nnz], device, uint32) and writes tile_rowptr
+ *   (device, ceil(n/T) + 1 entries).  The total tile count is written to the
+ *   HOST pointer *ntiles; the call synchronises `stream` to read it.
+ *   Columns inside a row may be unsorted and may repeat.  Every column index
+ *   must be < n (not checked on the device).
+ *   flags: 0 or B2SR_BUILD_LOWER.
+ *   Errors: EINVAL (tile not in {4,8,16,32}, NULL pointer with n > 0, unknown
+ *   flag), ERANGE (nnz >= 2^32), EHIP.
+ */
+int b2sr_count_tiles(uint32_t n, uint64_t nnz, const uint32_t *rowptr, const uint32_t *colind,
+                     uint32_t tile, unsigned flags, uint32_t *tile_rowptr, uint64_t *ntiles,
+                     hipStream_t stream);
+
+/*
+ * b2sr_from_csr: fills tile_colind[ntiles] and bits[ntiles * T words] (device,
+ *   caller-allocated) from the same CSR arrays, tile size and flags as the
+ *   preceding b2sr_count_tiles, given its tile_rowptr and tile count.  Bits of
+ *   repeated CSR entries are set once.  Does not synchronise.
+ *   Errors: EINVAL, ERANGE, EHIP.
+ */
+int b2sr_from_csr(uint32_t n, uint64_t nnz, const uint32_t *rowptr, const uint32_t *colind,
+                  uint32_t tile, unsigned flags, const uint32_t *tile_rowptr, uint64_t ntiles,
+                  uint32_t *tile_colind, void *bits, hipStream_t stream);
+
+/*
+ * b2sr_pack_bits: vector binarisation (Sec. IV, Listing 1's packed operand):
+ *   bits[ceil(n/32)] (device) receives bit v = (pred[v] != 0) for v < n, zero
+ *   padding above n.  pred is n bytes (device).
+ */
+int b2sr_pack_bits(uint32_t n, const uint8_t *pred, uint32_t *bits, hipStream_t stream);
+
+/* ---- matrix-vector products (Sec. IV, Table III) ------------------------
+ * spmv_bin_bin: 1-bit matrix times 1-bit vector x (bit layout, ceil(n/32)
+ *   words).
+ *   Default (bmv_bin_bin_bin, Boolean semiring): y is a bit vector with
+ *     y_i = OR_{j : A_ij = 1} x_j.
+ *   B2SR_OUT_COUNT (bmv_bin_bin_full, Listing 1): y is uint32_t[n] with
+ *     y_i = sum_J popcount(A's bit-row i in tile-column J AND x's segment J)
+ *         = |{ j : A_ij = 1 and x_j = 1 }|.
+ *   mask (nullable bit vector; the *_masked schemes of Table III, Sec. V BFS):
+ *     row i is kept if its mask bit is 1, or 0 under B2SR_MASK_COMPLEMENT;
+ *     the mask is applied to the result just before it is stored.  A dropped
+ *     row gets the identity (0), or keeps its old value under ACCUMULATE.
+ *   B2SR_ACCUMULATE: y |= result (bits) or y += result (counts).
+ *   Otherwise y is overwritten.  y must not alias x or mask.
+ *   Errors: EINVAL, EHIP.
+ */
+int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, unsigned flags,
+                 void *y, hipStream_t stream);
+
+/*
+ * spmv_bin_full (bmv_bin_full_full[_masked]): 1-bit matrix times a full
+ *   vector x (n elements) under `semiring`:
+ *   B2SR_PLUS_TIMES_F32: t_i = sum_{j : A_ij = 1} x_j * s_j, with s =
+ *       col_scale (nullable: s = 1; PageRank's 1/out-degree vector, Sec. V);
+ *       y_i = alpha * t_i + beta.
+ *   B2SR_MIN_PLUS_F32 / _U32: t_i = min_{j : A_ij = 1} (x_j + alpha), the
+ *       empty minimum being infinity; with B2SR_SELF also min'ed with x_i
+ *       (the diagonal as a real zero, Sec. V SSSP); y_i = t_i.  For _U32,
+ *       alpha must be a non-negative integer and additions saturate.
+ *   B2SR_OR_U64: y_i = OR_{j : A_ij = 1} x_j over uint64_t words.
+ *   mask / B2SR_MASK_COMPLEMENT: as for spmv_bin_bin; a dropped row gets 0
+ *   (plus-times, or-u64) or infinity (min-plus), or keeps its old value under
+ *   ACCUMULATE.  B2SR_ACCUMULATE: y_i = y_i + alpha t_i + beta (plus-times),
+ *   min(y_i, t_i) (min-plus), y_i | t_i (or-u64).
+ *   Floating-point sums are deterministic: a fixed reduction order that does
+ *   not depend on scheduling (rows split across work chunks are combined in
+ *   chunk order by a second kernel).
+ *   ws/ws_bytes: workspace of at least spmv_bin_full_workspace_bytes(A,
+ *   semiring) bytes (may be NULL when that is 0).  y must not alias x.
+ *   Errors: EINVAL, ENOSPC, ENOTSUP (unknown semiring), EHIP.
+ */
+size_t spmv_bin_full_workspace_bytes(const b2sr_matrix *A, int semiring);
+int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float *col_scale,
+                  const uint32_t *mask, unsigned flags, double alpha, double beta, void *y,
+                  void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- masked matrix-matrix product, summed (Sec. IV, Table IV, Listing 2) ---
+ * spgemm_masked: *d_sum (device uint64_t) receives
+ *     s = sum_{(i,j) : M_ij = 1} (A * B)_ij,   (A * B)_ij = sum_k A_ik B_kj,
+ *   an arithmetic sum of products (not a count of nonzero outputs).  B is
+ *   passed as its transpose Bt (row j of Bt holds column j of B), so that
+ *   (A * B)_ij is a dot product of bit-rows of A and Bt.  M == NULL means the
+ *   unmasked bmm_bin_bin_sum (every (i, j)).  A, Bt and M must have the same
+ *   n and T and may alias.  Triangle counting (Sec. V) is A = Bt = M = L, the
+ *   strictly lower triangle.
+ *   B2SR_ACCUMULATE adds to *d_sum instead of overwriting it.
+ *   ws: spgemm_masked_workspace_bytes(A, M) bytes (0 when M != NULL).
+ *   Errors: EINVAL, ENOSPC, EHIP.
+ */
+size_t spgemm_masked_workspace_bytes(const b2sr_matrix *A, const b2sr_matrix *M);
+int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix *M,
+                  unsigned flags, uint64_t *d_sum, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- graph algorithms on the products above (Sec. V) ---------------------
+ * Each driver runs its iteration loop on the host, launching the kernels
+ * above on `stream`, and reads one device flag per iteration to test
+ * convergence (so it synchronises `stream`).  The number of iterations run is
+ * written to the HOST pointer *iters when it is not NULL.  ws is a workspace
+ * of b2sr_algo_workspace_bytes(A, algo) bytes.  A must be symmetric (an
+ * undirected graph), which makes vxm and mxv the same product.
+ */
+#define B2SR_ALGO_BFS 1
+#define B2SR_ALGO_SSSP 2
+#define B2SR_ALGO_CC 3
+#define B2SR_ALGO_PAGERANK 4
+#define B2SR_ALGO_MSBFS 5
+size_t b2sr_algo_workspace_bytes(const b2sr_matrix *A, int algo);
+
+/* BFS (Sec. V): Boolean semiring, masked bin_bin_bin product per level with
+ * the complement of the visited set as the mask.  levels (uint32_t[n]):
+ * levels[src] = 0, unreachable = 0xFFFFFFFF. */
+int b2sr_bfs(const b2sr_matrix *A, uint32_t src, uint32_t *levels, void *ws, size_t ws_bytes,
+             uint32_t *iters, hipStream_t stream);
+
+/* Multi-source BFS: up to 64 sources at once as one uint64_t frontier word
+ * per vertex (bit s = source s), each level one B2SR_OR_U64 product masked by
+ * the visited words.  levels is nsrc x n uint32_t, row s for source srcs[s]
+ * (srcs is a HOST array; sources must be distinct and < n). */
+int b2sr_msbfs(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32_t *levels,
+               void *ws, size_t ws_bytes, uint32_t *iters, hipStream_t stream);
+
+/* SSSP with unit edge weights (Sec. V): tropical min-plus over float with the
+ * diagonal as zero, iterated to a fixpoint.  dist (uint32_t[n]) holds hop
+ * distances, unreachable = 0xFFFFFFFF. */
+int b2sr_sssp(const b2sr_matrix *A, uint32_t src, uint32_t *dist, void *ws, size_t ws_bytes,
+              uint32_t *iters, hipStream_t stream);
+
+/* Connected components (Sec. V): min-label propagation, x = min(x, A x) under
+ * min-plus over uint32 with zero edge weight, from x_i = i to a fixpoint.
+ * labels (uint32_t[n]) ends as the smallest vertex id of each component. */
+int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, uint32_t *iters,
+            hipStream_t stream);
+
+/* PageRank (Sec. V): r_0 = 1/n, then `iterations` steps of
+ * r_i = (1 - d)/n + d * sum_{j : A_ij = 1} r_j / deg_j in float, degree-0
+ * vertices contributing nothing.  rank is float[n]. */
+int b2sr_pagerank(const b2sr_matrix *A, float damping, uint32_t iterations, float *rank, void *ws,
+                  size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* B2SR_H */

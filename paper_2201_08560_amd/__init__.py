@@ -1,0 +1,328 @@
+"""Python binding of libb2sr.so: B2SR bit-tiled graphs and bit-level GraphBLAS
+kernels on AMD Instinct MI355X (gfx950).
+
+This module only marshals arguments: every step runs in the HIP kernels of
+``libb2sr.so`` (declared in ``include/b2sr.h``).  PyTorch provides device
+memory and the current stream.  The functions carry the C ABI's names.
+
+Integer vectors cross the boundary as int32/int64 tensors whose bits are the
+ABI's uint32/uint64 values (``as_u32``/``as_u64`` reinterpret them on the host).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+__all__ = [
+    "B2SRError", "B2SR", "lib", "b2sr_count_tiles", "b2sr_from_csr", "b2sr_pack_bits", "spmv_bin_bin",
+    "spmv_bin_full", "spmv_bin_full_workspace_bytes", "spgemm_masked", "spgemm_masked_workspace_bytes",
+    "b2sr_algo_workspace_bytes", "b2sr_bfs", "b2sr_msbfs", "b2sr_sssp", "b2sr_cc", "b2sr_pagerank",
+    "triangle_count", "b2sr_strerror", "as_u32", "as_u64", "header_functions", "FLAGS", "SEMIRINGS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libb2sr.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "b2sr.h")
+
+# flags and semirings (values from include/b2sr.h)
+BUILD_LOWER = 0x1
+MASK_COMPLEMENT = 0x1
+OUT_COUNT = 0x2
+ACCUMULATE = 0x4
+SELF = 0x8
+PLUS_TIMES_F32, MIN_PLUS_F32, MIN_PLUS_U32, OR_U64 = 1, 2, 3, 4
+ALGO_BFS, ALGO_SSSP, ALGO_CC, ALGO_PAGERANK, ALGO_MSBFS = 1, 2, 3, 4, 5
+FLAGS = {"BUILD_LOWER": BUILD_LOWER, "MASK_COMPLEMENT": MASK_COMPLEMENT, "OUT_COUNT": OUT_COUNT,
+         "ACCUMULATE": ACCUMULATE, "SELF": SELF}
+SEMIRINGS = {"plus_times_f32": PLUS_TIMES_F32, "min_plus_f32": MIN_PLUS_F32, "min_plus_u32": MIN_PLUS_U32,
+             "or_u64": OR_U64}
+UNREACHED = 0xFFFFFFFF
+
+
+class B2SRError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        text = _lib.b2sr_strerror(status).decode() if _lib is not None else str(status)
+        extra = _lib.b2sr_last_hip_error().decode() if (_lib is not None and status == -4) else ""
+        super().__init__(f"{where}: {text} ({status}){': ' + extra if extra else ''}")
+        self.status = status
+
+
+class b2sr_matrix(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("ntiles", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("tile_rowptr", ctypes.c_void_p),
+                ("tile_colind", ctypes.c_void_p), ("bits", ctypes.c_void_p)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_MP = ctypes.POINTER(b2sr_matrix)
+_U32, _U64, _I, _D, _SZ = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+
+_SIGS = {
+    "b2sr_strerror": (ctypes.c_char_p, [_I]),
+    "b2sr_last_hip_error": (ctypes.c_char_p, []),
+    "b2sr_version": (_I, []),
+    "b2sr_count_tiles": (_I, [_U32, _U64, _P, _P, _U32, ctypes.c_uint, _P, ctypes.POINTER(_U64), _P]),
+    "b2sr_from_csr": (_I, [_U32, _U64, _P, _P, _U32, ctypes.c_uint, _P, _U64, _P, _P, _P]),
+    "b2sr_pack_bits": (_I, [_U32, _P, _P, _P]),
+    "spmv_bin_bin": (_I, [_MP, _P, _P, ctypes.c_uint, _P, _P]),
+    "spmv_bin_full_workspace_bytes": (_SZ, [_MP, _I]),
+    "spmv_bin_full": (_I, [_MP, _I, _P, _P, _P, ctypes.c_uint, _D, _D, _P, _P, _SZ, _P]),
+    "spgemm_masked_workspace_bytes": (_SZ, [_MP, _MP]),
+    "spgemm_masked": (_I, [_MP, _MP, _MP, ctypes.c_uint, _P, _P, _SZ, _P]),
+    "b2sr_algo_workspace_bytes": (_SZ, [_MP, _I]),
+    "b2sr_bfs": (_I, [_MP, _U32, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
+    "b2sr_msbfs": (_I, [_MP, ctypes.POINTER(_U32), _U32, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
+    "b2sr_sssp": (_I, [_MP, _U32, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
+    "b2sr_cc": (_I, [_MP, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
+    "b2sr_pagerank": (_I, [_MP, ctypes.c_float, _U32, _P, _P, _SZ, _P]),
+}
+
+
+def lib():
+    """Loads libb2sr.so; raises when it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(or python paper_2201_08560_amd/build_lib.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of every function declared in include/b2sr.h."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z][a-z0-9_]*)\s*\(", text)) - {"defined", "sizeof"})
+
+
+def b2sr_strerror(status: int) -> str:
+    return lib().b2sr_strerror(status).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise B2SRError(rc, where)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def as_u32(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def as_u64(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def _i32(a, device="cuda"):
+    """uint32 data (numpy or tensor) as an int32 device tensor with the same bits."""
+    if isinstance(a, torch.Tensor):
+        return a.to(device)
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to(device)
+
+
+def _words(n: int) -> int:
+    return (n + 31) // 32
+
+
+_ROW_BYTES = {4: 1, 8: 1, 16: 2, 32: 4}
+
+
+class B2SR:
+    """A device-resident B2SR matrix; owns the three arrays as torch tensors."""
+
+    def __init__(self, n: int, tile: int, tile_rowptr, tile_colind, bits, ntiles: int):
+        self.n, self.tile, self.ntiles = int(n), int(tile), int(ntiles)
+        self.tile_rowptr, self.tile_colind, self.bits = tile_rowptr, tile_colind, bits
+        self._view = b2sr_matrix(self.n, self.tile, self.ntiles, 0, tile_rowptr.data_ptr(),
+                                 tile_colind.data_ptr(), bits.data_ptr())
+
+    @property
+    def view(self):
+        return ctypes.byref(self._view)
+
+    @property
+    def ntile_rows(self) -> int:
+        return (self.n + self.tile - 1) // self.tile
+
+    @property
+    def nbytes(self) -> int:
+        """Storage of the three arrays with 4-byte indices (Sec. III)."""
+        return 4 * (self.ntile_rows + 1) + 4 * self.ntiles + self.ntiles * self.tile * _ROW_BYTES[self.tile]
+
+    @classmethod
+    def from_csr(cls, rowptr, colind, n: int, tile: int, lower: bool = False):
+        """Builds B2SR on the device from CSR (uint32 numpy arrays or int32 device tensors)."""
+        rp, ci = _i32(rowptr), _i32(colind)
+        nnz = int(ci.numel())
+        flags = BUILD_LOWER if lower else 0
+        trp = torch.empty((n + tile - 1) // tile + 1, dtype=torch.int32, device="cuda")
+        nt = b2sr_count_tiles(n, nnz, rp, ci, tile, flags, trp)
+        tci = torch.empty(max(nt, 1), dtype=torch.int32, device="cuda")
+        bits = torch.empty(max(nt * tile * _ROW_BYTES[tile], 16), dtype=torch.uint8, device="cuda")
+        b2sr_from_csr(n, nnz, rp, ci, tile, flags, trp, nt, tci, bits)
+        return cls(n, tile, trp, tci, bits, nt)
+
+    @classmethod
+    def from_graph(cls, g, tile: int, lower: bool = False):
+        return cls.from_csr(g.rowptr, g.colind, g.n, tile, lower)
+
+    def to_host(self):
+        """(tile_rowptr u32, tile_colind u32, bits as u8/u8/u16/u32 words)."""
+        trp = as_u32(self.tile_rowptr)
+        tci = as_u32(self.tile_colind)[: self.ntiles]
+        raw = self.bits.cpu().numpy()[: self.ntiles * self.tile * _ROW_BYTES[self.tile]]
+        dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[_ROW_BYTES[self.tile]]
+        return trp, tci, raw.view(dt)
+
+
+# ---- format ------------------------------------------------------------------
+
+def b2sr_count_tiles(n, nnz, rowptr, colind, tile, flags, tile_rowptr) -> int:
+    out = _U64(0)
+    _check(lib().b2sr_count_tiles(n, nnz, _ptr(rowptr), _ptr(colind), tile, flags, _ptr(tile_rowptr),
+                                  ctypes.byref(out), _stream()), "b2sr_count_tiles")
+    return int(out.value)
+
+
+def b2sr_from_csr(n, nnz, rowptr, colind, tile, flags, tile_rowptr, ntiles, tile_colind, bits):
+    _check(lib().b2sr_from_csr(n, nnz, _ptr(rowptr), _ptr(colind), tile, flags, _ptr(tile_rowptr), ntiles,
+                               _ptr(tile_colind), _ptr(bits), _stream()), "b2sr_from_csr")
+
+
+def b2sr_pack_bits(pred: torch.Tensor, out=None) -> torch.Tensor:
+    """Bool/uint8 device vector -> bit vector (int32 words)."""
+    n = pred.numel()
+    p = pred.to(torch.uint8).contiguous()
+    out = torch.empty(max(_words(n), 1), dtype=torch.int32, device="cuda") if out is None else out
+    _check(lib().b2sr_pack_bits(n, _ptr(p), _ptr(out), _stream()), "b2sr_pack_bits")
+    return out
+
+
+# ---- products -------------------------------------------------------------------
+
+def spmv_bin_bin(A: B2SR, x, mask=None, complement=False, count=False, accumulate=False, out=None):
+    flags = (MASK_COMPLEMENT if complement else 0) | (OUT_COUNT if count else 0) | (ACCUMULATE if accumulate else 0)
+    if out is None:
+        out = torch.empty(A.n if count else max(_words(A.n), 1), dtype=torch.int32, device="cuda")
+    _check(lib().spmv_bin_bin(A.view, _ptr(x), _ptr(mask), flags, _ptr(out), _stream()), "spmv_bin_bin")
+    return out
+
+
+def spmv_bin_full_workspace_bytes(A: B2SR, semiring: int) -> int:
+    return int(lib().spmv_bin_full_workspace_bytes(A.view, semiring))
+
+
+_FULL_DTYPE = {PLUS_TIMES_F32: torch.float32, MIN_PLUS_F32: torch.float32, MIN_PLUS_U32: torch.int32,
+               OR_U64: torch.int64}
+
+
+def spmv_bin_full(A: B2SR, semiring: int, x, col_scale=None, mask=None, complement=False, self_loop=False,
+                  accumulate=False, alpha=1.0, beta=0.0, out=None, ws=None):
+    flags = (MASK_COMPLEMENT if complement else 0) | (SELF if self_loop else 0) | (ACCUMULATE if accumulate else 0)
+    if out is None:
+        out = torch.empty(A.n, dtype=_FULL_DTYPE[semiring], device="cuda")
+    need = spmv_bin_full_workspace_bytes(A, semiring)
+    if ws is None and need:
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    _check(lib().spmv_bin_full(A.view, semiring, _ptr(x), _ptr(col_scale), _ptr(mask), flags, float(alpha),
+                               float(beta), _ptr(out), _ptr(ws), need if ws is not None else 0, _stream()),
+           "spmv_bin_full")
+    return out
+
+
+def spgemm_masked_workspace_bytes(A: B2SR, M: B2SR | None) -> int:
+    return int(lib().spgemm_masked_workspace_bytes(A.view, None if M is None else M.view))
+
+
+def spgemm_masked(A: B2SR, Bt: B2SR, M: B2SR | None = None, accumulate=False, out=None, ws=None):
+    """Device int64 scalar (uint64 bits) = sum over M's ones of (A B)_ij, B = Bt^T."""
+    out = torch.zeros(1, dtype=torch.int64, device="cuda") if out is None else out
+    need = spgemm_masked_workspace_bytes(A, M)
+    if ws is None and need:
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    _check(lib().spgemm_masked(A.view, Bt.view, None if M is None else M.view, ACCUMULATE if accumulate else 0,
+                               _ptr(out), _ptr(ws), need, _stream()), "spgemm_masked")
+    return out
+
+
+# ---- algorithms -------------------------------------------------------------
+
+def b2sr_algo_workspace_bytes(A: B2SR, algo: int) -> int:
+    return int(lib().b2sr_algo_workspace_bytes(A.view, algo))
+
+
+def _ws(A, algo, ws):
+    need = b2sr_algo_workspace_bytes(A, algo)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    return ws, need
+
+
+def b2sr_bfs(A: B2SR, src: int, out=None, ws=None):
+    """Returns (levels int32 tensor with uint32 bits, levels run)."""
+    out = torch.empty(A.n, dtype=torch.int32, device="cuda") if out is None else out
+    ws, need = _ws(A, ALGO_BFS, ws)
+    it = _U32(0)
+    _check(lib().b2sr_bfs(A.view, src, _ptr(out), _ptr(ws), need, ctypes.byref(it), _stream()), "b2sr_bfs")
+    return out, it.value
+
+
+def b2sr_msbfs(A: B2SR, srcs, out=None, ws=None):
+    srcs = np.ascontiguousarray(srcs, dtype=np.uint32)
+    out = torch.empty((srcs.size, A.n), dtype=torch.int32, device="cuda") if out is None else out
+    ws, need = _ws(A, ALGO_MSBFS, ws)
+    it = _U32(0)
+    arr = (_U32 * srcs.size)(*srcs.tolist())
+    _check(lib().b2sr_msbfs(A.view, arr, srcs.size, _ptr(out), _ptr(ws), need, ctypes.byref(it), _stream()),
+           "b2sr_msbfs")
+    return out, it.value
+
+
+def b2sr_sssp(A: B2SR, src: int, out=None, ws=None):
+    out = torch.empty(A.n, dtype=torch.int32, device="cuda") if out is None else out
+    ws, need = _ws(A, ALGO_SSSP, ws)
+    it = _U32(0)
+    _check(lib().b2sr_sssp(A.view, src, _ptr(out), _ptr(ws), need, ctypes.byref(it), _stream()), "b2sr_sssp")
+    return out, it.value
+
+
+def b2sr_cc(A: B2SR, out=None, ws=None):
+    out = torch.empty(A.n, dtype=torch.int32, device="cuda") if out is None else out
+    ws, need = _ws(A, ALGO_CC, ws)
+    it = _U32(0)
+    _check(lib().b2sr_cc(A.view, _ptr(out), _ptr(ws), need, ctypes.byref(it), _stream()), "b2sr_cc")
+    return out, it.value
+
+
+def b2sr_pagerank(A: B2SR, damping=0.85, iterations=20, out=None, ws=None):
+    out = torch.empty(A.n, dtype=torch.float32, device="cuda") if out is None else out
+    ws, need = _ws(A, ALGO_PAGERANK, ws)
+    _check(lib().b2sr_pagerank(A.view, float(damping), int(iterations), _ptr(out), _ptr(ws), need, _stream()),
+           "b2sr_pagerank")
+    return out
+
+
+def triangle_count(rowptr, colind, n: int, tile: int) -> int:
+    """Triangles of an undirected graph (Sec. V): L = strict lower triangle in
+    B2SR, then the sum of (L L^T) masked by L."""
+    L = B2SR.from_csr(rowptr, colind, n, tile, lower=True)
+    s = spgemm_masked(L, L, L)
+    return int(as_u64(s)[0])

@@ -1,0 +1,419 @@
+// Graph algorithms on the B2SR products (Sec. V): BFS, multi-source BFS,
+// SSSP, connected components and PageRank.  Each driver runs its loop on the
+// host and launches the product kernels plus a small element-wise update
+// kernel per iteration; convergence is read back as one device word per
+// iteration (the flags alternate between two words so the update kernel can
+// clear the next one, which saves a launch).
+#include <utility>
+
+#include "common.h"
+
+using namespace b2sr_dev;
+
+namespace b2sr {
+int fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
+}
+
+namespace {
+
+constexpr uint32_t kUnreached = 0xFFFFFFFFu;
+
+// Carves aligned pieces out of a caller workspace (or just sizes them when
+// base is null).
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <class P> P *take(size_t bytes)
+    {
+        off = (off + 255) & ~(size_t)255;
+        P *p = base ? (P *)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+int read_flag(const uint32_t *d_flag, uint32_t *h, hipStream_t s)
+{
+    if (int rc = b2sr::check(hipMemcpyAsync(h, d_flag, sizeof *h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync(flag)"))
+        return rc;
+    return b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+// ---------------------------------------------------------------- BFS
+__global__ void bfs_init_kernel(uint32_t n, uint32_t src, uint32_t *levels, uint32_t *frontier, uint32_t *visited,
+                                uint32_t *flags)
+{
+    const uint32_t nw = (n + 31) / 32;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        levels[i] = i == src ? 0u : kUnreached;
+        if (i < nw) {
+            const uint32_t w = (i == src / 32) ? (1u << (src % 32)) : 0u;
+            frontier[i] = w;
+            visited[i] = w;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
+}
+
+// Newly reached vertices (next is already masked by NOT visited) get this
+// level and join the visited set.
+__global__ void bfs_update_kernel(uint32_t nw, const uint32_t *next, uint32_t *visited, uint32_t *levels,
+                                  uint32_t level, uint32_t *flag_now, uint32_t *flag_next)
+{
+    bool any = false;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t nb = next[w];
+        if (!nb) continue;
+        any = true;
+        visited[w] |= nb;
+        while (nb) {
+            const uint32_t b = __builtin_ctz(nb);
+            nb &= nb - 1;
+            levels[w * 32 + b] = level;
+        }
+    }
+    if (__any(any) && lane_id() == 0) atomicOr(flag_now, 1u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
+}
+
+// ---------------------------------------------------------------- multi-source BFS
+__global__ void msbfs_init_kernel(uint32_t n, uint32_t nsrc, const uint32_t *srcs, uint64_t *F, uint64_t *V,
+                                  uint32_t *levels, uint32_t *flags)
+{
+    const uint64_t total = (uint64_t)nsrc * n;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x)
+        levels[i] = kUnreached;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        F[i] = 0;
+        V[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
+}
+
+__global__ void msbfs_seed_kernel(uint32_t n, uint32_t nsrc, const uint32_t *srcs, uint64_t *F, uint64_t *V,
+                                  uint32_t *levels)
+{
+    // one thread seeds every source so repeated vertices (rejected on the host) cannot race
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (uint32_t s = 0; s < nsrc; ++s) {
+            F[srcs[s]] |= 1ull << s;
+            V[srcs[s]] |= 1ull << s;
+            levels[(size_t)s * n + srcs[s]] = 0;
+        }
+}
+
+__global__ void msbfs_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, uint64_t *V, uint32_t *levels,
+                                    uint32_t level, uint32_t *flag_now, uint32_t *flag_next)
+{
+    bool any = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t y = Y[i] & ~V[i];
+        F[i] = y;
+        if (!y) continue;
+        any = true;
+        V[i] |= y;
+        while (y) {
+            const uint32_t s = __builtin_ctzll(y);
+            y &= y - 1;
+            levels[(size_t)s * n + i] = level;
+        }
+    }
+    if (__any(any) && lane_id() == 0) atomicOr(flag_now, 1u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
+}
+
+// ---------------------------------------------------------------- SSSP / CC
+__global__ void sssp_init_kernel(uint32_t n, uint32_t src, float *d, uint32_t *flags)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        d[i] = i == src ? 0.0f : __builtin_huge_valf();
+    if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
+}
+
+template <class V>
+__global__ void changed_kernel(uint32_t n, const V *a, const V *b, uint32_t *flag_now, uint32_t *flag_next)
+{
+    bool diff = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        diff |= a[i] != b[i];
+    if (__any(diff) && lane_id() == 0) atomicOr(flag_now, 1u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
+}
+
+__global__ void dist_to_u32_kernel(uint32_t n, const float *d, uint32_t *out)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const float v = d[i];
+        out[i] = v == __builtin_huge_valf() ? kUnreached : (uint32_t)v;
+    }
+}
+
+__global__ void iota_kernel(uint32_t n, uint32_t *x, uint32_t *flags)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        x[i] = (uint32_t)i;
+    if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
+}
+
+__global__ void copy_u32_kernel(uint32_t n, const uint32_t *a, uint32_t *b)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+// ---------------------------------------------------------------- PageRank
+__global__ void ones_bits_kernel(uint32_t n, uint32_t *bits)
+{
+    const uint32_t nw = (n + 31) / 32;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t hi = (uint32_t)min<uint64_t>(32, n - w * 32);
+        bits[w] = hi == 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u);
+    }
+}
+
+__global__ void pr_init_kernel(uint32_t n, const uint32_t *deg, float *inv, float *r)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        inv[i] = deg[i] ? 1.0f / (float)deg[i] : 0.0f;
+        r[i] = 1.0f / (float)n;
+    }
+}
+
+__global__ void pr_scale_kernel(uint32_t n, const float *r, const float *inv, float *z)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        z[i] = r[i] * inv[i];
+}
+
+unsigned vgrid(uint64_t n) { return b2sr::grid_for(n, 256, 8192); }
+
+struct Layout {
+    // BFS
+    uint32_t *frontier = nullptr, *visited = nullptr, *next = nullptr;
+    // MSBFS
+    uint64_t *F = nullptr, *V = nullptr, *Y = nullptr;
+    uint32_t *srcs = nullptr;
+    // SSSP / CC / PR
+    float *f0 = nullptr, *f1 = nullptr, *f2 = nullptr;
+    uint32_t *u0 = nullptr, *ones = nullptr;
+    void *spmv_ws = nullptr;
+    size_t spmv_ws_bytes = 0;
+    uint32_t *flags = nullptr;
+    size_t bytes = 0;
+};
+
+Layout carve(const b2sr_matrix *A, int algo, void *ws)
+{
+    Carver c{(char *)ws};
+    Layout L;
+    const size_t n = A->n, nw = b2sr::n_words(A->n);
+    switch (algo) {
+    case B2SR_ALGO_BFS:
+        L.frontier = c.take<uint32_t>(nw * 4);
+        L.visited = c.take<uint32_t>(nw * 4);
+        L.next = c.take<uint32_t>(nw * 4);
+        break;
+    case B2SR_ALGO_MSBFS:
+        L.F = c.take<uint64_t>(n * 8);
+        L.V = c.take<uint64_t>(n * 8);
+        L.Y = c.take<uint64_t>(n * 8);
+        L.srcs = c.take<uint32_t>(64 * 4);
+        break;
+    case B2SR_ALGO_SSSP:
+        L.f0 = c.take<float>(n * 4);
+        L.f1 = c.take<float>(n * 4);
+        break;
+    case B2SR_ALGO_CC:
+        L.u0 = c.take<uint32_t>(n * 4);
+        break;
+    case B2SR_ALGO_PAGERANK:
+        L.f0 = c.take<float>(n * 4);  // z = r / deg
+        L.f1 = c.take<float>(n * 4);  // 1 / deg
+        L.f2 = c.take<float>(n * 4);  // second rank buffer
+        L.u0 = c.take<uint32_t>(n * 4);
+        L.ones = c.take<uint32_t>(nw * 4);
+        L.spmv_ws_bytes = spmv_bin_full_workspace_bytes(A, B2SR_PLUS_TIMES_F32);
+        L.spmv_ws = c.take<char>(L.spmv_ws_bytes);
+        break;
+    default: break;
+    }
+    L.flags = c.take<uint32_t>(2 * 4);
+    L.bytes = c.off;
+    return L;
+}
+
+int check_algo_args(const b2sr_matrix *A, int algo, void *ws, size_t ws_bytes, Layout *L)
+{
+    int rc = b2sr::validate_matrix(A);
+    if (rc) return rc;
+    if (!ws) return B2SR_ENOSPC;
+    *L = carve(A, algo, ws);
+    return ws_bytes < L->bytes ? B2SR_ENOSPC : B2SR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t b2sr_algo_workspace_bytes(const b2sr_matrix *A, int algo)
+{
+    if (!A || !b2sr::valid_tile(A->tile) || algo < B2SR_ALGO_BFS || algo > B2SR_ALGO_MSBFS) return 0;
+    return carve(A, algo, nullptr).bytes;
+}
+
+int b2sr_bfs(const b2sr_matrix *A, uint32_t src, uint32_t *levels, void *ws, size_t ws_bytes, uint32_t *iters,
+             hipStream_t stream)
+{
+    Layout L;
+    int rc = check_algo_args(A, B2SR_ALGO_BFS, ws, ws_bytes, &L);
+    if (rc) return rc;
+    if (!levels || src >= A->n) return B2SR_EINVAL;
+    const uint32_t n = A->n, nw = b2sr::n_words(n);
+    bfs_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, levels, L.frontier, L.visited, L.flags);
+    if ((rc = b2sr::check_launch("bfs_init_kernel"))) return rc;
+    uint32_t level = 0;
+    for (;;) {
+        ++level;
+        if ((rc = spmv_bin_bin(A, L.frontier, L.visited, B2SR_MASK_COMPLEMENT, L.next, stream))) return rc;
+        uint32_t *fnow = L.flags + (level & 1), *fnext = L.flags + ((level + 1) & 1);
+        bfs_update_kernel<<<vgrid(nw), 256, 0, stream>>>(nw, L.next, L.visited, levels, level, fnow, fnext);
+        if ((rc = b2sr::check_launch("bfs_update_kernel"))) return rc;
+        uint32_t any = 0;
+        if ((rc = read_flag(fnow, &any, stream))) return rc;
+        if (!any) break;
+        std::swap(L.frontier, L.next);
+    }
+    if (iters) *iters = level;
+    return B2SR_OK;
+}
+
+int b2sr_msbfs(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32_t *levels, void *ws,
+               size_t ws_bytes, uint32_t *iters, hipStream_t stream)
+{
+    Layout L;
+    int rc = check_algo_args(A, B2SR_ALGO_MSBFS, ws, ws_bytes, &L);
+    if (rc) return rc;
+    if (!levels || !srcs || nsrc == 0 || nsrc > 64) return B2SR_EINVAL;
+    for (uint32_t s = 0; s < nsrc; ++s) {
+        if (srcs[s] >= A->n) return B2SR_EINVAL;
+        for (uint32_t q = 0; q < s; ++q)
+            if (srcs[q] == srcs[s]) return B2SR_EINVAL;
+    }
+    const uint32_t n = A->n;
+    if ((rc = b2sr::check(hipMemcpyAsync(L.srcs, srcs, nsrc * 4, hipMemcpyHostToDevice, stream), "hipMemcpyAsync(srcs)")))
+        return rc;
+    msbfs_init_kernel<<<vgrid((uint64_t)nsrc * n), 256, 0, stream>>>(n, nsrc, L.srcs, L.F, L.V, levels, L.flags);
+    if ((rc = b2sr::check_launch("msbfs_init_kernel"))) return rc;
+    msbfs_seed_kernel<<<1, 64, 0, stream>>>(n, nsrc, L.srcs, L.F, L.V, levels);
+    if ((rc = b2sr::check_launch("msbfs_seed_kernel"))) return rc;
+    uint32_t level = 0;
+    for (;;) {
+        ++level;
+        if ((rc = spmv_bin_full(A, B2SR_OR_U64, L.F, nullptr, nullptr, 0, 0.0, 0.0, L.Y, nullptr, 0, stream)))
+            return rc;
+        uint32_t *fnow = L.flags + (level & 1), *fnext = L.flags + ((level + 1) & 1);
+        msbfs_update_kernel<<<vgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, levels, level, fnow, fnext);
+        if ((rc = b2sr::check_launch("msbfs_update_kernel"))) return rc;
+        uint32_t any = 0;
+        if ((rc = read_flag(fnow, &any, stream))) return rc;
+        if (!any) break;
+    }
+    if (iters) *iters = level;
+    return B2SR_OK;
+}
+
+int b2sr_sssp(const b2sr_matrix *A, uint32_t src, uint32_t *dist, void *ws, size_t ws_bytes, uint32_t *iters,
+              hipStream_t stream)
+{
+    Layout L;
+    int rc = check_algo_args(A, B2SR_ALGO_SSSP, ws, ws_bytes, &L);
+    if (rc) return rc;
+    if (!dist || src >= A->n) return B2SR_EINVAL;
+    const uint32_t n = A->n;
+    sssp_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, L.f0, L.flags);
+    if ((rc = b2sr::check_launch("sssp_init_kernel"))) return rc;
+    float *cur = L.f0, *nxt = L.f1;
+    uint32_t it = 0;
+    for (;;) {
+        ++it;
+        if ((rc = spmv_bin_full(A, B2SR_MIN_PLUS_F32, cur, nullptr, nullptr, B2SR_SELF, 1.0, 0.0, nxt, nullptr, 0,
+                                stream)))
+            return rc;
+        uint32_t *fnow = L.flags + (it & 1), *fnext = L.flags + ((it + 1) & 1);
+        changed_kernel<float><<<vgrid(n), 256, 0, stream>>>(n, cur, nxt, fnow, fnext);
+        if ((rc = b2sr::check_launch("changed_kernel"))) return rc;
+        uint32_t any = 0;
+        if ((rc = read_flag(fnow, &any, stream))) return rc;
+        std::swap(cur, nxt);
+        if (!any) break;
+    }
+    dist_to_u32_kernel<<<vgrid(n), 256, 0, stream>>>(n, cur, dist);
+    if ((rc = b2sr::check_launch("dist_to_u32_kernel"))) return rc;
+    if (iters) *iters = it;
+    return B2SR_OK;
+}
+
+int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, uint32_t *iters, hipStream_t stream)
+{
+    Layout L;
+    int rc = check_algo_args(A, B2SR_ALGO_CC, ws, ws_bytes, &L);
+    if (rc) return rc;
+    if (!labels) return B2SR_EINVAL;
+    const uint32_t n = A->n;
+    iota_kernel<<<vgrid(n), 256, 0, stream>>>(n, labels, L.flags);
+    if ((rc = b2sr::check_launch("iota_kernel"))) return rc;
+    uint32_t *cur = labels, *nxt = L.u0;
+    uint32_t it = 0;
+    for (;;) {
+        ++it;
+        if ((rc = spmv_bin_full(A, B2SR_MIN_PLUS_U32, cur, nullptr, nullptr, B2SR_SELF, 0.0, 0.0, nxt, nullptr, 0,
+                                stream)))
+            return rc;
+        uint32_t *fnow = L.flags + (it & 1), *fnext = L.flags + ((it + 1) & 1);
+        changed_kernel<uint32_t><<<vgrid(n), 256, 0, stream>>>(n, cur, nxt, fnow, fnext);
+        if ((rc = b2sr::check_launch("changed_kernel"))) return rc;
+        uint32_t any = 0;
+        if ((rc = read_flag(fnow, &any, stream))) return rc;
+        std::swap(cur, nxt);
+        if (!any) break;
+    }
+    if (cur != labels) {
+        copy_u32_kernel<<<vgrid(n), 256, 0, stream>>>(n, cur, labels);
+        if ((rc = b2sr::check_launch("copy_u32_kernel"))) return rc;
+    }
+    if (iters) *iters = it;
+    return B2SR_OK;
+}
+
+int b2sr_pagerank(const b2sr_matrix *A, float damping, uint32_t iterations, float *rank, void *ws, size_t ws_bytes,
+                  hipStream_t stream)
+{
+    Layout L;
+    int rc = check_algo_args(A, B2SR_ALGO_PAGERANK, ws, ws_bytes, &L);
+    if (rc) return rc;
+    if (!rank || !(damping >= 0.0f && damping <= 1.0f)) return B2SR_EINVAL;
+    const uint32_t n = A->n, nw = b2sr::n_words(n);
+    // out-degrees as a count product with the all-ones vector (bmv_bin_bin_full)
+    ones_bits_kernel<<<vgrid(nw), 256, 0, stream>>>(n, L.ones);
+    if ((rc = b2sr::check_launch("ones_bits_kernel"))) return rc;
+    if ((rc = spmv_bin_bin(A, L.ones, nullptr, B2SR_OUT_COUNT, L.u0, stream))) return rc;
+    float *r = rank, *r_next = L.f2;
+    pr_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, L.u0, L.f1, r);
+    if ((rc = b2sr::check_launch("pr_init_kernel"))) return rc;
+    const double beta = (1.0 - (double)damping) / (double)n;
+    for (uint32_t it = 0; it < iterations; ++it) {
+        pr_scale_kernel<<<vgrid(n), 256, 0, stream>>>(n, r, L.f1, L.f0);
+        if ((rc = b2sr::check_launch("pr_scale_kernel"))) return rc;
+        if ((rc = spmv_bin_full(A, B2SR_PLUS_TIMES_F32, L.f0, nullptr, nullptr, 0, damping, beta, r_next, L.spmv_ws,
+                                L.spmv_ws_bytes, stream)))
+            return rc;
+        std::swap(r, r_next);
+    }
+    if (r != rank) {
+        copy_u32_kernel<<<vgrid(n), 256, 0, stream>>>(n, (const uint32_t *)r, (uint32_t *)rank);
+        if ((rc = b2sr::check_launch("copy_u32_kernel"))) return rc;
+    }
+    return B2SR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,260 @@
+// Masked B2SR matrix-matrix product, reduced to one sum (Sec. IV, Table IV:
+// bmm_bin_bin_sum and bmm_bin_bin_sum_masked; Sec. V: triangle counting).
+//
+//   s = sum_{(i,j) : M_ij = 1} sum_k A_ik * B_kj,  B supplied as Bt (rows of Bt
+//   are columns of B), so (A B)_ij is the dot product of bit-row i of A with
+//   bit-row j of Bt.
+//
+// The paper's kernel walks A's tile-row, multiplies whole tile pairs with
+// shuffles and popcounts, and masks afterwards.  Here the mask drives the work
+// (a masked dot product): only output positions with M_ij = 1 are computed.
+//   * A workgroup owns one tile-row I.  It marks the tile columns of A's
+//     tile-row I in an LDS bitmap with a popcount prefix per word, which turns
+//     "is there a tile A_IK, and where" into two LDS reads.
+//   * Its waves take the mask tiles (I, J) of M's tile-row I in turn.  A wave
+//     lists the set bits (r, c) of the mask tile in LDS, then streams Bt's
+//     tile-row J one tile column K per lane; each lane whose K also appears in
+//     A's tile-row adds popcount(A_IK[r] & Bt_JK[c]) over the listed (r, c).
+//   * Lanes accumulate in 64-bit registers; one atomic add per wave at the end.
+// For triangle counting (A = Bt = M = L, the strict lower triangle) row I of L
+// is read once per workgroup and Bt's rows are re-read from L2/MALL.
+#include "common.h"
+
+using namespace b2sr_dev;
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / B2SR_WAVE;
+constexpr uint32_t kMapWords = 4096;  // bitmap of up to 131072 tile columns
+constexpr uint32_t kMaxPairs = 1024;  // set bits of a 32 x 32 mask tile
+
+template <int T> __device__ __forceinline__ uint32_t load_word(const void *bits, size_t idx)
+{
+    if constexpr (T == 32) return ((const uint32_t *)bits)[idx];
+    else if constexpr (T == 16) return ((const uint16_t *)bits)[idx];
+    else return ((const uint8_t *)bits)[idx];
+}
+
+struct GemmArgs {
+    const uint32_t *a_rp, *a_ci;
+    const void *a_bits;
+    const uint32_t *b_rp, *b_ci;
+    const void *b_bits;
+    const uint32_t *m_rp, *m_ci;
+    const void *m_bits;
+    uint32_t ntr;
+    unsigned long long *sum;
+};
+
+template <int T> __global__ void __launch_bounds__(kThreads) spgemm_masked_kernel(GemmArgs g)
+{
+    __shared__ uint32_t s_map[kMapWords];
+    __shared__ uint32_t s_pre[kMapWords];
+    __shared__ uint32_t s_thr[kThreads];
+    __shared__ uint16_t s_pairs[kWaves][kMaxPairs];
+    __shared__ uint32_t s_cnt[kWaves][B2SR_WAVE];
+    const uint32_t lane = lane_id(), wv = threadIdx.x / B2SR_WAVE;
+    unsigned long long acc = 0;
+
+    for (uint32_t I = blockIdx.x; I < g.ntr; I += gridDim.x) {
+        const uint32_t m0 = g.m_rp[I], m1 = g.m_rp[I + 1];
+        const uint32_t a0 = g.a_rp[I], a1 = g.a_rp[I + 1];
+        if (m0 == m1 || a0 == a1) continue;  // workgroup-uniform
+        const uint32_t jlo = g.a_ci[a0], jhi = g.a_ci[a1 - 1];
+        const uint32_t span = jhi - jlo + 1;
+        const bool use_map = span <= kMapWords * 32;
+        __syncthreads();
+        if (use_map) {
+            const uint32_t nw = (span + 31) / 32;
+            for (uint32_t w = threadIdx.x; w < nw; w += kThreads) s_map[w] = 0;
+            __syncthreads();
+            for (uint32_t e = a0 + threadIdx.x; e < a1; e += kThreads) {
+                const uint32_t off = g.a_ci[e] - jlo;
+                atomicOr(&s_map[off >> 5], 1u << (off & 31));
+            }
+            __syncthreads();
+            const uint32_t per = (nw + kThreads - 1) / kThreads;
+            const uint32_t w0 = threadIdx.x * per, w1 = min(nw, w0 + per);
+            uint32_t local = 0;
+            for (uint32_t w = w0; w < w1; ++w) local += __popc(s_map[w]);
+            s_thr[threadIdx.x] = local;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t run = 0;
+                for (int k = 0; k < kThreads; ++k) {
+                    const uint32_t t = s_thr[k];
+                    s_thr[k] = run;
+                    run += t;
+                }
+            }
+            __syncthreads();
+            uint32_t run = s_thr[threadIdx.x];
+            for (uint32_t w = w0; w < w1; ++w) {
+                s_pre[w] = run;
+                run += __popc(s_map[w]);
+            }
+            __syncthreads();
+        }
+        // Position of tile column K in A's tile-row I, or -1.
+        auto lookup = [&](uint32_t K) -> int64_t {
+            if (K < jlo || K > jhi) return -1;
+            if (use_map) {
+                const uint32_t off = K - jlo, w = off >> 5, b = off & 31;
+                const uint32_t m = s_map[w];
+                if (!((m >> b) & 1u)) return -1;
+                return (int64_t)a0 + s_pre[w] + __popc(m & ((1u << b) - 1u));
+            }
+            uint32_t lo = a0, hi = a1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (g.a_ci[mid] < K) lo = mid + 1; else hi = mid;
+            }
+            return (lo < a1 && g.a_ci[lo] == K) ? (int64_t)lo : -1;
+        };
+
+        for (uint32_t m = m0 + wv; m < m1; m += kWaves) {
+            const uint32_t J = g.m_ci[m];
+            // list the set bits (r, c) of mask tile m
+            const uint32_t mw = lane < (uint32_t)T ? load_word<T>(g.m_bits, (size_t)m * T + lane) : 0u;
+            const uint32_t cnt = __popc(mw);
+            uint32_t inc = cnt;
+            for (uint32_t d = 1; d < 64; d <<= 1) {
+                const uint32_t o = shfl_up(inc, d);
+                if (lane >= d) inc += o;
+            }
+            const uint32_t npairs = readlane(inc, 63);
+            uint32_t pos = inc - cnt, w = mw;
+            while (w) {
+                const uint32_t c = __builtin_ctz(w);
+                w &= w - 1;
+                s_pairs[wv][pos++] = (uint16_t)((lane << 8) | c);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const uint32_t b0 = g.b_rp[J], b1 = g.b_rp[J + 1];
+            for (uint32_t kb = b0 + lane; kb < b1 + ((b1 - b0) % 64 ? 64 - (b1 - b0) % 64 : 0); kb += 64) {
+                int64_t ia = -1;
+                if (kb < b1) ia = lookup(g.b_ci[kb]);
+                if (ia >= 0) {
+                    const size_t abase = (size_t)ia * T, bbase = (size_t)kb * T;
+                    uint32_t part = 0;
+                    for (uint32_t q = 0; q < npairs; ++q) {
+                        const uint32_t rc = s_pairs[wv][q];
+                        part += __popc(load_word<T>(g.a_bits, abase + (rc >> 8)) &
+                                       load_word<T>(g.b_bits, bbase + (rc & 0xFFu)));
+                    }
+                    acc += part;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    (void)s_cnt;
+    for (int d = 32; d >= 1; d >>= 1) acc += shfl_xor((uint64_t)acc, d);
+    if (lane == 0 && acc) atomicAdd(g.sum, acc);
+}
+
+// Unmasked sum: sum_{i,j} (A B)_ij = sum_k colsum_A(k) * colsum_Bt(k).
+// One thread per (tile, column) counts that column's bits.
+template <int T>
+__global__ void column_counts_kernel(const uint32_t *__restrict__ ci, const void *__restrict__ bits, uint32_t ntiles,
+                                     uint32_t *__restrict__ colsum)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)ntiles * T;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t t = (uint32_t)(i / T), c = (uint32_t)(i % T);
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int r = 0; r < T; ++r) cnt += (load_word<T>(bits, (size_t)t * T + r) >> c) & 1u;
+        if (cnt) atomicAdd(&colsum[(size_t)ci[t] * T + c], cnt);
+    }
+}
+
+__global__ void __launch_bounds__(256) dot_counts_kernel(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+                                                         uint64_t len, unsigned long long *sum)
+{
+    unsigned long long acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (uint64_t)gridDim.x * blockDim.x)
+        acc += (unsigned long long)a[i] * b[i];
+    for (int d = 32; d >= 1; d >>= 1) acc += shfl_xor((uint64_t)acc, d);
+    if (lane_id() == 0 && acc) atomicAdd(sum, acc);
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p) { *p = 0; }
+
+template <int T> int launch_masked(const GemmArgs &g, hipStream_t s)
+{
+    spgemm_masked_kernel<T><<<b2sr::grid_for(g.ntr, 1, 1u << 16), kThreads, 0, s>>>(g);
+    return b2sr::check_launch("spgemm_masked_kernel");
+}
+
+template <int T>
+int launch_unmasked(const b2sr_matrix *A, const b2sr_matrix *Bt, uint32_t *ws, uint64_t len,
+                    unsigned long long *sum, hipStream_t s)
+{
+    column_counts_kernel<T><<<b2sr::grid_for((uint64_t)A->ntiles * T, 256, 65536), 256, 0, s>>>(
+        A->tile_colind, A->bits, A->ntiles, ws);
+    if (int rc = b2sr::check_launch("column_counts_kernel")) return rc;
+    column_counts_kernel<T><<<b2sr::grid_for((uint64_t)Bt->ntiles * T, 256, 65536), 256, 0, s>>>(
+        Bt->tile_colind, Bt->bits, Bt->ntiles, ws + len);
+    if (int rc = b2sr::check_launch("column_counts_kernel")) return rc;
+    dot_counts_kernel<<<b2sr::grid_for(len, 256, 4096), 256, 0, s>>>(ws, ws + len, len, sum);
+    return b2sr::check_launch("dot_counts_kernel");
+}
+
+}  // namespace
+
+namespace b2sr {
+int fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
+}
+
+extern "C" {
+
+size_t spgemm_masked_workspace_bytes(const b2sr_matrix *A, const b2sr_matrix *M)
+{
+    if (!A || !b2sr::valid_tile(A->tile) || M) return 0;
+    return (size_t)2 * b2sr::n_tile_rows(A->n, A->tile) * A->tile * sizeof(uint32_t);
+}
+
+int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix *M, unsigned flags,
+                  uint64_t *d_sum, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    int rc = b2sr::validate_matrix(A);
+    if (rc) return rc;
+    if ((rc = b2sr::validate_matrix(Bt))) return rc;
+    if (M && (rc = b2sr::validate_matrix(M))) return rc;
+    if (flags & ~B2SR_ACCUMULATE) return B2SR_EINVAL;
+    if (!d_sum) return B2SR_EINVAL;
+    if (Bt->n != A->n || Bt->tile != A->tile) return B2SR_EINVAL;
+    if (M && (M->n != A->n || M->tile != A->tile)) return B2SR_EINVAL;
+    const size_t need = spgemm_masked_workspace_bytes(A, M);
+    if (ws_bytes < need || (need && !ws)) return B2SR_ENOSPC;
+    unsigned long long *sum = (unsigned long long *)d_sum;
+    if (!(flags & B2SR_ACCUMULATE)) {
+        zero_u64_kernel<<<1, 1, 0, stream>>>(sum);
+        if ((rc = b2sr::check_launch("zero_u64_kernel"))) return rc;
+    }
+    if (A->n == 0 || A->ntiles == 0 || Bt->ntiles == 0 || (M && M->ntiles == 0)) return B2SR_OK;
+    if (!M) {
+        const uint64_t len = (uint64_t)b2sr::n_tile_rows(A->n, A->tile) * A->tile;
+        if ((rc = b2sr::fill_u32((uint32_t *)ws, 2 * len, 0, stream))) return rc;
+        switch (A->tile) {
+        case 4: return launch_unmasked<4>(A, Bt, (uint32_t *)ws, len, sum, stream);
+        case 8: return launch_unmasked<8>(A, Bt, (uint32_t *)ws, len, sum, stream);
+        case 16: return launch_unmasked<16>(A, Bt, (uint32_t *)ws, len, sum, stream);
+        default: return launch_unmasked<32>(A, Bt, (uint32_t *)ws, len, sum, stream);
+        }
+    }
+    GemmArgs g{A->tile_rowptr, A->tile_colind, A->bits, Bt->tile_rowptr, Bt->tile_colind, Bt->bits,
+               M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), sum};
+    switch (A->tile) {
+    case 4: return launch_masked<4>(g, stream);
+    case 8: return launch_masked<8>(g, stream);
+    case 16: return launch_masked<16>(g, stream);
+    default: return launch_masked<32>(g, stream);
+    }
+}
+
+}  // extern "C"

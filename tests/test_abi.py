@@ -1,0 +1,124 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/b2sr.h declares, and rejects bad arguments on the host before any
+launch."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+import paper_2201_08560_amd as b2
+
+L = b2.lib()
+FAKE = 0x1000  # never dereferenced: every call below fails host validation first
+
+
+def mat(n=64, tile=8, ntiles=4, rp=FAKE, ci=FAKE, bits=FAKE, reserved=0):
+    return b2.b2sr_matrix(n, tile, ntiles, reserved, rp, ci, bits)
+
+
+def test_every_declared_function_is_exported():
+    names = b2.header_functions()
+    assert {"b2sr_from_csr", "spmv_bin_bin", "spmv_bin_full", "spgemm_masked"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", b2.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = {line.split()[-1] for line in out.stdout.splitlines() if " T " in line}
+    missing = [f for f in names if f not in exported]
+    assert not missing, missing
+    for f in names:
+        assert hasattr(L, f)
+
+
+def test_strerror_and_version():
+    assert b2.b2sr_strerror(0) == "success"
+    assert "invalid" in b2.b2sr_strerror(-1)
+    assert "workspace" in b2.b2sr_strerror(-3)
+    assert b2.b2sr_strerror(-99) == "unknown status"
+    assert L.b2sr_version() >= 100
+
+
+def test_matrix_validation():
+    S = None
+    x = ctypes.c_void_p(FAKE)
+    assert L.spmv_bin_bin(None, x, None, 0, x, S) == -1
+    for bad in (mat(tile=6), mat(tile=64), mat(reserved=1), mat(rp=0), mat(ci=0), mat(bits=0),
+                mat(tile=32, bits=FAKE + 4), mat(ntiles=10**6, n=64, tile=32)):
+        assert L.spmv_bin_bin(ctypes.byref(bad), x, None, 0, x, S) == -1
+    assert L.spmv_bin_bin(ctypes.byref(mat(n=0xFFFFFFF0)), x, None, 0, x, S) == -2
+
+
+def test_spmv_argument_errors():
+    A = ctypes.byref(mat())
+    x = ctypes.c_void_p(FAKE)
+    y = ctypes.c_void_p(FAKE + 4096)
+    assert L.spmv_bin_bin(A, None, None, 0, y, None) == -1                 # x NULL
+    assert L.spmv_bin_bin(A, x, None, 0, None, None) == -1                 # y NULL
+    assert L.spmv_bin_bin(A, x, None, 0x100, y, None) == -1                # unknown flag
+    assert L.spmv_bin_bin(A, x, None, 0, x, None) == -1                    # y aliases x
+    assert L.spmv_bin_full(A, 9, x, None, None, 0, 1.0, 0.0, y, None, 0, None) == -5   # unknown semiring
+    assert L.spmv_bin_full(A, 1, x, None, None, b2.SELF, 1.0, 0.0, y, None, 0, None) == -1  # SELF on plus
+    assert L.spmv_bin_full(A, 3, x, None, None, 0, 1.5, 0.0, y, None, 0, None) == -1   # non-integral u32 weight
+    assert L.spmv_bin_full(A, 3, x, ctypes.c_void_p(FAKE), None, 0, 1.0, 0.0, y, None, 0, None) == -1  # scale on min
+    need = L.spmv_bin_full_workspace_bytes(A, 1)
+    assert need > 0
+    assert L.spmv_bin_full(A, 1, x, None, None, 0, 1.0, 0.0, y, None, 0, None) == -3   # no workspace
+    assert L.spmv_bin_full(A, 1, x, None, None, 0, 1.0, 0.0, y, x, need - 1, None) == -3
+    assert L.spmv_bin_full_workspace_bytes(A, 2) == 0
+
+
+def test_spgemm_and_build_argument_errors():
+    A = ctypes.byref(mat())
+    B16 = ctypes.byref(mat(tile=16))
+    Bn = ctypes.byref(mat(n=65))
+    s = ctypes.c_void_p(FAKE)
+    assert L.spgemm_masked(A, B16, None, 0, s, None, 0, None) == -1     # tile mismatch
+    assert L.spgemm_masked(A, Bn, None, 0, s, None, 0, None) == -1      # n mismatch
+    assert L.spgemm_masked(A, A, A, 0, None, None, 0, None) == -1       # no output
+    assert L.spgemm_masked(A, A, A, 0x8, s, None, 0, None) == -1        # unknown flag
+    assert L.spgemm_masked_workspace_bytes(A, A) == 0
+    assert L.spgemm_masked_workspace_bytes(A, None) == 2 * 8 * 8 * 4
+    assert L.spgemm_masked(A, A, None, 0, s, None, 0, None) == -3       # unmasked needs workspace
+    nt = ctypes.c_uint64(0)
+    p = ctypes.c_void_p(FAKE)
+    assert L.b2sr_count_tiles(10, 5, p, p, 5, 0, p, ctypes.byref(nt), None) == -1       # tile 5
+    assert L.b2sr_count_tiles(10, 5, p, p, 8, 2, p, ctypes.byref(nt), None) == -1       # unknown flag
+    assert L.b2sr_count_tiles(10, 1 << 32, p, p, 8, 0, p, ctypes.byref(nt), None) == -2  # nnz too large
+    assert L.b2sr_count_tiles(10, 5, None, p, 8, 0, p, ctypes.byref(nt), None) == -1
+    assert L.b2sr_from_csr(10, 5, p, p, 8, 0, p, 1 << 32, p, p, None) == -2
+    assert L.b2sr_from_csr(10, 5, p, p, 8, 0, p, 3, p, ctypes.c_void_p(FAKE + 2), None) == -1
+    assert L.b2sr_pack_bits(10, None, p, None) == -1
+
+
+def test_algorithm_argument_errors():
+    A = ctypes.byref(mat())
+    need = L.b2sr_algo_workspace_bytes(A, b2.ALGO_BFS)
+    assert need > 0
+    for algo in (b2.ALGO_BFS, b2.ALGO_SSSP, b2.ALGO_CC, b2.ALGO_PAGERANK, b2.ALGO_MSBFS):
+        assert L.b2sr_algo_workspace_bytes(A, algo) > 0
+    assert L.b2sr_algo_workspace_bytes(A, 99) == 0
+    p = ctypes.c_void_p(FAKE)
+    it = ctypes.c_uint32(0)
+    assert L.b2sr_bfs(A, 0, p, None, 0, ctypes.byref(it), None) == -3             # no workspace
+    assert L.b2sr_bfs(A, 0, p, p, need - 1, ctypes.byref(it), None) == -3
+    assert L.b2sr_bfs(A, 64, p, p, need, ctypes.byref(it), None) == -1            # src >= n
+    wsm = L.b2sr_algo_workspace_bytes(A, b2.ALGO_MSBFS)
+    srcs = (ctypes.c_uint32 * 3)(1, 2, 1)
+    assert L.b2sr_msbfs(A, srcs, 3, p, p, wsm, ctypes.byref(it), None) == -1      # repeated source
+    srcs65 = (ctypes.c_uint32 * 65)(*range(65))
+    assert L.b2sr_msbfs(A, srcs65, 65, p, p, wsm, ctypes.byref(it), None) == -1   # > 64 sources
+    wpr = L.b2sr_algo_workspace_bytes(A, b2.ALGO_PAGERANK)
+    assert L.b2sr_pagerank(A, ctypes.c_float(1.5), 3, p, p, wpr, None) == -1      # damping > 1
+
+
+def test_library_has_no_cpu_fallback_symbols():
+    """The product library links the HIP runtime and nothing from the oracle."""
+    out = subprocess.run(["nm", "-D", b2.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    assert "orc_" not in out
+    ldd = subprocess.run(["ldd", b2.LIB_PATH], capture_output=True, text=True).stdout
+    assert "amdhip64" in ldd and "oracle" not in ldd
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(b2, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(b2, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        b2.lib()
