@@ -1,0 +1,325 @@
+"""Benchmark of the B2SR hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (timed step): R-MAT scale 20, edge factor 16 (a, b, c = 0.57, 0.19,
+0.19; symmetrised, self-loops removed, seed 20), B2SR tile 32x32, resident in
+HBM.  One step runs every product of the path once over it:
+  * vector binarisation of a predicate vector;
+  * one masked bin x bin SpMV with a full frontier (mask: 1 % visited);
+  * one bin x bin count SpMV (popcount dot products);
+  * one plus-times and one min-plus bin x full SpMV;
+  * BFS from 64 seeded sources as one 64-wide bit-frontier BFS;
+  * SSSP (unit weights) from the first source; CC by min-label propagation;
+  * 50 PageRank iterations (d = 0.85) in float32.
+value = edges evaluated per second over the step: every matrix product in the
+step counts nnz(A) edges (the product is computed over the whole matrix; tiles
+that cannot contribute are skipped, which changes no result).
+
+Also reported (same process, outside the timed step): the CSR -> B2SR
+conversion time, single-source BFS GTEPS (Graph500 style), triangle counting
+(masked SpGEMM) edges/s on R-MAT scale 18 and a 2048 x 2048 king grid for tile
+widths 4..32, the roofline of the headline kernel (masked bin x bin SpMV,
+measured with HIP events on its stream), and the CPU oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import graphgen as gg  # noqa: E402
+import paper_2201_08560_amd as b2  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pack(b: np.ndarray) -> torch.Tensor:
+    nw = max((b.size + 31) // 32, 1)
+    pad = np.zeros(nw * 32, dtype=np.uint8)
+    pad[: b.size] = b
+    return torch.from_numpy(np.packbits(pad, bitorder="little").view(np.int32).copy()).cuda()
+
+
+def spmv_bytes(A: b2.B2SR, with_mask: bool) -> int:
+    """Compulsory HBM bytes of one full-frontier bin x bin SpMV: the three B2SR
+    arrays once, the x bit vector, the y bit vector and the mask."""
+    vec = ((A.n + 31) // 32) * 4
+    return A.nbytes + vec * (3 if with_mask else 2)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("common.h", "spmv.hip"):
+        with open(os.path.join(ROOT, "paper_2201_08560_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(digest: str):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they
+    were taken on the current kernel source."""
+    path = os.path.join(PROFILES, "spmv_bits_t32_rmat20_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_digest") != digest:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class Workload:
+    def __init__(self, g: gg.Csr, tile: int):
+        self.g = g
+        t0 = time.perf_counter()
+        self.A = b2.B2SR.from_graph(g, tile)
+        torch.cuda.synchronize()
+        self.convert_s = time.perf_counter() - t0
+        n = g.n
+        r = gg.rng(2020)
+        self.sources = gg.sample_sources(g, 64, seed=64)
+        self.pred = torch.from_numpy((r.random(n) < 0.5).astype(np.uint8)).cuda()
+        self.x_full = pack(np.ones(n, bool))
+        self.mask = pack(r.random(n) < 0.01)
+        self.xf = torch.from_numpy(r.random(n).astype(np.float32)).cuda()
+        self.xd = torch.from_numpy(np.where(r.random(n) < 0.5, r.integers(0, 20, n), np.inf).astype(np.float32)).cuda()
+        self.bits_out = torch.empty(max((n + 31) // 32, 1), dtype=torch.int32, device="cuda")
+        self.y_bits = torch.zeros_like(self.bits_out)
+        self.y_cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+        self.y_f = torch.empty(n, dtype=torch.float32, device="cuda")
+        self.y_f2 = torch.empty(n, dtype=torch.float32, device="cuda")
+        self.ws_plus = torch.empty(max(b2.spmv_bin_full_workspace_bytes(self.A, b2.PLUS_TIMES_F32), 1),
+                                   dtype=torch.uint8, device="cuda")
+        self.ws = {a: torch.empty(b2.b2sr_algo_workspace_bytes(self.A, a), dtype=torch.uint8, device="cuda")
+                   for a in (b2.ALGO_MSBFS, b2.ALGO_SSSP, b2.ALGO_CC, b2.ALGO_PAGERANK, b2.ALGO_BFS)}
+        self.lv_multi = torch.empty((64, n), dtype=torch.int32, device="cuda")
+        self.dist = torch.empty(n, dtype=torch.int32, device="cuda")
+        self.labels = torch.empty(n, dtype=torch.int32, device="cuda")
+        self.rank = torch.empty(n, dtype=torch.float32, device="cuda")
+        self.ev = []
+        self.products = 0
+
+    def step(self, record: bool):
+        A = self.A
+        prods = 0
+        b2.b2sr_pack_bits(self.pred, out=self.bits_out)
+        # headline kernel: masked bin x bin SpMV, bracketed by events on its stream
+        self.y_bits.zero_()
+        if record:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+        b2.spmv_bin_bin(A, self.x_full, self.mask, complement=True, accumulate=True, out=self.y_bits)
+        if record:
+            e1.record()
+            self.ev.append((e0, e1))
+        b2.spmv_bin_bin(A, self.x_full, None, count=True, out=self.y_cnt)
+        b2.spmv_bin_full(A, b2.PLUS_TIMES_F32, self.xf, out=self.y_f, ws=self.ws_plus)
+        b2.spmv_bin_full(A, b2.MIN_PLUS_F32, self.xd, self_loop=True, alpha=1.0, out=self.y_f2)
+        prods += 4
+        _, it = b2.b2sr_msbfs(A, self.sources, out=self.lv_multi, ws=self.ws[b2.ALGO_MSBFS])
+        prods += it
+        _, it = b2.b2sr_sssp(A, int(self.sources[0]), out=self.dist, ws=self.ws[b2.ALGO_SSSP])
+        prods += it
+        _, it = b2.b2sr_cc(A, out=self.labels, ws=self.ws[b2.ALGO_CC])
+        prods += it
+        b2.b2sr_pagerank(A, 0.85, 50, out=self.rank, ws=self.ws[b2.ALGO_PAGERANK])
+        prods += 51  # 50 iterations + the degree count
+        self.products = prods
+
+
+def bfs_gteps(w: Workload, nsrc: int = 8) -> dict:
+    """Single-source BFS, Graph500 style: undirected edges of the source's
+    component over the BFS time, harmonic mean over sources."""
+    g = w.g
+    rates, times = [], []
+    for s in w.sources[:nsrc]:
+        lv, _ = b2.b2sr_bfs(w.A, int(s), ws=w.ws[b2.ALGO_BFS])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lv, _ = b2.b2sr_bfs(w.A, int(s), ws=w.ws[b2.ALGO_BFS])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        reached = b2.as_u32(lv) != b2.UNREACHED
+        edges = int(g.degrees()[reached].sum()) // 2
+        rates.append(edges / dt / 1e9)
+        times.append(dt)
+    return {"gteps_hmean": len(rates) / sum(1.0 / r for r in rates), "ms_mean": 1e3 * float(np.mean(times)),
+            "sources": nsrc}
+
+
+def tc_section(reps: int = 3) -> dict:
+    out = {}
+    for name, g in (("rmat18_ef16", gg.rmat(18, 16, seed=18)), ("king2048", gg.king_grid(2048, 2048))):
+        log(f"tc {name}: n={g.n} nnz={g.nnz}")
+        res = {"edges": g.edges}
+        for T in (4, 8, 16, 32):
+            L = b2.B2SR.from_graph(g, T, lower=True)
+            s = b2.spgemm_masked(L, L, L)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                b2.spgemm_masked(L, L, L, out=s)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) / 1e3)
+            t = float(np.median(ts))
+            res[f"T{T}"] = {"triangles": int(b2.as_u64(s)[0]), "ms": 1e3 * t, "edges_per_s": g.edges / t}
+            del L
+        out[name] = res
+    return out
+
+
+def cpu_baseline(w: Workload, edges_per_step: float) -> dict:
+    """The oracle on the host: the same step's results (64 BFS, SSSP, CC,
+    PageRank x 50 and the four single products), timed once."""
+    import oracle as orc
+    g = w.g
+    n = g.n
+    r = gg.rng(2020)
+    pred = r.random(n) < 0.5  # noqa: F841  (same draws as the GPU inputs)
+    ones = np.ones(n, bool)
+    mask = r.random(n) < 0.01
+    xf = r.random(n)
+    xd = np.where(r.random(n) < 0.5, r.integers(0, 20, n), np.inf).astype(np.float64)
+    orc.lib()
+    t0 = time.perf_counter()
+    orc.spmv_or(g, ones, mask, True)
+    orc.spmv_count(g, ones)
+    orc.spmv_plus(g, xf)
+    orc.spmv_min_plus(g, xd, 1.0, True)
+    orc.bfs_multi(g, w.sources)
+    orc.sssp_unit(g, int(w.sources[0]))
+    orc.cc(g)
+    orc.pagerank(g, 0.85, 50)
+    dt = time.perf_counter() - t0
+    return {"value": edges_per_step / dt / 1e9, "unit": "GTEPS", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": "one full step of the same workload (R-MAT s20): 4 single products, 64 BFS, SSSP, CC, "
+                      f"PageRank x 50; {dt:.1f} s wall"}
+
+
+def verify(w: Workload) -> dict:
+    """Spot checks of the timed outputs against the oracle."""
+    import oracle as orc
+    g = w.g
+    ok = {}
+    lv = b2.as_u32(w.lv_multi)
+    ref = orc.bfs_multi(g, w.sources[:4])
+    ok["bfs64_first4"] = bool(np.array_equal(lv[:4], ref))
+    ok["sssp"] = bool(np.array_equal(b2.as_u32(w.dist), orc.sssp_unit(g, int(w.sources[0]))))
+    ok["cc"] = bool(np.array_equal(b2.as_u32(w.labels), orc.cc(g)))
+    pr = w.rank.cpu().numpy().astype(np.float64)
+    refp = orc.pagerank(g, 0.85, 50)
+    ok["pagerank_rel_l1"] = float(np.abs(pr - refp).sum() / refp.sum())
+    return ok
+
+
+def profile_mode(args):
+    """A short fixed program for rocprofv3 counter runs: a 1 GiB device copy
+    (the scale for FETCH_SIZE / WRITE_SIZE) and a few headline SpMV launches."""
+    g = gg.rmat(20, 16, seed=20)
+    w = Workload(g, 32)
+    src = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    for _ in range(args.steps):
+        w.y_bits.zero_()
+        b2.spmv_bin_bin(w.A, w.x_full, w.mask, complement=True, accumulate=True, out=w.y_bits)
+    torch.cuda.synchronize()
+    log(json.dumps({"profile_mode": True, "spmv_bytes": spmv_bytes(w.A, True), "copy_bytes": 2 * src.numel() * 4,
+                    "kernel_source_digest": source_digest()}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--profile-mode", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE={world}) is not supported: this build "
+              "runs the B2SR path on a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    if args.profile_mode:
+        profile_mode(args)
+        return
+
+    log("generating R-MAT s20 ef16 ...")
+    g = gg.rmat(20, 16, seed=20)
+    w = Workload(g, 32)
+    log(f"B2SR-32: ntiles={w.A.ntiles} bytes={w.A.nbytes} convert={w.convert_s * 1e3:.1f} ms")
+
+    for _ in range(args.warmup):
+        w.step(record=False)
+    torch.cuda.synchronize()
+    w.ev.clear()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        w.step(record=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    edges_per_step = w.products * g.nnz
+    value = edges_per_step * args.steps / t / 1e9
+    kt = float(np.mean([a.elapsed_time(b) for a, b in w.ev])) / 1e3
+    alg = spmv_bytes(w.A, True)
+    digest = source_digest()
+    traffic = read_traffic(digest)
+    out = {
+        "metric": "B2SR SpMV GTEPS + masked-SpGEMM TC edges/s; batched vs per-graph launches",
+        "value": value, "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * t / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 bit tiles; f32 PageRank/SSSP; u32 CC", "data": "synthetic",
+        "config": {"workload": "R-MAT scale 20, edge factor 16 (0.57/0.19/0.19), symmetrised, B2SR-32: "
+                               "4 single products + 64-source BFS + SSSP + CC + 50 PageRank iterations",
+                   "n": g.n, "nnz": g.nnz, "tile": 32, "ntiles": w.A.ntiles, "products_per_step": w.products,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "spmv_bits_kernel<32> (masked bin x bin SpMV, full frontier)",
+                     "achieved": alg / kt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / kt / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg, "ms_per_launch": kt * 1e3, "gteps": g.nnz / kt / 1e9,
+                     "kernel_source_digest": digest},
+        "convert_ms": w.convert_s * 1e3,
+    }
+    if not args.no_extras:
+        out["verify"] = verify(w)
+        out["bfs_single_source"] = bfs_gteps(w)
+        out["tc"] = tc_section()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, edges_per_step)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
