@@ -92,6 +92,9 @@ def read_traffic(digest: str):
 class Workload:
     def __init__(self, g: gg.Csr, tile: int):
         self.g = g
+        small = gg.er_gnm(1024, 4096, seed=3)  # first launches load the code objects: keep them out of the timing
+        b2.B2SR.from_graph(small, tile)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         self.A = b2.B2SR.from_graph(g, tile)
         torch.cuda.synchronize()
@@ -206,19 +209,24 @@ def cpu_baseline(w: Workload, edges_per_step: float) -> dict:
     xf = r.random(n)
     xd = np.where(r.random(n) < 0.5, r.integers(0, 20, n), np.inf).astype(np.float64)
     orc.lib()
+    reps = 0
     t0 = time.perf_counter()
-    orc.spmv_or(g, ones, mask, True)
-    orc.spmv_count(g, ones)
-    orc.spmv_plus(g, xf)
-    orc.spmv_min_plus(g, xd, 1.0, True)
-    orc.bfs_multi(g, w.sources)
-    orc.sssp_unit(g, int(w.sources[0]))
-    orc.cc(g)
-    orc.pagerank(g, 0.85, 50)
-    dt = time.perf_counter() - t0
+    while True:  # whole steps until at least 10 s of host work
+        orc.spmv_or(g, ones, mask, True)
+        orc.spmv_count(g, ones)
+        orc.spmv_plus(g, xf)
+        orc.spmv_min_plus(g, xd, 1.0, True)
+        orc.bfs_multi(g, w.sources)
+        orc.sssp_unit(g, int(w.sources[0]))
+        orc.cc(g)
+        orc.pagerank(g, 0.85, 50)
+        reps += 1
+        if time.perf_counter() - t0 >= 10.0:
+            break
+    dt = (time.perf_counter() - t0) / reps
     return {"value": edges_per_step / dt / 1e9, "unit": "GTEPS", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": "one full step of the same workload (R-MAT s20): 4 single products, 64 BFS, SSSP, CC, "
-                      f"PageRank x 50; {dt:.1f} s wall"}
+            "sample": f"{reps} full steps of the same workload (R-MAT s20: 4 single products, 64 BFS, SSSP, CC, "
+                      f"PageRank x 50), {dt:.2f} s wall each"}
 
 
 def verify(w: Workload) -> dict:

@@ -88,6 +88,9 @@ extern "C" {
 #define B2SR_ACCUMULATE 0x4u      /* combine with the existing y (or *d_sum) instead of     */
                                   /* overwriting it                                          */
 #define B2SR_SELF 0x8u            /* min-plus: the diagonal is a real zero (Sec. V, SSSP)   */
+#define B2SR_SPARSE_X 0x10u       /* spmv_bin_bin hint: x has few set bits, so read a tile   */
+                                  /* only after finding its x segment non-zero (results are  */
+                                  /* the same either way; only the memory traffic differs)   */
 
 /* Semirings for spmv_bin_full (Table V). */
 #define B2SR_PLUS_TIMES_F32 1 /* arithmetic, float x / y                           */
@@ -165,6 +168,7 @@ int b2sr_pack_bits(uint32_t n, const uint8_t *pred, uint32_t *bits, hipStream_t 
  *     row gets the identity (0), or keeps its old value under ACCUMULATE.
  *   B2SR_ACCUMULATE: y |= result (bits) or y += result (counts).
  *   Otherwise y is overwritten.  y must not alias x or mask.
+ *   B2SR_SPARSE_X: a performance hint for sparse frontiers (see the flag).
  *   Errors: EINVAL, EHIP.
  */
 int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, unsigned flags,
@@ -190,6 +194,7 @@ int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, 
  *   chunk order by a second kernel).
  *   ws/ws_bytes: workspace of at least spmv_bin_full_workspace_bytes(A,
  *   semiring) bytes (may be NULL when that is 0).  y must not alias x.
+ *   x and col_scale must be 16-byte aligned (segments are read as vectors).
  *   Errors: EINVAL, ENOSPC, ENOTSUP (unknown semiring), EHIP.
  */
 size_t spmv_bin_full_workspace_bytes(const b2sr_matrix *A, int semiring);

@@ -34,10 +34,11 @@ MASK_COMPLEMENT = 0x1
 OUT_COUNT = 0x2
 ACCUMULATE = 0x4
 SELF = 0x8
+SPARSE_X = 0x10
 PLUS_TIMES_F32, MIN_PLUS_F32, MIN_PLUS_U32, OR_U64 = 1, 2, 3, 4
 ALGO_BFS, ALGO_SSSP, ALGO_CC, ALGO_PAGERANK, ALGO_MSBFS = 1, 2, 3, 4, 5
 FLAGS = {"BUILD_LOWER": BUILD_LOWER, "MASK_COMPLEMENT": MASK_COMPLEMENT, "OUT_COUNT": OUT_COUNT,
-         "ACCUMULATE": ACCUMULATE, "SELF": SELF}
+         "ACCUMULATE": ACCUMULATE, "SELF": SELF, "SPARSE_X": SPARSE_X}
 SEMIRINGS = {"plus_times_f32": PLUS_TIMES_F32, "min_plus_f32": MIN_PLUS_F32, "min_plus_u32": MIN_PLUS_U32,
              "or_u64": OR_U64}
 UNREACHED = 0xFFFFFFFF
@@ -218,8 +219,10 @@ def b2sr_pack_bits(pred: torch.Tensor, out=None) -> torch.Tensor:
 
 # ---- products -------------------------------------------------------------------
 
-def spmv_bin_bin(A: B2SR, x, mask=None, complement=False, count=False, accumulate=False, out=None):
+def spmv_bin_bin(A: B2SR, x, mask=None, complement=False, count=False, accumulate=False, out=None,
+                 sparse_x=False):
     flags = (MASK_COMPLEMENT if complement else 0) | (OUT_COUNT if count else 0) | (ACCUMULATE if accumulate else 0)
+    flags |= SPARSE_X if sparse_x else 0
     if out is None:
         out = torch.empty(A.n if count else max(_words(A.n), 1), dtype=torch.int32, device="cuda")
     _check(lib().spmv_bin_bin(A.view, _ptr(x), _ptr(mask), flags, _ptr(out), _stream()), "spmv_bin_bin")

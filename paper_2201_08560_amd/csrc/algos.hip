@@ -56,15 +56,15 @@ __global__ void bfs_init_kernel(uint32_t n, uint32_t src, uint32_t *levels, uint
 }
 
 // Newly reached vertices (next is already masked by NOT visited) get this
-// level and join the visited set.
+// level and join the visited set; *flag_now receives how many there were.
 __global__ void bfs_update_kernel(uint32_t nw, const uint32_t *next, uint32_t *visited, uint32_t *levels,
                                   uint32_t level, uint32_t *flag_now, uint32_t *flag_next)
 {
-    bool any = false;
+    uint32_t found = 0;
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t nb = next[w];
         if (!nb) continue;
-        any = true;
+        found += __popc(nb);
         visited[w] |= nb;
         while (nb) {
             const uint32_t b = __builtin_ctz(nb);
@@ -72,7 +72,8 @@ __global__ void bfs_update_kernel(uint32_t nw, const uint32_t *next, uint32_t *v
             levels[w * 32 + b] = level;
         }
     }
-    if (__any(any) && lane_id() == 0) atomicOr(flag_now, 1u);
+    for (int d = 32; d >= 1; d >>= 1) found += shfl_xor(found, d);
+    if (lane_id() == 0 && found) atomicAdd(flag_now, found);
     if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
 }
 
@@ -118,7 +119,7 @@ __global__ void msbfs_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, 
             levels[(size_t)s * n + i] = level;
         }
     }
-    if (__any(any) && lane_id() == 0) atomicOr(flag_now, 1u);
+    if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(flag_now, 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
 }
 
@@ -136,7 +137,7 @@ __global__ void changed_kernel(uint32_t n, const V *a, const V *b, uint32_t *fla
     bool diff = false;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         diff |= a[i] != b[i];
-    if (__any(diff) && lane_id() == 0) atomicOr(flag_now, 1u);
+    if (__syncthreads_or(diff) && threadIdx.x == 0) atomicOr(flag_now, 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
 }
 
@@ -186,6 +187,9 @@ __global__ void pr_scale_kernel(uint32_t n, const float *r, const float *inv, fl
 }
 
 unsigned vgrid(uint64_t n) { return b2sr::grid_for(n, 256, 8192); }
+// Grids of the kernels that raise a convergence flag: at most 1024 blocks, so
+// at most 1024 atomics on the flag word.
+unsigned fgrid(uint64_t n) { return b2sr::grid_for(n, 256, 1024); }
 
 struct Layout {
     // BFS
@@ -271,16 +275,19 @@ int b2sr_bfs(const b2sr_matrix *A, uint32_t src, uint32_t *levels, void *ws, siz
     const uint32_t n = A->n, nw = b2sr::n_words(n);
     bfs_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, levels, L.frontier, L.visited, L.flags);
     if ((rc = b2sr::check_launch("bfs_init_kernel"))) return rc;
-    uint32_t level = 0;
+    // A frontier with fewer vertices than there are tile columns leaves most x
+    // segments empty: then tiles are read only behind a non-empty segment.
+    const uint32_t sparse_below = b2sr::n_tile_rows(n, A->tile);
+    uint32_t level = 0, frontier_size = 1;
     for (;;) {
         ++level;
-        if ((rc = spmv_bin_bin(A, L.frontier, L.visited, B2SR_MASK_COMPLEMENT, L.next, stream))) return rc;
+        const unsigned fl = B2SR_MASK_COMPLEMENT | (frontier_size < sparse_below ? B2SR_SPARSE_X : 0u);
+        if ((rc = spmv_bin_bin(A, L.frontier, L.visited, fl, L.next, stream))) return rc;
         uint32_t *fnow = L.flags + (level & 1), *fnext = L.flags + ((level + 1) & 1);
-        bfs_update_kernel<<<vgrid(nw), 256, 0, stream>>>(nw, L.next, L.visited, levels, level, fnow, fnext);
+        bfs_update_kernel<<<fgrid(nw), 256, 0, stream>>>(nw, L.next, L.visited, levels, level, fnow, fnext);
         if ((rc = b2sr::check_launch("bfs_update_kernel"))) return rc;
-        uint32_t any = 0;
-        if ((rc = read_flag(fnow, &any, stream))) return rc;
-        if (!any) break;
+        if ((rc = read_flag(fnow, &frontier_size, stream))) return rc;
+        if (!frontier_size) break;
         std::swap(L.frontier, L.next);
     }
     if (iters) *iters = level;
@@ -312,7 +319,7 @@ int b2sr_msbfs(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32
         if ((rc = spmv_bin_full(A, B2SR_OR_U64, L.F, nullptr, nullptr, 0, 0.0, 0.0, L.Y, nullptr, 0, stream)))
             return rc;
         uint32_t *fnow = L.flags + (level & 1), *fnext = L.flags + ((level + 1) & 1);
-        msbfs_update_kernel<<<vgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, levels, level, fnow, fnext);
+        msbfs_update_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, levels, level, fnow, fnext);
         if ((rc = b2sr::check_launch("msbfs_update_kernel"))) return rc;
         uint32_t any = 0;
         if ((rc = read_flag(fnow, &any, stream))) return rc;
@@ -340,7 +347,7 @@ int b2sr_sssp(const b2sr_matrix *A, uint32_t src, uint32_t *dist, void *ws, size
                                 stream)))
             return rc;
         uint32_t *fnow = L.flags + (it & 1), *fnext = L.flags + ((it + 1) & 1);
-        changed_kernel<float><<<vgrid(n), 256, 0, stream>>>(n, cur, nxt, fnow, fnext);
+        changed_kernel<float><<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, fnow, fnext);
         if ((rc = b2sr::check_launch("changed_kernel"))) return rc;
         uint32_t any = 0;
         if ((rc = read_flag(fnow, &any, stream))) return rc;
@@ -370,7 +377,7 @@ int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, u
                                 stream)))
             return rc;
         uint32_t *fnow = L.flags + (it & 1), *fnext = L.flags + ((it + 1) & 1);
-        changed_kernel<uint32_t><<<vgrid(n), 256, 0, stream>>>(n, cur, nxt, fnow, fnext);
+        changed_kernel<uint32_t><<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, fnow, fnext);
         if ((rc = b2sr::check_launch("changed_kernel"))) return rc;
         uint32_t any = 0;
         if ((rc = read_flag(fnow, &any, stream))) return rc;

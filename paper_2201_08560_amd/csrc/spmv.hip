@@ -5,12 +5,18 @@
 // waves with thousands of tiles, so here every wave takes a fixed CHUNK of
 // consecutive tiles instead, whatever rows they belong to:
 //   * a wave step covers TPW consecutive tiles; LPT lanes share a tile and each
-//     reads one 16/8/4-byte piece holding RPL bit-rows (TileShape), so the
-//     wave's loads are one contiguous run of tile bytes;
+//     reads one 16/8/4-byte piece holding RPL bit-rows (TileShape), so a step
+//     reads one contiguous run of tile bytes;
+//   * steps are grouped into blocks of U steps whose loads are all issued before
+//     any of them is used (U * 16 bytes of tile data in flight per lane for
+//     T = 32), together with the block's tile-column indices, one per lane;
+//   * full-precision vector segments (T values per tile, Sec. IV "efficient
+//     full-precision vector load") are read with coalesced vector loads and
+//     staged in LDS, so a set bit costs one LDS read instead of a dependent
+//     global gather;
 //   * the tile-row of the chunk's first tile comes from a 64-way search of
-//     TileRowPtr (3 rounds for 2^18 tile-rows);
-//   * when a whole step lies inside the current tile-row (the common case on
-//     long rows) each lane just folds its partial into a register accumulator;
+//     TileRowPtr; when a whole step lies inside the current tile-row each lane
+//     folds its partial into a register accumulator;
 //   * when a step crosses row ends, each lane finds its tile's row from the
 //     next 64 row pointers held one per lane, and a segmented scan over the
 //     wave combines partials of equal rows;
@@ -19,8 +25,9 @@
 //     chunk directly and park the partials of rows that straddle chunks in the
 //     workspace, where a second kernel adds them in chunk order, so every float
 //     result is deterministic.
-// Masks are applied when a row is stored (Sec. V, BFS), and tiles whose rows
-// are all masked out or whose vector segment is empty are not read.
+// Masks are applied when a row is stored (Sec. V, BFS).  Blocks whose rows are
+// all masked out are not read, and with B2SR_SPARSE_X tiles whose x segment is
+// empty are not read either.
 #include "common.h"
 
 using namespace b2sr_dev;
@@ -30,6 +37,11 @@ namespace {
 enum Kind : int { kBits = 0, kCount = 1, kPlusF32 = 2, kMinF32 = 3, kMinU32 = 4, kOr64 = 5 };
 
 template <int K> struct KindTraits;
+template <> struct KindTraits<kBits> {
+    using V = uint32_t;
+    static __device__ __forceinline__ V id() { return 0u; }
+    static __device__ __forceinline__ V op(V a, V b) { return a | b; }
+};
 template <> struct KindTraits<kCount> {
     using V = uint32_t;
     static __device__ __forceinline__ V id() { return 0u; }
@@ -72,11 +84,72 @@ struct SpmvArgs {
     float *ws_part;     // float sums: partials of straddling rows, 2*T per chunk
 };
 
-// Tiles per wave chunk.
-template <int T> constexpr uint32_t chunk_tiles() { return T == 32 ? 256u : (T == 16 ? 512u : 1024u); }
-inline uint32_t chunk_tiles_rt(uint32_t T)
+// Block shape per tile width and kind.  Bit and count products read the x
+// segment as T bits; the others stage T values per tile in LDS, 8 KiB per
+// wave.
+template <int T, int K> struct Cfg {
+    using S = TileShape<T>;
+    static constexpr int LPT = S::LPT, RPL = S::RPL, TPW = S::TPW;
+    static constexpr bool kStage = K >= kPlusF32;
+    static constexpr int VB = sizeof(typename KindTraits<K>::V);
+    static constexpr int U = kStage ? 8192 / (TPW * T * VB) : 8;
+    static constexpr int BT = U * TPW;                 // tiles per block
+    static constexpr int JK = BT >= 64 ? BT / 64 : 1;  // tile-column registers per lane
+    static constexpr int XW = T / LPT;                 // staged x values per lane per tile
+    static_assert(U >= 1 && (64 % TPW) == 0, "block shape");
+};
+
+// Tiles per wave chunk: whole blocks, aiming at about 32K waves per launch,
+// between 1 and 16 blocks.  A pure function of (T, kind, ntiles), so the
+// float-sum workspace query and the launch agree.
+template <int T, int K> inline uint32_t chunk_tiles(uint32_t ntiles)
 {
-    return T == 32 ? chunk_tiles<32>() : T == 16 ? chunk_tiles<16>() : T == 8 ? chunk_tiles<8>() : chunk_tiles<4>();
+    constexpr uint32_t bt = Cfg<T, K>::BT;
+    uint64_t nb = ((uint64_t)ntiles + 32768ull * bt - 1) / (32768ull * bt);
+    nb = nb < 1 ? 1 : (nb > 16 ? 16 : nb);
+    return (uint32_t)(bt * nb);
+}
+
+// One lane's raw piece of a tile.
+template <int T> struct PieceT { using type = u32x4; };
+template <> struct PieceT<8> { using type = u32x2; };
+template <> struct PieceT<4> { using type = uint32_t; };
+
+template <int T> __device__ __forceinline__ typename PieceT<T>::type load_piece(const void *bits, uint32_t t, uint32_t sub)
+{
+    if constexpr (T == 32) return __builtin_nontemporal_load((const u32x4 *)bits + ((size_t)t * 8 + sub));
+    else if constexpr (T == 16) return __builtin_nontemporal_load((const u32x4 *)bits + ((size_t)t * 2 + sub));
+    else if constexpr (T == 8) return __builtin_nontemporal_load((const u32x2 *)bits + t);
+    else return __builtin_nontemporal_load((const uint32_t *)bits + t);
+}
+
+template <int T> __device__ __forceinline__ typename PieceT<T>::type zero_piece()
+{
+    typename PieceT<T>::type z;
+    if constexpr (T == 4) z = 0u;
+    else z = 0u;  // splat
+    return z;
+}
+
+// The RPL bit-rows of a piece as T-bit values (Table II word layout).
+template <int T>
+__device__ __forceinline__ void piece_rows(const typename PieceT<T>::type &v, uint32_t (&a)[TileShape<T>::RPL])
+{
+    if constexpr (T == 32) {
+        a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+    } else if constexpr (T == 16) {
+        a[0] = v.x & 0xFFFFu; a[1] = v.x >> 16; a[2] = v.y & 0xFFFFu; a[3] = v.y >> 16;
+        a[4] = v.z & 0xFFFFu; a[5] = v.z >> 16; a[6] = v.w & 0xFFFFu; a[7] = v.w >> 16;
+    } else if constexpr (T == 8) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a[k] = (v.x >> (8 * k)) & 0xFFu;
+            a[4 + k] = (v.y >> (8 * k)) & 0xFFu;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = (v >> (8 * k)) & 0xFu;
+    }
 }
 
 // Tile-row holding tile t: the last r with trp[r] <= t (trp[ntr] > t).  A
@@ -135,137 +208,22 @@ template <int T> __device__ __forceinline__ uint32_t keep_bits(const uint32_t *m
     return (flags & B2SR_MASK_COMPLEMENT) ? (~w & full) : w;
 }
 
-// ---------------------------------------------------------------------------
-// Boolean product, bit output (bmv_bin_bin_bin[_masked])
-// ---------------------------------------------------------------------------
-
-// OR-test of this lane's bit-rows of tile t against x's segment, placed at the
-// rows' bit positions inside the tile-row.
-template <int T> __device__ __forceinline__ uint32_t bits_partial(const SpmvArgs &p, uint32_t t, uint32_t sub)
+__device__ __forceinline__ void wave_lds_sync()
 {
-    using S = TileShape<T>;
-    const uint32_t seg = bit_segment<T>((const uint32_t *)p.x, p.tci[t]);
-    if (!seg) return 0;  // frontier-empty segment: the tile cannot contribute
-    uint32_t a[S::RPL];
-    load_rows<T>(p.bits, t, sub, a);
-    uint32_t m = 0;
-#pragma unroll
-    for (int k = 0; k < S::RPL; ++k) m |= (uint32_t)((a[k] & seg) != 0) << (sub * S::RPL + k);
-    return m;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// ---------------------------------------------------------------------------
+// Row stores
+// ---------------------------------------------------------------------------
 
 template <int T> __device__ __forceinline__ void store_bits(const SpmvArgs &p, uint32_t I, uint32_t m)
 {
     if (!m) return;
     const uint32_t bit = I * T;
     atomicOr((uint32_t *)p.y + (bit >> 5), m << (bit & 31u));
-}
-
-__device__ __forceinline__ uint32_t wave_or(uint32_t v)
-{
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) v |= shfl_xor(v, d);
-    return v;
-}
-
-template <int T> __global__ void __launch_bounds__(256) spmv_bits_kernel(SpmvArgs p)
-{
-    using S = TileShape<T>;
-    const uint32_t lane = lane_id(), grp = lane / S::LPT, sub = lane % S::LPT;
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE;
-    if (wave * p.chunk >= p.ntiles) return;
-    const uint32_t t_begin = (uint32_t)(wave * p.chunk);
-    const uint32_t t_end = min(t_begin + p.chunk, p.ntiles);
-
-    uint32_t r_cur = find_row(p.trp, p.ntr, t_begin);
-    uint32_t r_end = p.trp[r_cur + 1];
-    uint32_t keep = keep_bits<T>(p.mask, p.flags, r_cur);
-    uint32_t acc = 0;
-    uint32_t base = t_begin;
-    while (base < t_end) {
-        const uint32_t last = min(base + S::TPW, t_end) - 1;
-        const bool valid = base + grp < t_end;
-        const uint32_t t = valid ? base + grp : t_end - 1;
-        if (last < r_end) {
-            if (!keep) {  // every row of this tile-row is masked out
-                base = min(r_end, t_end);
-                continue;
-            }
-            if (valid) acc |= bits_partial<T>(p, t, sub);
-            base += S::TPW;
-            continue;
-        }
-        // the step crosses the end of row r_cur
-        const uint32_t row = lane_row(p.trp, p.ntr, r_cur, t);
-        const uint32_t rkeep = row == r_cur ? keep : keep_bits<T>(p.mask, p.flags, row);
-        const uint32_t part = (valid && rkeep) ? bits_partial<T>(p, t, sub) : 0u;
-        const uint32_t acc_all = wave_or(acc);
-        uint32_t v = part;
-        if (readlane(row, 0) != r_cur) {
-            if (lane == 0) store_bits<T>(p, r_cur, acc_all & keep);
-        } else if (lane == 0) {
-            v |= acc_all;
-        }
-#pragma unroll
-        for (uint32_t d = 1; d < 64; d <<= 1) {
-            const uint32_t o = shfl_up(v, d), ro = shfl_up(row, d);
-            if (lane >= d && ro == row) v |= o;
-        }
-        const uint32_t r_last = readlane(row, 63);
-        const uint32_t next_row = shfl(row, (int)min(lane + 1, 63u));
-        if ((lane == 63 || next_row != row) && row != r_last) store_bits<T>(p, row, v & rkeep);
-        acc = row == r_last ? part : 0u;
-        r_cur = r_last;
-        r_end = p.trp[r_cur + 1];
-        keep = keep_bits<T>(p.mask, p.flags, r_cur);
-        base += S::TPW;
-    }
-    const uint32_t acc_all = wave_or(acc);
-    if (lane == 0) store_bits<T>(p, r_cur, acc_all & keep);
-}
-
-// ---------------------------------------------------------------------------
-// Value outputs: counts (bmv_bin_bin_full), and bmv_bin_full_full under
-// plus-times, min-plus and 64-wide OR
-// ---------------------------------------------------------------------------
-
-template <int T, int K>
-__device__ __forceinline__ void value_partial(const SpmvArgs &p, uint32_t t, uint32_t sub,
-                                              typename KindTraits<K>::V (&part)[TileShape<T>::RPL])
-{
-    using S = TileShape<T>;
-    using KT = KindTraits<K>;
-    const uint32_t J = p.tci[t];
-    uint32_t a[S::RPL];
-    if constexpr (K == kCount) {
-        const uint32_t seg = bit_segment<T>((const uint32_t *)p.x, J);
-        if (!seg) return;  // frontier-empty segment
-        load_rows<T>(p.bits, t, sub, a);
-#pragma unroll
-        for (int k = 0; k < S::RPL; ++k) part[k] = (uint32_t)__popc(a[k] & seg);  // Listing 1's dot product
-    } else {
-        load_rows<T>(p.bits, t, sub, a);
-        const size_t col0 = (size_t)J * T;
-#pragma unroll
-        for (int k = 0; k < S::RPL; ++k) {
-            uint32_t w = a[k];
-            while (w) {
-                const uint32_t c = __builtin_ctz(w);
-                w &= w - 1;
-                if constexpr (K == kPlusF32) {
-                    float xv = ((const float *)p.x)[col0 + c];
-                    if (p.s) xv *= p.s[col0 + c];
-                    part[k] += xv;
-                } else if constexpr (K == kMinF32) {
-                    part[k] = KT::op(part[k], ((const float *)p.x)[col0 + c]);
-                } else if constexpr (K == kMinU32) {
-                    part[k] = KT::op(part[k], ((const uint32_t *)p.x)[col0 + c]);
-                } else {
-                    part[k] |= ((const uint64_t *)p.x)[col0 + c];
-                }
-            }
-        }
-    }
 }
 
 // Stores the RPL rows [sub*RPL, sub*RPL + RPL) of tile-row I.
@@ -303,13 +261,23 @@ __device__ __forceinline__ void store_values(const SpmvArgs &p, uint32_t I, uint
     }
 }
 
-template <int T, int K> __global__ void __launch_bounds__(256) spmv_values_kernel(SpmvArgs p)
+// ---------------------------------------------------------------------------
+// The product kernel, one template for every kind
+// ---------------------------------------------------------------------------
+
+template <int T, int K> __global__ void __launch_bounds__(256) spmv_kernel(SpmvArgs p)
 {
-    using S = TileShape<T>;
+    using C = Cfg<T, K>;
     using KT = KindTraits<K>;
     using V = typename KT::V;
-    constexpr int RPL = S::RPL, LPT = S::LPT, TPW = S::TPW;
+    using Piece = typename PieceT<T>::type;
+    constexpr int LPT = C::LPT, RPL = C::RPL, TPW = C::TPW, U = C::U, BT = C::BT, JK = C::JK, XW = C::XW;
+    // Partials of one lane: a bit mask for kBits, RPL values otherwise.
+    constexpr int NV = K == kBits ? 1 : RPL;
+    __shared__ __align__(16) V s_x[C::kStage ? 4 * BT * T : 1];
+
     const uint32_t lane = lane_id(), grp = lane / LPT, sub = lane % LPT;
+    V *xs = s_x + (C::kStage ? (threadIdx.x / B2SR_WAVE) * BT * T : 0);
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE;
     if (wave * p.chunk >= p.ntiles) return;
     const uint32_t chunk_id = (uint32_t)wave;
@@ -323,107 +291,265 @@ template <int T, int K> __global__ void __launch_bounds__(256) spmv_values_kerne
     // A row straddles chunks when it starts before t_begin or ends after t_end;
     // only the chunk's first and last rows can.
     auto straddles = [&](uint32_t I) { return p.trp[I] < t_begin || p.trp[I + 1] > t_end; };
+    auto slot_of = [&](uint32_t I) { return I == r_first ? 0u : 1u; };
 
-    V acc[RPL];
+    V acc[NV];
 #pragma unroll
-    for (int k = 0; k < RPL; ++k) acc[k] = KT::id();
-    uint32_t base = t_begin;
-    while (base < t_end) {
-        const uint32_t last = min(base + TPW, t_end) - 1;
-        const bool valid = base + grp < t_end;
-        const uint32_t t = valid ? base + grp : t_end - 1;
-        if (last < r_end) {
-            if (!keep && K != kPlusF32) {  // all rows masked out (float sums still park partials)
-                base = min(r_end, t_end);
-                continue;
-            }
-            if (valid) {
-                V part[RPL];
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) part[k] = KT::id();
-                value_partial<T, K>(p, t, sub, part);
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) acc[k] = KT::op(acc[k], part[k]);
-            }
-            base += TPW;
+    for (int k = 0; k < NV; ++k) acc[k] = KT::id();
+
+    uint32_t blk = t_begin;
+    while (blk < t_end) {
+        if (min(blk + BT, t_end) - 1 < r_end && !keep) {  // the block lies in a row masked out entirely
+            blk = min(r_end, t_end);
             continue;
         }
-        const uint32_t row = lane_row(p.trp, p.ntr, r_cur, t);
-        const uint32_t rkeep = row == r_cur ? keep : keep_bits<T>(p.mask, p.flags, row);
-        V part[RPL], v[RPL], tot[RPL];
+        // ---- load phase: tile pieces, tile columns, x segments
+        uint32_t Jr[JK];
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) part[k] = KT::id();
-        if (valid && (rkeep || K == kPlusF32)) value_partial<T, K>(p, t, sub, part);
-        // total of the running accumulator over the groups (rows by sub)
+        for (int k = 0; k < JK; ++k) {
+            const uint32_t tk = blk + 64 * k + lane;
+            Jr[k] = tk < t_end ? p.tci[tk] : 0u;
+        }
+        Piece pc[U];
+        uint32_t seg[U];
+        if constexpr (!C::kStage) {
+            if (p.flags & B2SR_SPARSE_X) {
+                // read a tile only when its x segment has a set bit
+                uint32_t Sr[JK];
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) {
+                for (int k = 0; k < JK; ++k)
+                    Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>((const uint32_t *)p.x, Jr[k]) : 0u;
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    const uint32_t ti = i * TPW + grp;
+                    seg[i] = shfl(Sr[(i * TPW) / 64], (int)(ti % 64));
+                    pc[i] = (blk + ti < t_end && seg[i]) ? load_piece<T>(p.bits, blk + ti, sub) : zero_piece<T>();
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    const uint32_t t = blk + i * TPW + grp;
+                    pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
+                }
+                uint32_t Sr[JK];
+#pragma unroll
+                for (int k = 0; k < JK; ++k)
+                    Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>((const uint32_t *)p.x, Jr[k]) : 0u;
+#pragma unroll
+                for (int i = 0; i < U; ++i) seg[i] = shfl(Sr[(i * TPW) / 64], (int)((i * TPW + grp) % 64));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                const uint32_t t = blk + i * TPW + grp;
+                pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
+            }
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                const uint32_t ti = i * TPW + grp;
+                const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
+                if (blk + ti >= t_end) continue;
+                const size_t c0 = (size_t)J * T + sub * XW;
+                V *dst = xs + ti * T + sub * XW;
+                if (c0 + XW <= p.n) {
+                    // XW values = XW * VB bytes, aligned to 16 bytes
+                    const u32x4 *src = (const u32x4 *)((const V *)p.x + c0);
+                    constexpr int NQ = XW * C::VB / 16;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        u32x4 v = src[q];
+                        if constexpr (K == kPlusF32) {
+                            if (p.s) {
+                                const u32x4 sv = ((const u32x4 *)(p.s + c0))[q];
+                                v.x = __float_as_uint(__uint_as_float(v.x) * __uint_as_float(sv.x));
+                                v.y = __float_as_uint(__uint_as_float(v.y) * __uint_as_float(sv.y));
+                                v.z = __float_as_uint(__uint_as_float(v.z) * __uint_as_float(sv.z));
+                                v.w = __float_as_uint(__uint_as_float(v.w) * __uint_as_float(sv.w));
+                            }
+                        }
+                        ((u32x4 *)dst)[q] = v;
+                    }
+                } else {
+                    // the last, partial tile column: values past n are never selected
+                    for (int q = 0; q < XW; ++q) {
+                        V v = KT::id();
+                        if (c0 + q < p.n) {
+                            v = ((const V *)p.x)[c0 + q];
+                            if constexpr (K == kPlusF32) {
+                                if (p.s) v *= p.s[c0 + q];
+                            }
+                        }
+                        dst[q] = v;
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+
+        // ---- compute phase, one step at a time
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const uint32_t base = blk + i * TPW;
+            if (base >= t_end) break;
+            const uint32_t last = min(base + TPW, t_end) - 1;
+            const bool valid = base + grp < t_end;
+            const uint32_t t = valid ? base + grp : t_end - 1;
+            const uint32_t ti = i * TPW + grp;
+            V part[NV];
+            auto compute = [&]() {
+                uint32_t a[RPL];
+                piece_rows<T>(pc[i], a);
+                if constexpr (K == kBits) {
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) m |= (uint32_t)((a[k] & seg[i]) != 0) << (sub * RPL + k);
+                    part[0] = m;
+                } else if constexpr (K == kCount) {
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) part[k] = (uint32_t)__popc(a[k] & seg[i]);  // Listing 1's dot
+                } else {
+                    const V *xt = xs + ti * T;
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        V v = KT::id();
+                        uint32_t w = a[k];
+                        while (w) {
+                            const uint32_t c = __builtin_ctz(w);
+                            w &= w - 1;
+                            v = KT::op(v, xt[c]);
+                        }
+                        part[k] = v;
+                    }
+                }
+            };
+            if (last < r_end) {
+                compute();
+#pragma unroll
+                for (int k = 0; k < NV; ++k) acc[k] = KT::op(acc[k], part[k]);
+                continue;
+            }
+            // the step crosses the end of row r_cur
+            const uint32_t row = lane_row(p.trp, p.ntr, r_cur, t);
+            const uint32_t rkeep = row == r_cur ? keep : keep_bits<T>(p.mask, p.flags, row);
+            if (valid && rkeep) compute();
+            else {
+#pragma unroll
+                for (int k = 0; k < NV; ++k) part[k] = KT::id();
+            }
+            const uint32_t r_last = readlane(row, 63);
+            const bool first_in_cur = readlane(row, 0) == r_cur;
+            if constexpr (K == kBits) {
+                uint32_t acc_all = acc[0];
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) acc_all |= shfl_xor(acc_all, d);
+                uint32_t v = part[0];
+                if (!first_in_cur) {
+                    if (lane == 0) store_bits<T>(p, r_cur, acc_all & keep);
+                } else if (lane == 0) {
+                    v |= acc_all;
+                }
+#pragma unroll
+                for (uint32_t d = 1; d < 64; d <<= 1) {
+                    const uint32_t o = shfl_up(v, d), ro = shfl_up(row, d);
+                    if (lane >= d && ro == row) v |= o;
+                }
+                const uint32_t next_row = shfl(row, (int)min(lane + 1, 63u));
+                if ((lane == 63 || next_row != row) && row != r_last) store_bits<T>(p, row, v & rkeep);
+                acc[0] = row == r_last ? part[0] : 0u;
+            } else {
+                V v[NV], tot[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    tot[k] = acc[k];
+#pragma unroll
+                    for (int d = LPT; d < 64; d <<= 1) tot[k] = KT::op(tot[k], shfl_xor(tot[k], d));
+                    v[k] = part[k];
+                }
+                if (!first_in_cur) {
+                    if (grp == 0) store_values<T, K>(p, r_cur, sub, keep, tot, straddles(r_cur), chunk_id, slot_of(r_cur));
+                } else if (grp == 0) {
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) v[k] = KT::op(tot[k], part[k]);
+                }
+                // segmented inclusive scan over groups, keyed by row
+#pragma unroll
+                for (int d = 1; d < TPW; d <<= 1) {
+                    const uint32_t ro = shfl_up(row, d * LPT);
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) {
+                        const V o = shfl_up(v[k], d * LPT);
+                        if (grp >= (uint32_t)d && ro == row) v[k] = KT::op(v[k], o);
+                    }
+                }
+                const uint32_t next_row = shfl(row, (int)min(lane + LPT, 63u));
+                if ((grp == TPW - 1 || next_row != row) && row != r_last)
+                    store_values<T, K>(p, row, sub, rkeep, v, straddles(row), chunk_id, slot_of(row));
+#pragma unroll
+                for (int k = 0; k < NV; ++k) acc[k] = row == r_last ? part[k] : KT::id();
+            }
+            r_cur = r_last;
+            r_end = p.trp[r_cur + 1];
+            keep = keep_bits<T>(p.mask, p.flags, r_cur);
+        }
+        blk += BT;
+        if constexpr (C::kStage) wave_lds_sync();  // the next block's LDS writes follow this block's reads
+    }
+    // flush the row the chunk ends in
+    if constexpr (K == kBits) {
+        uint32_t acc_all = acc[0];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) acc_all |= shfl_xor(acc_all, d);
+        if (lane == 0) store_bits<T>(p, r_cur, acc_all & keep);
+    } else {
+        V tot[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
             tot[k] = acc[k];
 #pragma unroll
             for (int d = LPT; d < 64; d <<= 1) tot[k] = KT::op(tot[k], shfl_xor(tot[k], d));
-            v[k] = part[k];
         }
-        if (readlane(row, 0) != r_cur) {
-            if (grp == 0) store_values<T, K>(p, r_cur, sub, keep, tot, straddles(r_cur), chunk_id, r_cur == r_first ? 0 : 1);
-        } else if (grp == 0) {
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) v[k] = KT::op(tot[k], part[k]);
-        }
-        // segmented inclusive scan over groups, keyed by row
-#pragma unroll
-        for (int d = 1; d < TPW; d <<= 1) {
-            const uint32_t ro = shfl_up(row, d * LPT);
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) {
-                const V o = shfl_up(v[k], d * LPT);
-                if (grp >= (uint32_t)d && ro == row) v[k] = KT::op(v[k], o);
+        if (grp == 0) store_values<T, K>(p, r_cur, sub, keep, tot, straddles(r_cur), chunk_id, slot_of(r_cur));
+        if constexpr (K == kPlusF32) {
+            if (lane == 0) {
+                p.ws_rows[2 * chunk_id] = r_first;
+                p.ws_rows[2 * chunk_id + 1] = r_cur;
             }
-        }
-        const uint32_t r_last = readlane(row, 63);
-        const uint32_t next_row = shfl(row, (int)min(lane + LPT, 63u));
-        if ((grp == TPW - 1 || next_row != row) && row != r_last)
-            store_values<T, K>(p, row, sub, rkeep, v, straddles(row), chunk_id, row == r_first ? 0 : 1);
-#pragma unroll
-        for (int k = 0; k < RPL; ++k) acc[k] = row == r_last ? part[k] : KT::id();
-        r_cur = r_last;
-        r_end = p.trp[r_cur + 1];
-        keep = keep_bits<T>(p.mask, p.flags, r_cur);
-        base += TPW;
-    }
-    V tot[RPL];
-#pragma unroll
-    for (int k = 0; k < RPL; ++k) {
-        tot[k] = acc[k];
-#pragma unroll
-        for (int d = LPT; d < 64; d <<= 1) tot[k] = KT::op(tot[k], shfl_xor(tot[k], d));
-    }
-    if (grp == 0) store_values<T, K>(p, r_cur, sub, keep, tot, straddles(r_cur), chunk_id, r_cur == r_first ? 0 : 1);
-    if constexpr (K == kPlusF32) {
-        if (lane == 0) {
-            p.ws_rows[2 * chunk_id] = r_first;
-            p.ws_rows[2 * chunk_id + 1] = r_cur;
         }
     }
 }
 
-// Float sums of rows that straddle chunks: the chunk where such a row starts
-// adds its own partial and those of the following chunks, in chunk order.
+// Float sums of rows that straddle chunks.  Lane l of a wave checks chunk
+// 64*w + l; for every chunk where its last row starts and continues into the
+// next chunk, the wave adds that row's partials over the chunks it spans, in
+// chunk order.
 template <int T> __global__ void __launch_bounds__(256) plus_fixup_kernel(SpmvArgs p, uint32_t nchunks)
 {
-    const uint64_t c64 = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE;
-    if (c64 >= nchunks) return;
-    const uint32_t c = (uint32_t)c64, lane = lane_id();
-    const uint32_t t_begin = c * p.chunk, t_end = min(t_begin + p.chunk, p.ntiles);
-    const uint32_t r_first = p.ws_rows[2 * c], R = p.ws_rows[2 * c + 1];
-    if (p.trp[R + 1] <= t_end || p.trp[R] < t_begin) return;  // R does not start here or ends here
-    if (lane >= (uint32_t)T) return;
-    float sum = p.ws_part[((size_t)c * 2 + (R == r_first ? 0 : 1)) * T + lane];
-    for (uint32_t c2 = c + 1; c2 < nchunks && p.ws_rows[2 * c2] == R; ++c2)
-        sum += p.ws_part[(size_t)c2 * 2 * T + lane];
-    const uint32_t row = R * T + lane;
-    if (row >= p.n || !((keep_bits<T>(p.mask, p.flags, R) >> lane) & 1u)) return;
-    float *y = (float *)p.y + row;
-    if (p.flags & B2SR_ACCUMULATE) *y = *y + p.alpha * sum;
-    else *y = p.alpha * sum + p.beta;
+    const uint32_t lane = lane_id();
+    const uint64_t c64 = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64 + lane;
+    bool owner = false;
+    uint32_t c = 0, r_first = 0, R = 0;
+    if (c64 < nchunks) {
+        c = (uint32_t)c64;
+        const uint32_t t_begin = c * p.chunk, t_end = min(t_begin + p.chunk, p.ntiles);
+        r_first = p.ws_rows[2 * c];
+        R = p.ws_rows[2 * c + 1];
+        owner = p.trp[R + 1] > t_end && p.trp[R] >= t_begin;
+    }
+    uint64_t todo = __ballot(owner);
+    while (todo) {
+        const int src = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const uint32_t cc = readlane(c, src), RR = readlane(R, src), rf = readlane(r_first, src);
+        if (lane >= (uint32_t)T) continue;
+        float sum = p.ws_part[((size_t)cc * 2 + (RR == rf ? 0 : 1)) * T + lane];
+        for (uint32_t c2 = cc + 1; c2 < nchunks && p.ws_rows[2 * c2] == RR; ++c2)
+            sum += p.ws_part[(size_t)c2 * 2 * T + lane];
+        const uint32_t row = RR * T + lane;
+        if (row >= p.n || !((keep_bits<T>(p.mask, p.flags, RR) >> lane) & 1u)) continue;
+        float *y = (float *)p.y + row;
+        if (p.flags & B2SR_ACCUMULATE) *y = *y + p.alpha * sum;
+        else *y = p.alpha * sum + p.beta;
+    }
 }
 
 // Output initialisation: identity (or the diagonal term under SELF) for every
@@ -453,39 +579,42 @@ template <int K> __global__ void init_values_kernel(SpmvArgs p)
     }
 }
 
-template <int T, int K> int launch_values(SpmvArgs p, hipStream_t stream)
+__global__ void zero_words_kernel(uint32_t *__restrict__ y, uint32_t nwords)
 {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) y[i] = 0;
+}
+
+template <int T, int K> int launch(SpmvArgs p, hipStream_t stream)
+{
+    p.chunk = chunk_tiles<T, K>(p.ntiles);
     const uint32_t nchunks = (uint32_t)((p.ntiles + (uint64_t)p.chunk - 1) / p.chunk);
-    if (p.n) {
-        init_values_kernel<K><<<b2sr::grid_for(p.n, 256, 65536), 256, 0, stream>>>(p);
-        if (int rc = b2sr::check_launch("init_values_kernel")) return rc;
+    if (!(p.flags & B2SR_ACCUMULATE) || K >= kPlusF32) {
+        if constexpr (K == kBits) {
+            const uint32_t nw = b2sr::n_words(p.n);
+            zero_words_kernel<<<b2sr::grid_for(nw, 256, 4096), 256, 0, stream>>>((uint32_t *)p.y, nw);
+        } else {
+            init_values_kernel<K><<<b2sr::grid_for(p.n, 256, 8192), 256, 0, stream>>>(p);
+        }
+        if (int rc = b2sr::check_launch("init kernel")) return rc;
     }
     if (nchunks == 0) return B2SR_OK;
-    spmv_values_kernel<T, K><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
-    if (int rc = b2sr::check_launch("spmv_values_kernel")) return rc;
+    spmv_kernel<T, K><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
+    if (int rc = b2sr::check_launch("spmv_kernel")) return rc;
     if constexpr (K == kPlusF32) {
-        plus_fixup_kernel<T><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p, nchunks);
+        plus_fixup_kernel<T><<<b2sr::grid_for(nchunks, 256), 256, 0, stream>>>(p, nchunks);
         if (int rc = b2sr::check_launch("plus_fixup_kernel")) return rc;
     }
     return B2SR_OK;
 }
 
-template <int K> int dispatch_values(uint32_t T, const SpmvArgs &p, hipStream_t s)
+template <int K> int dispatch(uint32_t T, const SpmvArgs &p, hipStream_t s)
 {
     switch (T) {
-    case 4: return launch_values<4, K>(p, s);
-    case 8: return launch_values<8, K>(p, s);
-    case 16: return launch_values<16, K>(p, s);
-    default: return launch_values<32, K>(p, s);
+    case 4: return launch<4, K>(p, s);
+    case 8: return launch<8, K>(p, s);
+    case 16: return launch<16, K>(p, s);
+    default: return launch<32, K>(p, s);
     }
-}
-
-template <int T> int launch_bits(const SpmvArgs &p, hipStream_t stream)
-{
-    const uint32_t nchunks = (uint32_t)((p.ntiles + (uint64_t)p.chunk - 1) / p.chunk);
-    if (nchunks == 0) return B2SR_OK;
-    spmv_bits_kernel<T><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
-    return b2sr::check_launch("spmv_bits_kernel");
 }
 
 SpmvArgs make_args(const b2sr_matrix *A)
@@ -497,15 +626,20 @@ SpmvArgs make_args(const b2sr_matrix *A)
     p.n = A->n;
     p.ntr = b2sr::n_tile_rows(A->n, A->tile);
     p.ntiles = A->ntiles;
-    p.chunk = chunk_tiles_rt(A->tile);
     return p;
 }
 
-}  // namespace
-
-namespace b2sr {
-int fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
+uint32_t plus_chunk(uint32_t T, uint32_t ntiles)
+{
+    switch (T) {
+    case 4: return chunk_tiles<4, kPlusF32>(ntiles);
+    case 8: return chunk_tiles<8, kPlusF32>(ntiles);
+    case 16: return chunk_tiles<16, kPlusF32>(ntiles);
+    default: return chunk_tiles<32, kPlusF32>(ntiles);
+    }
 }
+
+}  // namespace
 
 extern "C" {
 
@@ -514,7 +648,7 @@ int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, 
 {
     int rc = b2sr::validate_matrix(A);
     if (rc) return rc;
-    if (flags & ~(B2SR_MASK_COMPLEMENT | B2SR_OUT_COUNT | B2SR_ACCUMULATE)) return B2SR_EINVAL;
+    if (flags & ~(B2SR_MASK_COMPLEMENT | B2SR_OUT_COUNT | B2SR_ACCUMULATE | B2SR_SPARSE_X)) return B2SR_EINVAL;
     if (A->n > 0 && (!x || !y)) return B2SR_EINVAL;
     if (A->n == 0) return B2SR_OK;
     if ((const void *)x == y || (const void *)mask == y) return B2SR_EINVAL;
@@ -523,24 +657,15 @@ int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, 
     p.mask = mask;
     p.flags = flags;
     p.y = y;
-    if (flags & B2SR_OUT_COUNT) {
-        if (!(flags & B2SR_ACCUMULATE) && (rc = b2sr::fill_u32((uint32_t *)y, A->n, 0, stream))) return rc;
-        return dispatch_values<kCount>(A->tile, p, stream);
-    }
-    if (!(flags & B2SR_ACCUMULATE) && (rc = b2sr::fill_u32((uint32_t *)y, b2sr::n_words(A->n), 0, stream)))
-        return rc;
-    switch (A->tile) {
-    case 4: return launch_bits<4>(p, stream);
-    case 8: return launch_bits<8>(p, stream);
-    case 16: return launch_bits<16>(p, stream);
-    default: return launch_bits<32>(p, stream);
-    }
+    if (flags & B2SR_OUT_COUNT) return dispatch<kCount>(A->tile, p, stream);
+    return dispatch<kBits>(A->tile, p, stream);
 }
 
 size_t spmv_bin_full_workspace_bytes(const b2sr_matrix *A, int semiring)
 {
     if (!A || !b2sr::valid_tile(A->tile) || semiring != B2SR_PLUS_TIMES_F32) return 0;
-    const uint64_t nchunks = ((uint64_t)A->ntiles + chunk_tiles_rt(A->tile) - 1) / chunk_tiles_rt(A->tile);
+    const uint32_t chunk = plus_chunk(A->tile, A->ntiles);
+    const uint64_t nchunks = ((uint64_t)A->ntiles + chunk - 1) / chunk;
     const uint64_t rows_bytes = (nchunks * 2 * 4 + 255) & ~255ull;
     return (size_t)(rows_bytes + nchunks * 2 * A->tile * 4);
 }
@@ -560,6 +685,8 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
     if (A->n > 0 && (!x || !y)) return B2SR_EINVAL;
     if (A->n == 0) return B2SR_OK;
     if (x == y) return B2SR_EINVAL;
+    // x segments are read as 16-byte vectors
+    if (((uintptr_t)x & 15) || ((uintptr_t)col_scale & 15)) return B2SR_EINVAL;
     const size_t need = spmv_bin_full_workspace_bytes(A, semiring);
     if (ws_bytes < need || (need && !ws)) return B2SR_ENOSPC;
     SpmvArgs p = make_args(A);
@@ -572,15 +699,16 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
     p.w_u32 = semiring == B2SR_MIN_PLUS_U32 ? (uint32_t)alpha : 0u;
     p.y = y;
     if (need) {
-        const uint64_t nchunks = ((uint64_t)A->ntiles + p.chunk - 1) / p.chunk;
+        const uint64_t nchunks = ((uint64_t)A->ntiles + plus_chunk(A->tile, A->ntiles) - 1) /
+                                 plus_chunk(A->tile, A->ntiles);
         p.ws_rows = (uint32_t *)ws;
         p.ws_part = (float *)((char *)ws + ((nchunks * 2 * 4 + 255) & ~255ull));
     }
     switch (semiring) {
-    case B2SR_PLUS_TIMES_F32: return dispatch_values<kPlusF32>(A->tile, p, stream);
-    case B2SR_MIN_PLUS_F32: return dispatch_values<kMinF32>(A->tile, p, stream);
-    case B2SR_MIN_PLUS_U32: return dispatch_values<kMinU32>(A->tile, p, stream);
-    default: return dispatch_values<kOr64>(A->tile, p, stream);
+    case B2SR_PLUS_TIMES_F32: return dispatch<kPlusF32>(A->tile, p, stream);
+    case B2SR_MIN_PLUS_F32: return dispatch<kMinF32>(A->tile, p, stream);
+    case B2SR_MIN_PLUS_U32: return dispatch<kMinU32>(A->tile, p, stream);
+    default: return dispatch<kOr64>(A->tile, p, stream);
     }
 }
 

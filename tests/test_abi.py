@@ -53,6 +53,7 @@ def test_spmv_argument_errors():
     assert L.spmv_bin_bin(A, None, None, 0, y, None) == -1                 # x NULL
     assert L.spmv_bin_bin(A, x, None, 0, None, None) == -1                 # y NULL
     assert L.spmv_bin_bin(A, x, None, 0x100, y, None) == -1                # unknown flag
+    assert L.spmv_bin_full(A, 1, ctypes.c_void_p(FAKE + 4), None, None, 0, 1.0, 0.0, y, None, 0, None) == -1  # x misaligned
     assert L.spmv_bin_bin(A, x, None, 0, x, None) == -1                    # y aliases x
     assert L.spmv_bin_full(A, 9, x, None, None, 0, 1.0, 0.0, y, None, 0, None) == -5   # unknown semiring
     assert L.spmv_bin_full(A, 1, x, None, None, b2.SELF, 1.0, 0.0, y, None, 0, None) == -1  # SELF on plus

@@ -108,14 +108,18 @@ def test_spmv_bin_bin(gi, T):
         if density == 0.002 and g.n:
             x[0] = True
         xd = dev_u32(pack_bits(x))
-        for mask, comp in masks_for(g.n, gi + T):
-            print(f"spmv_bin_bin {g.name} T={T} density={density} mask={mask is not None} comp={comp}", flush=True)
+        for (mask, comp), sparse in zip(masks_for(g.n, gi + T), (False, True, False, True)):
+            print(f"spmv_bin_bin {g.name} T={T} density={density} mask={mask is not None} comp={comp} "
+                  f"sparse={sparse}", flush=True)
             md = None if mask is None else dev_u32(pack_bits(mask))
-            yb = b2.as_u32(b2.spmv_bin_bin(A, xd, md, comp))
-            assert padding_zero(yb, g.n)
-            assert np.array_equal(unpack_bits(yb, g.n), orc.spmv_or(g, x, mask, comp))
-            yc = b2.as_u32(b2.spmv_bin_bin(A, xd, md, comp, count=True))
-            assert np.array_equal(yc, orc.spmv_count(g, x, mask, comp))
+            ref = orc.spmv_or(g, x, mask, comp)
+            refc = orc.spmv_count(g, x, mask, comp)
+            for sp in (sparse, not sparse):
+                yb = b2.as_u32(b2.spmv_bin_bin(A, xd, md, comp, sparse_x=sp))
+                assert padding_zero(yb, g.n)
+                assert np.array_equal(unpack_bits(yb, g.n), ref)
+                yc = b2.as_u32(b2.spmv_bin_bin(A, xd, md, comp, count=True, sparse_x=sp))
+                assert np.array_equal(yc, refc)
     # accumulate: y |= A x (bits), y += A x (counts); masked rows keep their old value
     x = r.random(g.n) < 0.2
     mask = r.random(g.n) < 0.6
