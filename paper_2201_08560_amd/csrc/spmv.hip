@@ -348,15 +348,26 @@ template <int T, int K> __global__ void __launch_bounds__(256) spmv_kernel(SpmvA
             for (int i = 0; i < U; ++i) {
                 const uint32_t ti = i * TPW + grp;
                 const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
+                // columns of the tile that hold a set bit: OR of its bit-rows over the tile's lanes
+                uint32_t a[RPL];
+                piece_rows<T>(pc[i], a);
+                uint32_t cols = 0;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) cols |= a[k];
+#pragma unroll
+                for (int d = 1; d < LPT; d <<= 1) cols |= shfl_xor(cols, d);
                 if (blk + ti >= t_end) continue;
                 const size_t c0 = (size_t)J * T + sub * XW;
                 V *dst = xs + ti * T + sub * XW;
+                constexpr int QV = 16 / C::VB;  // values per 16-byte quad
+                constexpr int NQ = XW / QV;
                 if (c0 + XW <= p.n) {
-                    // XW values = XW * VB bytes, aligned to 16 bytes
                     const u32x4 *src = (const u32x4 *)((const V *)p.x + c0);
-                    constexpr int NQ = XW * C::VB / 16;
 #pragma unroll
                     for (int q = 0; q < NQ; ++q) {
+                        // read only the quads whose columns are used by some bit-row
+                        const uint32_t qmask = ((1u << QV) - 1u) << (sub * XW + q * QV);
+                        if (!(cols & qmask)) continue;
                         u32x4 v = src[q];
                         if constexpr (K == kPlusF32) {
                             if (p.s) {
@@ -541,9 +552,12 @@ template <int T> __global__ void __launch_bounds__(256) plus_fixup_kernel(SpmvAr
         todo &= todo - 1;
         const uint32_t cc = readlane(c, src), RR = readlane(R, src), rf = readlane(r_first, src);
         if (lane >= (uint32_t)T) continue;
+        // the row's later partials sit in the head slots of chunks cc+1 .. c_last;
+        // their addresses are known up front, so the loads overlap
+        const uint32_t c_last = (p.trp[RR + 1] - 1) / p.chunk;
         float sum = p.ws_part[((size_t)cc * 2 + (RR == rf ? 0 : 1)) * T + lane];
-        for (uint32_t c2 = cc + 1; c2 < nchunks && p.ws_rows[2 * c2] == RR; ++c2)
-            sum += p.ws_part[(size_t)c2 * 2 * T + lane];
+#pragma unroll 8
+        for (uint32_t c2 = cc + 1; c2 <= c_last; ++c2) sum += p.ws_part[(size_t)c2 * 2 * T + lane];
         const uint32_t row = RR * T + lane;
         if (row >= p.n || !((keep_bits<T>(p.mask, p.flags, RR) >> lane) & 1u)) continue;
         float *y = (float *)p.y + row;
