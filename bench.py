@@ -246,19 +246,25 @@ def verify(w: Workload) -> dict:
 
 
 def profile_mode(args):
-    """A short fixed program for rocprofv3 counter runs: a 1 GiB device copy
-    (the scale for FETCH_SIZE / WRITE_SIZE) and a few headline SpMV launches."""
+    """A short fixed program for rocprofv3 counter runs: a 1 GiB device-to-device
+    copy (the known-size reference for FETCH_SIZE / WRITE_SIZE), then --steps
+    launches each of the headline masked bin x bin SpMV and of the plus-times
+    bin x full SpMV on the R-MAT s20 B2SR-32 workload."""
     g = gg.rmat(20, 16, seed=20)
     w = Workload(g, 32)
-    src = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
+    torch.cuda.synchronize()
     for _ in range(args.steps):
         w.y_bits.zero_()
         b2.spmv_bin_bin(w.A, w.x_full, w.mask, complement=True, accumulate=True, out=w.y_bits)
+    for _ in range(args.steps):
+        b2.spmv_bin_full(w.A, b2.PLUS_TIMES_F32, w.xf, out=w.y_f, ws=w.ws_plus)
     torch.cuda.synchronize()
-    log(json.dumps({"profile_mode": True, "spmv_bytes": spmv_bytes(w.A, True), "copy_bytes": 2 * src.numel() * 4,
+    log(json.dumps({"profile_mode": True, "spmv_bits_alg_bytes": spmv_bytes(w.A, True),
+                    "copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
                     "kernel_source_digest": source_digest()}))
 
 

@@ -348,14 +348,6 @@ template <int T, int K> __global__ void __launch_bounds__(256) spmv_kernel(SpmvA
             for (int i = 0; i < U; ++i) {
                 const uint32_t ti = i * TPW + grp;
                 const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
-                // columns of the tile that hold a set bit: OR of its bit-rows over the tile's lanes
-                uint32_t a[RPL];
-                piece_rows<T>(pc[i], a);
-                uint32_t cols = 0;
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) cols |= a[k];
-#pragma unroll
-                for (int d = 1; d < LPT; d <<= 1) cols |= shfl_xor(cols, d);
                 if (blk + ti >= t_end) continue;
                 const size_t c0 = (size_t)J * T + sub * XW;
                 V *dst = xs + ti * T + sub * XW;
@@ -365,9 +357,6 @@ template <int T, int K> __global__ void __launch_bounds__(256) spmv_kernel(SpmvA
                     const u32x4 *src = (const u32x4 *)((const V *)p.x + c0);
 #pragma unroll
                     for (int q = 0; q < NQ; ++q) {
-                        // read only the quads whose columns are used by some bit-row
-                        const uint32_t qmask = ((1u << QV) - 1u) << (sub * XW + q * QV);
-                        if (!(cols & qmask)) continue;
                         u32x4 v = src[q];
                         if constexpr (K == kPlusF32) {
                             if (p.s) {
@@ -529,41 +518,29 @@ template <int T, int K> __global__ void __launch_bounds__(256) spmv_kernel(SpmvA
     }
 }
 
-// Float sums of rows that straddle chunks.  Lane l of a wave checks chunk
-// 64*w + l; for every chunk where its last row starts and continues into the
-// next chunk, the wave adds that row's partials over the chunks it spans, in
-// chunk order.
+// Float sums of rows that straddle chunks.  One thread per (chunk, row of a
+// tile-row): when the chunk's last tile-row starts in it and continues into the
+// next chunk, the thread adds that row's partials over every chunk the
+// tile-row spans, in chunk order.  The partials' addresses are known up front,
+// so the loads overlap.
 template <int T> __global__ void __launch_bounds__(256) plus_fixup_kernel(SpmvArgs p, uint32_t nchunks)
 {
-    const uint32_t lane = lane_id();
-    const uint64_t c64 = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64 + lane;
-    bool owner = false;
-    uint32_t c = 0, r_first = 0, R = 0;
-    if (c64 < nchunks) {
-        c = (uint32_t)c64;
-        const uint32_t t_begin = c * p.chunk, t_end = min(t_begin + p.chunk, p.ntiles);
-        r_first = p.ws_rows[2 * c];
-        R = p.ws_rows[2 * c + 1];
-        owner = p.trp[R + 1] > t_end && p.trp[R] >= t_begin;
-    }
-    uint64_t todo = __ballot(owner);
-    while (todo) {
-        const int src = __builtin_ctzll(todo);
-        todo &= todo - 1;
-        const uint32_t cc = readlane(c, src), RR = readlane(R, src), rf = readlane(r_first, src);
-        if (lane >= (uint32_t)T) continue;
-        // the row's later partials sit in the head slots of chunks cc+1 .. c_last;
-        // their addresses are known up front, so the loads overlap
-        const uint32_t c_last = (p.trp[RR + 1] - 1) / p.chunk;
-        float sum = p.ws_part[((size_t)cc * 2 + (RR == rf ? 0 : 1)) * T + lane];
+    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (uint64_t)nchunks * T) return;
+    const uint32_t c = (uint32_t)(id / T), r = (uint32_t)(id % T);
+    const uint32_t t_begin = c * p.chunk, t_end = min(t_begin + p.chunk, p.ntiles);
+    const uint32_t r_first = p.ws_rows[2 * c], R = p.ws_rows[2 * c + 1];
+    const uint32_t R_end = p.trp[R + 1];
+    if (R_end <= t_end || p.trp[R] < t_begin) return;  // R ends here, or started in an earlier chunk
+    const uint32_t c_last = (R_end - 1) / p.chunk;
+    float sum = p.ws_part[((size_t)c * 2 + (R == r_first ? 0 : 1)) * T + r];
 #pragma unroll 8
-        for (uint32_t c2 = cc + 1; c2 <= c_last; ++c2) sum += p.ws_part[(size_t)c2 * 2 * T + lane];
-        const uint32_t row = RR * T + lane;
-        if (row >= p.n || !((keep_bits<T>(p.mask, p.flags, RR) >> lane) & 1u)) continue;
-        float *y = (float *)p.y + row;
-        if (p.flags & B2SR_ACCUMULATE) *y = *y + p.alpha * sum;
-        else *y = p.alpha * sum + p.beta;
-    }
+    for (uint32_t c2 = c + 1; c2 <= c_last; ++c2) sum += p.ws_part[(size_t)c2 * 2 * T + r];
+    const uint32_t row = R * T + r;
+    if (row >= p.n || !((keep_bits<T>(p.mask, p.flags, R) >> r) & 1u)) return;
+    float *y = (float *)p.y + row;
+    if (p.flags & B2SR_ACCUMULATE) *y = *y + p.alpha * sum;
+    else *y = p.alpha * sum + p.beta;
 }
 
 // Output initialisation: identity (or the diagonal term under SELF) for every
@@ -615,7 +592,7 @@ template <int T, int K> int launch(SpmvArgs p, hipStream_t stream)
     spmv_kernel<T, K><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
     if (int rc = b2sr::check_launch("spmv_kernel")) return rc;
     if constexpr (K == kPlusF32) {
-        plus_fixup_kernel<T><<<b2sr::grid_for(nchunks, 256), 256, 0, stream>>>(p, nchunks);
+        plus_fixup_kernel<T><<<b2sr::grid_for((uint64_t)nchunks * T, 256), 256, 0, stream>>>(p, nchunks);
         if (int rc = b2sr::check_launch("plus_fixup_kernel")) return rc;
     }
     return B2SR_OK;
