@@ -297,25 +297,34 @@ template <int T, int K> __global__ void __launch_bounds__(256) spmv_kernel(SpmvA
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = KT::id();
 
+    // Tile columns of a block, one per lane (JK registers); the next block's are
+    // prefetched while the current block computes, so its x-segment loads can
+    // leave together with its tile loads.
+    auto load_cols = [&](uint32_t b, uint32_t (&J)[JK]) {
+#pragma unroll
+        for (int k = 0; k < JK; ++k) {
+            const uint32_t tk = b + 64 * k + lane;
+            J[k] = tk < t_end ? p.tci[tk] : 0u;
+        }
+    };
     uint32_t blk = t_begin;
+    uint32_t Jr[JK];
+    load_cols(blk, Jr);
     while (blk < t_end) {
         if (min(blk + BT, t_end) - 1 < r_end && !keep) {  // the block lies in a row masked out entirely
             blk = min(r_end, t_end);
+            load_cols(blk, Jr);
             continue;
         }
-        // ---- load phase: tile pieces, tile columns, x segments
-        uint32_t Jr[JK];
-#pragma unroll
-        for (int k = 0; k < JK; ++k) {
-            const uint32_t tk = blk + 64 * k + lane;
-            Jr[k] = tk < t_end ? p.tci[tk] : 0u;
-        }
+        const uint32_t nblk = blk + BT;
+        uint32_t Jn[JK];
+        // ---- load phase: tile pieces, x segments, next block's tile columns
         Piece pc[U];
         uint32_t seg[U];
         if constexpr (!C::kStage) {
+            uint32_t Sr[JK];
             if (p.flags & B2SR_SPARSE_X) {
                 // read a tile only when its x segment has a set bit
-                uint32_t Sr[JK];
 #pragma unroll
                 for (int k = 0; k < JK; ++k)
                     Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>((const uint32_t *)p.x, Jr[k]) : 0u;
@@ -325,52 +334,67 @@ template <int T, int K> __global__ void __launch_bounds__(256) spmv_kernel(SpmvA
                     seg[i] = shfl(Sr[(i * TPW) / 64], (int)(ti % 64));
                     pc[i] = (blk + ti < t_end && seg[i]) ? load_piece<T>(p.bits, blk + ti, sub) : zero_piece<T>();
                 }
+                load_cols(nblk, Jn);
             } else {
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
                     const uint32_t t = blk + i * TPW + grp;
                     pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
                 }
-                uint32_t Sr[JK];
 #pragma unroll
                 for (int k = 0; k < JK; ++k)
                     Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>((const uint32_t *)p.x, Jr[k]) : 0u;
+                load_cols(nblk, Jn);
 #pragma unroll
                 for (int i = 0; i < U; ++i) seg[i] = shfl(Sr[(i * TPW) / 64], (int)((i * TPW + grp) % 64));
             }
         } else {
+            constexpr int QV = 16 / C::VB;  // values per 16-byte quad
+            constexpr int NQ = XW / QV;
 #pragma unroll
             for (int i = 0; i < U; ++i) {
                 const uint32_t t = blk + i * TPW + grp;
                 pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
             }
+            // x segment quads of each step's tile (held in registers until stored to LDS)
+            u32x4 xv[U][NQ];
+            bool whole[U];
 #pragma unroll
             for (int i = 0; i < U; ++i) {
                 const uint32_t ti = i * TPW + grp;
                 const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
-                if (blk + ti >= t_end) continue;
                 const size_t c0 = (size_t)J * T + sub * XW;
-                V *dst = xs + ti * T + sub * XW;
-                constexpr int QV = 16 / C::VB;  // values per 16-byte quad
-                constexpr int NQ = XW / QV;
-                if (c0 + XW <= p.n) {
-                    const u32x4 *src = (const u32x4 *)((const V *)p.x + c0);
+                whole[i] = blk + ti < t_end && c0 + XW <= p.n;
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
-                        u32x4 v = src[q];
+                for (int q = 0; q < NQ; ++q) {
+                    xv[i][q] = u32x4(0u);
+                    if (whole[i]) {
+                        xv[i][q] = ((const u32x4 *)((const V *)p.x + c0))[q];
                         if constexpr (K == kPlusF32) {
                             if (p.s) {
                                 const u32x4 sv = ((const u32x4 *)(p.s + c0))[q];
-                                v.x = __float_as_uint(__uint_as_float(v.x) * __uint_as_float(sv.x));
-                                v.y = __float_as_uint(__uint_as_float(v.y) * __uint_as_float(sv.y));
-                                v.z = __float_as_uint(__uint_as_float(v.z) * __uint_as_float(sv.z));
-                                v.w = __float_as_uint(__uint_as_float(v.w) * __uint_as_float(sv.w));
+                                xv[i][q].x = __float_as_uint(__uint_as_float(xv[i][q].x) * __uint_as_float(sv.x));
+                                xv[i][q].y = __float_as_uint(__uint_as_float(xv[i][q].y) * __uint_as_float(sv.y));
+                                xv[i][q].z = __float_as_uint(__uint_as_float(xv[i][q].z) * __uint_as_float(sv.z));
+                                xv[i][q].w = __float_as_uint(__uint_as_float(xv[i][q].w) * __uint_as_float(sv.w));
                             }
                         }
-                        ((u32x4 *)dst)[q] = v;
                     }
+                }
+            }
+            load_cols(nblk, Jn);
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                const uint32_t ti = i * TPW + grp;
+                if (blk + ti >= t_end) continue;
+                V *dst = xs + ti * T + sub * XW;
+                if (whole[i]) {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) ((u32x4 *)dst)[q] = xv[i][q];
                 } else {
                     // the last, partial tile column: values past n are never selected
+                    const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
+                    const size_t c0 = (size_t)J * T + sub * XW;
                     for (int q = 0; q < XW; ++q) {
                         V v = KT::id();
                         if (c0 + q < p.n) {
@@ -491,7 +515,9 @@ template <int T, int K> __global__ void __launch_bounds__(256) spmv_kernel(SpmvA
             r_end = p.trp[r_cur + 1];
             keep = keep_bits<T>(p.mask, p.flags, r_cur);
         }
-        blk += BT;
+        blk = nblk;
+#pragma unroll
+        for (int k = 0; k < JK; ++k) Jr[k] = Jn[k];
         if constexpr (C::kStage) wave_lds_sync();  // the next block's LDS writes follow this block's reads
     }
     // flush the row the chunk ends in
