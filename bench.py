@@ -64,7 +64,7 @@ def spmv_bytes(A: b2.B2SR, with_mask: bool) -> int:
 
 def source_digest() -> str:
     h = hashlib.sha256()
-    for f in ("common.h", "spmv.hip"):
+    for f in ("common.h", "spmv_core.h", "spmv.hip"):
         with open(os.path.join(ROOT, "paper_2201_08560_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -265,6 +265,48 @@ int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, u
 int b2sr_pagerank(const b2sr_matrix *A, float damping, uint32_t iterations, float *rank, void *ws,
                   size_t ws_bytes, hipStream_t stream);
 
+/* ---- batched multi-source BFS over many graphs ---------------------------
+ * Many graphs are placed in one vertex space of n vertices (each graph's ids
+ * offset by a multiple of 64) and grouped by tile width; group k is the B2SR
+ * matrix groups[k] (a HOST array of ngroups <= 8 views, each n x n and
+ * block-diagonal).  The sources are nseeds distinct (vertex, bit) pairs given
+ * as DEVICE arrays seed_vertex[] and seed_bit[] (bit < 64): bit s of a vertex's
+ * 64-bit frontier word carries the BFS from the source seeded with bit s in
+ * that vertex's graph, so up to 64 sources per graph run at once (seeds with
+ * vertex >= n or bit >= 64 are ignored).  Each level
+ * is one B2SR_OR_U64 product per group plus an element-wise update.
+ * levels (DEVICE, n * 64 uint32_t, vertex-major: levels[v * 64 + s]) receives
+ * the BFS level of v from source s of v's graph, 0xFFFFFFFF if unreached.
+ * *iters (HOST, nullable) receives the number of levels run.
+ *   mode B2SR_BATCH_LEVELS:     one product launch per group and one update
+ *                               launch per level; reads one flag per level.
+ *   mode B2SR_BATCH_PERSISTENT: one cooperative kernel runs all levels with
+ *                               grid barriers (B2SR_ENOTSUP if the device has
+ *                               no cooperative launch).
+ * The call synchronises `stream` (it reads flags back).  ws: workspace of
+ * b2sr_msbfs_batch_workspace_bytes(n) bytes.
+ * Errors: EINVAL, ERANGE, ENOSPC, ENOTSUP, EHIP. */
+#define B2SR_BATCH_LEVELS 0u
+#define B2SR_BATCH_PERSISTENT 1u
+size_t b2sr_msbfs_batch_workspace_bytes(uint32_t n);
+int b2sr_msbfs_batch(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t nseeds,
+                     const uint32_t *seed_vertex, const uint32_t *seed_bit, uint32_t *levels,
+                     unsigned mode, void *ws, size_t ws_bytes, uint32_t *iters,
+                     hipStream_t stream);
+
+/* A plan instantiates the persistent batched BFS (initialisation, seeding and
+ * the cooperative kernel) as a hipGraph once; each launch replays it with one
+ * hipGraphLaunch.  The plan keeps the pointers it was created with: rewrite
+ * the seed arrays in device memory between launches to run other sources.
+ * plan_launch synchronises `stream` only when iters is not NULL. */
+typedef struct b2sr_msbfs_plan_s *b2sr_msbfs_plan;
+int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups,
+                                 uint32_t nseeds, const uint32_t *seed_vertex,
+                                 const uint32_t *seed_bit, uint32_t *levels, void *ws,
+                                 size_t ws_bytes, hipStream_t stream, b2sr_msbfs_plan *plan);
+int b2sr_msbfs_batch_plan_launch(b2sr_msbfs_plan plan, uint32_t *iters, hipStream_t stream);
+int b2sr_msbfs_batch_plan_destroy(b2sr_msbfs_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

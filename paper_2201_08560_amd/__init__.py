@@ -22,6 +22,7 @@ __all__ = [
     "spmv_bin_full", "spmv_bin_full_workspace_bytes", "spgemm_masked", "spgemm_masked_workspace_bytes",
     "b2sr_algo_workspace_bytes", "b2sr_bfs", "b2sr_msbfs", "b2sr_sssp", "b2sr_cc", "b2sr_pagerank",
     "triangle_count", "b2sr_strerror", "as_u32", "as_u64", "header_functions", "FLAGS", "SEMIRINGS",
+    "b2sr_msbfs_batch", "b2sr_msbfs_batch_workspace_bytes", "MsbfsPlan",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,6 +38,7 @@ SELF = 0x8
 SPARSE_X = 0x10
 PLUS_TIMES_F32, MIN_PLUS_F32, MIN_PLUS_U32, OR_U64 = 1, 2, 3, 4
 ALGO_BFS, ALGO_SSSP, ALGO_CC, ALGO_PAGERANK, ALGO_MSBFS = 1, 2, 3, 4, 5
+BATCH_LEVELS, BATCH_PERSISTENT = 0, 1
 FLAGS = {"BUILD_LOWER": BUILD_LOWER, "MASK_COMPLEMENT": MASK_COMPLEMENT, "OUT_COUNT": OUT_COUNT,
          "ACCUMULATE": ACCUMULATE, "SELF": SELF, "SPARSE_X": SPARSE_X}
 SEMIRINGS = {"plus_times_f32": PLUS_TIMES_F32, "min_plus_f32": MIN_PLUS_F32, "min_plus_u32": MIN_PLUS_U32,
@@ -81,6 +83,11 @@ _SIGS = {
     "b2sr_sssp": (_I, [_MP, _U32, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_cc": (_I, [_MP, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_pagerank": (_I, [_MP, ctypes.c_float, _U32, _P, _P, _SZ, _P]),
+    "b2sr_msbfs_batch_workspace_bytes": (_SZ, [_U32]),
+    "b2sr_msbfs_batch": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, ctypes.c_uint, _P, _SZ, ctypes.POINTER(_U32), _P]),
+    "b2sr_msbfs_batch_plan_create": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, _P, _SZ, _P, ctypes.POINTER(_P)]),
+    "b2sr_msbfs_batch_plan_launch": (_I, [_P, ctypes.POINTER(_U32), _P]),
+    "b2sr_msbfs_batch_plan_destroy": (_I, [_P]),
 }
 
 
@@ -329,3 +336,64 @@ def triangle_count(rowptr, colind, n: int, tile: int) -> int:
     L = B2SR.from_csr(rowptr, colind, n, tile, lower=True)
     s = spgemm_masked(L, L, L)
     return int(as_u64(s)[0])
+
+
+# ---- batched multi-source BFS -----------------------------------------------
+
+def _views(groups):
+    arr = (b2sr_matrix * len(groups))()
+    for k, A in enumerate(groups):
+        arr[k] = A._view
+    return arr
+
+
+def b2sr_msbfs_batch_workspace_bytes(n: int) -> int:
+    return int(lib().b2sr_msbfs_batch_workspace_bytes(n))
+
+
+def b2sr_msbfs_batch(n: int, groups, seed_vertex, seed_bit, mode=BATCH_LEVELS, out=None, ws=None):
+    """Batched 64-wide BFS over block-diagonal groups sharing an n-vertex space.
+    Returns (levels int32 tensor [n, 64] with uint32 bits, levels run)."""
+    out = torch.empty((n, 64), dtype=torch.int32, device="cuda") if out is None else out
+    need = b2sr_msbfs_batch_workspace_bytes(n)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda") if ws is None else ws
+    it = _U32(0)
+    views = _views(groups)
+    _check(lib().b2sr_msbfs_batch(n, len(groups), views, seed_vertex.numel(), _ptr(seed_vertex), _ptr(seed_bit),
+                                  _ptr(out), mode, _ptr(ws), need, ctypes.byref(it), _stream()), "b2sr_msbfs_batch")
+    return out, it.value
+
+
+class MsbfsPlan:
+    """The persistent batched BFS instantiated once as a hipGraph (see b2sr.h)."""
+
+    def __init__(self, n: int, groups, seed_vertex, seed_bit, out=None, ws=None):
+        self.n = n
+        self.groups = list(groups)
+        self.seed_vertex, self.seed_bit = seed_vertex, seed_bit
+        self.out = torch.empty((n, 64), dtype=torch.int32, device="cuda") if out is None else out
+        need = b2sr_msbfs_batch_workspace_bytes(n)
+        self.ws = torch.empty(need, dtype=torch.uint8, device="cuda") if ws is None else ws
+        self._views = _views(self.groups)
+        h = _P()
+        _check(lib().b2sr_msbfs_batch_plan_create(n, len(self.groups), self._views, seed_vertex.numel(),
+                                                  _ptr(seed_vertex), _ptr(seed_bit), _ptr(self.out), _ptr(self.ws),
+                                                  need, _stream(), ctypes.byref(h)), "b2sr_msbfs_batch_plan_create")
+        self._h = h
+
+    def launch(self, want_iters: bool = False):
+        it = _U32(0)
+        _check(lib().b2sr_msbfs_batch_plan_launch(self._h, ctypes.byref(it) if want_iters else None, _stream()),
+               "b2sr_msbfs_batch_plan_launch")
+        return it.value if want_iters else None
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _check(lib().b2sr_msbfs_batch_plan_destroy(self._h), "b2sr_msbfs_batch_plan_destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

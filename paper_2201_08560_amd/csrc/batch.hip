@@ -1,0 +1,460 @@
+// Batched multi-source BFS over many graphs at once.
+//
+// Many graphs share one vertex space (each graph's ids offset by a multiple
+// of 64) and are grouped by tile width; each group is one block-diagonal B2SR
+// matrix over the whole space.  Every vertex carries a 64-bit frontier word, so
+// one level of 64-source BFS on every graph is one OR_U64 product per group
+// (the Boolean semiring of Table V on 64 vectors at once) plus an element-wise
+// update:
+//     Y = OR over groups of (A_g (x) F);  new = Y & ~V;  V |= new;  F = new;
+//     level[v][s] = current level for every new bit s of v.
+// Three ways to run the levels:
+//   * B2SR_BATCH_LEVELS:     one product launch per group and one update launch
+//                            per level, with one flag read back per level;
+//   * B2SR_BATCH_PERSISTENT: one kernel runs every level, separating the product
+//                            and update phases with grid barriers.  The grid is
+//                            sized from the occupancy API and launched
+//                            cooperatively (the runtime refuses a grid that
+//                            cannot be co-resident); the barrier itself is a
+//                            generation counter whose waits are bounded: a wait
+//                            that runs out raises an error flag, every block
+//                            leaves the level loop, and the call reports an
+//                            error instead of hanging;
+//   * a plan: the persistent launch (with its initialisation) instantiated as a
+//     hipGraph once and replayed.
+#include <new>
+
+#include "spmv_core.h"
+
+using namespace b2sr_dev;
+using namespace b2sr_core;
+
+namespace {
+
+constexpr uint32_t kMaxGroups = 8;
+constexpr uint32_t kUnreached = 0xFFFFFFFFu;
+
+struct Group {
+    SpmvArgs p;      // product A_g (x) F -> Y (OR_U64 atomics), chunked as spmv_bin_full does
+    uint32_t tile;
+    uint32_t item0;  // first global work item (chunk) of the group
+    uint32_t nchunks;
+};
+
+struct BatchArgs {
+    uint32_t n, ngroups, nitems, max_levels;
+    Group g[kMaxGroups];
+    uint64_t *F, *V, *Y;
+    uint32_t *levels;  // n x 64, vertex-major
+    uint32_t *flags;   // [0], [1]: per-level parity flags; [2]: levels run;
+                       // [3]: barrier arrivals; [4]: barrier generation; [5]: barrier timed out
+    const uint32_t *seed_vertex, *seed_bit;
+    uint32_t nseeds;
+};
+
+__global__ void batch_init_kernel(BatchArgs b)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = tid; i < (uint64_t)b.n * 64; i += stride) b.levels[i] = kUnreached;
+    for (uint64_t i = tid; i < b.n; i += stride) {
+        b.F[i] = 0;
+        b.V[i] = 0;
+        b.Y[i] = 0;
+    }
+    if (tid < 6) b.flags[tid] = 0;
+}
+
+// Seeds are distinct (vertex, bit) pairs, so the level writes never collide and
+// the frontier words are combined with atomics.
+__global__ void batch_seed_kernel(BatchArgs b)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.nseeds;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = b.seed_vertex[i], s = b.seed_bit[i];
+        if (v >= b.n || s >= 64) continue;  // out-of-range seeds are ignored
+        atomicOr((unsigned long long *)b.F + v, 1ull << s);
+        atomicOr((unsigned long long *)b.V + v, 1ull << s);
+        b.levels[(size_t)v * 64 + s] = 0;
+    }
+}
+
+// One vertex: take the new frontier bits, mark them visited, record their
+// level, and clear Y for the next level's product.  Returns whether any bit was new.
+__device__ __forceinline__ bool update_vertex(const BatchArgs &b, uint64_t i, uint32_t level)
+{
+    uint64_t y = b.Y[i] & ~b.V[i];
+    b.Y[i] = 0;
+    b.F[i] = y;
+    if (!y) return false;
+    b.V[i] |= y;
+    uint32_t *lv = b.levels + i * 64;
+    while (y) {
+        const uint32_t s = __builtin_ctzll(y);
+        y &= y - 1;
+        lv[s] = level;
+    }
+    return true;
+}
+
+__global__ void batch_update_kernel(BatchArgs b, uint32_t level)
+{
+    bool any = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.n; i += (uint64_t)gridDim.x * blockDim.x)
+        any |= update_vertex(b, i, level);
+    if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(b.flags + (level & 1), 1u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.flags[(level + 1) & 1] = 0;
+        b.flags[2] = level;
+    }
+}
+
+// One group's product for one level (B2SR_BATCH_LEVELS): one wave per chunk.
+template <int T> __global__ void __launch_bounds__(256) batch_product_kernel(SpmvArgs p, uint32_t nchunks)
+{
+    __shared__ __align__(16) uint64_t s_x[4 * kStageBytesPerWave / sizeof(uint64_t)];
+    const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE;
+    if (wave >= nchunks) return;
+    spmv_chunk<T, kOr64>(p, wave, s_x + (threadIdx.x / B2SR_WAVE) * (kStageBytesPerWave / sizeof(uint64_t)));
+}
+
+template <int T> __device__ __forceinline__ void run_chunk(const Group &g, uint32_t c, uint64_t *xs)
+{
+    spmv_chunk<T, kOr64>(g.p, c, xs);
+}
+
+// Grid-wide barrier for the persistent kernel: block leaders count arrivals;
+// the last one resets the count and advances the generation the others wait
+// on.  Fences around it publish each block's writes device-wide.  A wait is
+// bounded (2^22 polls, a few seconds of wall time): when it runs
+// out, the flag flags[5] is raised and the caller leaves its loop.
+__device__ __forceinline__ void grid_barrier(uint32_t *flags)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t *count = flags + 3, *gen = flags + 4, *timed_out = flags + 5;
+        const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        if (atomicAdd(count, 1u) + 1 == gridDim.x) {
+            atomicExch(count, 0u);
+            __threadfence();
+            atomicAdd(gen, 1u);
+        } else {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins == (1u << 22)) {
+                    atomicOr(timed_out, 1u);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// Every level of every graph in one launch.  Waves take work items (chunks of
+// every group) in a grid-stride loop; grid barriers separate the product from
+// the update, and the update from the convergence test.  All threads read the
+// same flags after the barrier, so they leave the level loop together; the loop
+// is also bounded by max_levels and left at once if a barrier timed out.
+__global__ void __launch_bounds__(256) batch_persistent_kernel(BatchArgs b)
+{
+    __shared__ __align__(16) uint64_t s_x[4 * kStageBytesPerWave / sizeof(uint64_t)];
+    uint64_t *xs = s_x + (threadIdx.x / B2SR_WAVE) * (kStageBytesPerWave / sizeof(uint64_t));
+    const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE;
+    const uint32_t nwaves = gridDim.x * (blockDim.x / B2SR_WAVE);
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    for (uint32_t level = 1; level <= b.max_levels; ++level) {
+        for (uint32_t item = wave; item < b.nitems; item += nwaves) {
+            uint32_t gi = 0;
+            while (gi + 1 < b.ngroups && item >= b.g[gi + 1].item0) ++gi;
+            const Group &g = b.g[gi];
+            const uint32_t c = item - g.item0;
+            switch (g.tile) {
+            case 4: run_chunk<4>(g, c, xs); break;
+            case 8: run_chunk<8>(g, c, xs); break;
+            case 16: run_chunk<16>(g, c, xs); break;
+            default: run_chunk<32>(g, c, xs); break;
+            }
+        }
+        grid_barrier(b.flags);
+        if (__hip_atomic_load(b.flags + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        bool any = false;
+        for (uint64_t i = tid; i < b.n; i += nthreads) any |= update_vertex(b, i, level);
+        if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(b.flags + (level & 1), 1u);
+        if (tid == 0) {
+            b.flags[(level + 1) & 1] = 0;
+            b.flags[2] = level;
+        }
+        grid_barrier(b.flags);
+        if (__hip_atomic_load(b.flags + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (__hip_atomic_load(b.flags + (level & 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+    }
+}
+
+struct Layout {
+    uint64_t *F, *V, *Y;
+    uint32_t *flags;
+    size_t bytes;
+};
+
+Layout carve(uint32_t n, void *ws)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        char *p = ws ? (char *)ws + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    L.F = (uint64_t *)take((size_t)n * 8);
+    L.V = (uint64_t *)take((size_t)n * 8);
+    L.Y = (uint64_t *)take((size_t)n * 8);
+    L.flags = (uint32_t *)take(32);
+    L.bytes = off;
+    return L;
+}
+
+template <int T> uint32_t or64_chunk(uint32_t ntiles) { return chunk_tiles<T, kOr64>(ntiles); }
+
+int make_args(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t nseeds, const uint32_t *seed_vertex,
+              const uint32_t *seed_bit, uint32_t *levels, void *ws, size_t ws_bytes, BatchArgs *out)
+{
+    if (n == 0 || ngroups == 0 || ngroups > kMaxGroups || !groups || !levels) return B2SR_EINVAL;
+    if (n > 0xFFFFFF00u) return B2SR_ERANGE;
+    if (nseeds > 0 && (!seed_vertex || !seed_bit)) return B2SR_EINVAL;
+    const Layout L = carve(n, ws);
+    if (!ws || ws_bytes < L.bytes) return B2SR_ENOSPC;
+    BatchArgs b{};
+    b.n = n;
+    b.ngroups = ngroups;
+    b.F = L.F;
+    b.V = L.V;
+    b.Y = L.Y;
+    b.levels = levels;
+    b.flags = L.flags;
+    b.seed_vertex = seed_vertex;
+    b.seed_bit = seed_bit;
+    b.nseeds = nseeds;
+    b.max_levels = n + 1;  // a BFS level adds at least one vertex, so n + 1 levels always suffice
+    uint64_t items = 0;
+    for (uint32_t k = 0; k < ngroups; ++k) {
+        const b2sr_matrix *A = groups + k;
+        if (int rc = b2sr::validate_matrix(A)) return rc;
+        if (A->n != n) return B2SR_EINVAL;
+        Group &g = b.g[k];
+        g.p = SpmvArgs{};
+        g.p.trp = A->tile_rowptr;
+        g.p.tci = A->tile_colind;
+        g.p.bits = A->bits;
+        g.p.n = n;
+        g.p.ntr = b2sr::n_tile_rows(n, A->tile);
+        g.p.ntiles = A->ntiles;
+        g.p.chunk = A->tile == 4 ? or64_chunk<4>(A->ntiles) : A->tile == 8 ? or64_chunk<8>(A->ntiles)
+                  : A->tile == 16 ? or64_chunk<16>(A->ntiles) : or64_chunk<32>(A->ntiles);
+        g.p.x = L.F;
+        g.p.y = L.Y;
+        g.p.flags = B2SR_ACCUMULATE;
+        g.tile = A->tile;
+        g.item0 = (uint32_t)items;
+        g.nchunks = (uint32_t)(((uint64_t)A->ntiles + g.p.chunk - 1) / g.p.chunk);
+        items += g.nchunks;
+    }
+    if (items >= (1ull << 32)) return B2SR_ERANGE;
+    b.nitems = (uint32_t)items;
+    *out = b;
+    return B2SR_OK;
+}
+
+unsigned vgrid(uint64_t n) { return b2sr::grid_for(n, 256, 8192); }
+
+int launch_init(const BatchArgs &b, hipStream_t stream)
+{
+    batch_init_kernel<<<vgrid((uint64_t)b.n * 64), 256, 0, stream>>>(b);
+    if (int rc = b2sr::check_launch("batch_init_kernel")) return rc;
+    if (b.nseeds) {
+        batch_seed_kernel<<<vgrid(b.nseeds), 256, 0, stream>>>(b);
+        if (int rc = b2sr::check_launch("batch_seed_kernel")) return rc;
+    }
+    return B2SR_OK;
+}
+
+int persistent_grid(unsigned *grid)
+{
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (int rc = b2sr::check(hipGetDevice(&dev), "hipGetDevice")) return rc;
+    if (int rc = b2sr::check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties")) return rc;
+    if (int rc = b2sr::check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_persistent_kernel, 256, 0),
+                             "hipOccupancyMaxActiveBlocksPerMultiprocessor"))
+        return rc;
+    if (per_cu < 1 || !prop.cooperativeLaunch) return B2SR_ENOTSUP;
+    *grid = (unsigned)per_cu * (unsigned)prop.multiProcessorCount;
+    return B2SR_OK;
+}
+
+int launch_persistent(BatchArgs &b, hipStream_t stream)
+{
+    unsigned grid = 0;
+    if (int rc = persistent_grid(&grid)) return rc;
+    void *args[] = {&b};
+    return b2sr::check(hipLaunchCooperativeKernel((const void *)batch_persistent_kernel, dim3(grid), dim3(256), args, 0,
+                                                  stream),
+                       "hipLaunchCooperativeKernel(batch_persistent_kernel)");
+}
+
+int read_u32(const uint32_t *d, uint32_t *h, hipStream_t s)
+{
+    if (int rc = b2sr::check(hipMemcpyAsync(h, d, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync")) return rc;
+    return b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+// Reads the levels run and the barrier time-out flag after a persistent run.
+int finish_persistent(const BatchArgs &b, uint32_t *iters, hipStream_t s)
+{
+    uint32_t h[6] = {0, 0, 0, 0, 0, 0};
+    if (int rc = b2sr::check(hipMemcpyAsync(h, b.flags, sizeof h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync")) return rc;
+    if (int rc = b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize")) return rc;
+    if (h[5]) {
+        b2sr::set_hip_error(hipErrorLaunchTimeOut, "batch_persistent_kernel grid barrier timed out");
+        return B2SR_EHIP;
+    }
+    if (iters) *iters = h[2];
+    return B2SR_OK;
+}
+
+}  // namespace
+
+struct b2sr_msbfs_plan_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BatchArgs args{};
+};
+
+extern "C" {
+
+size_t b2sr_msbfs_batch_workspace_bytes(uint32_t n) { return carve(n, nullptr).bytes; }
+
+int b2sr_msbfs_batch(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t nseeds,
+                     const uint32_t *seed_vertex, const uint32_t *seed_bit, uint32_t *levels, unsigned mode, void *ws,
+                     size_t ws_bytes, uint32_t *iters, hipStream_t stream)
+{
+    if (mode != B2SR_BATCH_LEVELS && mode != B2SR_BATCH_PERSISTENT) return B2SR_EINVAL;
+    BatchArgs b;
+    int rc = make_args(n, ngroups, groups, nseeds, seed_vertex, seed_bit, levels, ws, ws_bytes, &b);
+    if (rc) return rc;
+    if ((rc = launch_init(b, stream))) return rc;
+    if (mode == B2SR_BATCH_PERSISTENT) {
+        if ((rc = launch_persistent(b, stream))) return rc;
+        return finish_persistent(b, iters, stream);
+    }
+    uint32_t level = 0;
+    for (;;) {
+        ++level;
+        for (uint32_t k = 0; k < b.ngroups; ++k) {
+            const Group &g = b.g[k];
+            if (!g.nchunks) continue;
+            const unsigned grid = b2sr::grid_for(g.nchunks, 4);
+            switch (g.tile) {
+            case 4: batch_product_kernel<4><<<grid, 256, 0, stream>>>(g.p, g.nchunks); break;
+            case 8: batch_product_kernel<8><<<grid, 256, 0, stream>>>(g.p, g.nchunks); break;
+            case 16: batch_product_kernel<16><<<grid, 256, 0, stream>>>(g.p, g.nchunks); break;
+            default: batch_product_kernel<32><<<grid, 256, 0, stream>>>(g.p, g.nchunks); break;
+            }
+            if ((rc = b2sr::check_launch("spmv_kernel (batch)"))) return rc;
+        }
+        batch_update_kernel<<<b2sr::grid_for(b.n, 256, 1024), 256, 0, stream>>>(b, level);
+        if ((rc = b2sr::check_launch("batch_update_kernel"))) return rc;
+        uint32_t any = 0;
+        if ((rc = read_u32(b.flags + (level & 1), &any, stream))) return rc;
+        if (!any || level > b.max_levels) break;
+    }
+    if (iters) *iters = level;
+    return B2SR_OK;
+}
+
+int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t nseeds,
+                                 const uint32_t *seed_vertex, const uint32_t *seed_bit, uint32_t *levels, void *ws,
+                                 size_t ws_bytes, hipStream_t stream, b2sr_msbfs_plan *plan)
+{
+    if (!plan) return B2SR_EINVAL;
+    *plan = nullptr;
+    b2sr_msbfs_plan_s *P = new (std::nothrow) b2sr_msbfs_plan_s();
+    if (!P) return B2SR_ENOSPC;
+    int rc = make_args(n, ngroups, groups, nseeds, seed_vertex, seed_bit, levels, ws, ws_bytes, &P->args);
+    unsigned grid = 0;
+    if (!rc) rc = persistent_grid(&grid);
+    if (!rc) rc = b2sr::check(hipGraphCreate(&P->graph, 0), "hipGraphCreate");
+    hipGraphNode_t n_init = nullptr, n_seed = nullptr, n_run = nullptr;
+    void *args[] = {&P->args};
+    if (!rc) {
+        hipKernelNodeParams kp{};
+        kp.func = (void *)batch_init_kernel;
+        kp.gridDim = dim3(vgrid((uint64_t)n * 64));
+        kp.blockDim = dim3(256);
+        kp.kernelParams = args;
+        rc = b2sr::check(hipGraphAddKernelNode(&n_init, P->graph, nullptr, 0, &kp), "hipGraphAddKernelNode(init)");
+    }
+    hipGraphNode_t last = n_init;
+    if (!rc && nseeds) {
+        hipKernelNodeParams kp{};
+        kp.func = (void *)batch_seed_kernel;
+        kp.gridDim = dim3(vgrid(nseeds));
+        kp.blockDim = dim3(256);
+        kp.kernelParams = args;
+        rc = b2sr::check(hipGraphAddKernelNode(&n_seed, P->graph, &last, 1, &kp), "hipGraphAddKernelNode(seed)");
+        last = n_seed;
+    }
+    if (!rc) {
+        hipKernelNodeParams kp{};
+        kp.func = (void *)batch_persistent_kernel;
+        kp.gridDim = dim3(grid);
+        kp.blockDim = dim3(256);
+        kp.kernelParams = args;
+        rc = b2sr::check(hipGraphAddKernelNode(&n_run, P->graph, &last, 1, &kp), "hipGraphAddKernelNode(persistent)");
+    }
+    if (!rc) {
+        // ask for co-residency checks where the runtime offers them; the barrier
+        // itself needs no runtime support and the grid is sized to be resident
+        hipKernelNodeAttrValue v{};
+        v.cooperative = 1;
+        if (hipGraphKernelNodeSetAttribute(n_run, hipKernelNodeAttributeCooperative, &v) != hipSuccess)
+            (void)hipGetLastError();
+    }
+    if (!rc) rc = b2sr::check(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    (void)stream;
+    if (rc) {
+        b2sr_msbfs_batch_plan_destroy(P);
+        return rc;
+    }
+    *plan = P;
+    return B2SR_OK;
+}
+
+int b2sr_msbfs_batch_plan_launch(b2sr_msbfs_plan plan, uint32_t *iters, hipStream_t stream)
+{
+    if (!plan || !plan->exec) return B2SR_EINVAL;
+    int rc = b2sr::check(hipGraphLaunch(plan->exec, stream), "hipGraphLaunch");
+    if (rc) return rc;
+    if (iters) return finish_persistent(plan->args, iters, stream);
+    return B2SR_OK;
+}
+
+int b2sr_msbfs_batch_plan_destroy(b2sr_msbfs_plan plan)
+{
+    if (!plan) return B2SR_OK;
+    int rc = B2SR_OK;
+    if (plan->exec) rc = b2sr::check(hipGraphExecDestroy(plan->exec), "hipGraphExecDestroy");
+    if (plan->graph) {
+        int r2 = b2sr::check(hipGraphDestroy(plan->graph), "hipGraphDestroy");
+        if (!rc) rc = r2;
+    }
+    delete plan;
+    return rc;
+}
+
+}  // extern "C"

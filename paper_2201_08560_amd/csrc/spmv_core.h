@@ -1,0 +1,524 @@
+// Device-side machinery of the B2SR matrix-vector products, shared by the
+// product kernels (spmv.hip) and the persistent batched BFS (batch.hip).
+// Internal to libb2sr.so.
+#pragma once
+
+#include "common.h"
+
+namespace b2sr_core {
+
+using namespace b2sr_dev;
+
+enum Kind : int { kBits = 0, kCount = 1, kPlusF32 = 2, kMinF32 = 3, kMinU32 = 4, kOr64 = 5 };
+
+template <int K> struct KindTraits;
+template <> struct KindTraits<kBits> {
+    using V = uint32_t;
+    static __device__ __forceinline__ V id() { return 0u; }
+    static __device__ __forceinline__ V op(V a, V b) { return a | b; }
+};
+template <> struct KindTraits<kCount> {
+    using V = uint32_t;
+    static __device__ __forceinline__ V id() { return 0u; }
+    static __device__ __forceinline__ V op(V a, V b) { return a + b; }
+};
+template <> struct KindTraits<kPlusF32> {
+    using V = float;
+    static __device__ __forceinline__ V id() { return 0.0f; }
+    static __device__ __forceinline__ V op(V a, V b) { return a + b; }
+};
+template <> struct KindTraits<kMinF32> {
+    using V = float;
+    static __device__ __forceinline__ V id() { return __builtin_huge_valf(); }
+    static __device__ __forceinline__ V op(V a, V b) { return b < a ? b : a; }
+};
+template <> struct KindTraits<kMinU32> {
+    using V = uint32_t;
+    static __device__ __forceinline__ V id() { return 0xFFFFFFFFu; }
+    static __device__ __forceinline__ V op(V a, V b) { return b < a ? b : a; }
+};
+template <> struct KindTraits<kOr64> {
+    using V = uint64_t;
+    static __device__ __forceinline__ V id() { return 0ull; }
+    static __device__ __forceinline__ V op(V a, V b) { return a | b; }
+};
+
+struct SpmvArgs {
+    const uint32_t *trp;
+    const uint32_t *tci;
+    const void *bits;
+    uint32_t n, ntr, ntiles, chunk;
+    const void *x;
+    const float *s;
+    const uint32_t *mask;
+    unsigned flags;
+    float alpha, beta;
+    uint32_t w_u32;
+    void *y;
+    uint32_t *ws_rows;  // float sums: first and last row of each chunk
+    float *ws_part;     // float sums: partials of straddling rows, 2*T per chunk
+};
+
+// Block shape per tile width and kind.  Bit and count products read the x
+// segment as T bits; the others stage T values per tile in LDS, 8 KiB per
+// wave.
+template <int T, int K> struct Cfg {
+    using S = TileShape<T>;
+    static constexpr int LPT = S::LPT, RPL = S::RPL, TPW = S::TPW;
+    static constexpr bool kStage = K >= kPlusF32;
+    static constexpr int VB = sizeof(typename KindTraits<K>::V);
+    static constexpr int U = kStage ? 8192 / (TPW * T * VB) : 8;
+    static constexpr int BT = U * TPW;                 // tiles per block
+    static constexpr int JK = BT >= 64 ? BT / 64 : 1;  // tile-column registers per lane
+    static constexpr int XW = T / LPT;                 // staged x values per lane per tile
+    static_assert(U >= 1 && (64 % TPW) == 0, "block shape");
+};
+
+// Tiles per wave chunk: whole blocks, aiming at about 32K waves per launch,
+// between 1 and 16 blocks.  A pure function of (T, kind, ntiles), so the
+// float-sum workspace query and the launch agree.
+template <int T, int K> inline uint32_t chunk_tiles(uint32_t ntiles)
+{
+    constexpr uint32_t bt = Cfg<T, K>::BT;
+    uint64_t nb = ((uint64_t)ntiles + 32768ull * bt - 1) / (32768ull * bt);
+    nb = nb < 1 ? 1 : (nb > 16 ? 16 : nb);
+    return (uint32_t)(bt * nb);
+}
+
+// One lane's raw piece of a tile.
+template <int T> struct PieceT { using type = u32x4; };
+template <> struct PieceT<8> { using type = u32x2; };
+template <> struct PieceT<4> { using type = uint32_t; };
+
+template <int T> __device__ __forceinline__ typename PieceT<T>::type load_piece(const void *bits, uint32_t t, uint32_t sub)
+{
+    if constexpr (T == 32) return __builtin_nontemporal_load((const u32x4 *)bits + ((size_t)t * 8 + sub));
+    else if constexpr (T == 16) return __builtin_nontemporal_load((const u32x4 *)bits + ((size_t)t * 2 + sub));
+    else if constexpr (T == 8) return __builtin_nontemporal_load((const u32x2 *)bits + t);
+    else return __builtin_nontemporal_load((const uint32_t *)bits + t);
+}
+
+template <int T> __device__ __forceinline__ typename PieceT<T>::type zero_piece()
+{
+    typename PieceT<T>::type z;
+    if constexpr (T == 4) z = 0u;
+    else z = 0u;  // splat
+    return z;
+}
+
+// The RPL bit-rows of a piece as T-bit values (Table II word layout).
+template <int T>
+__device__ __forceinline__ void piece_rows(const typename PieceT<T>::type &v, uint32_t (&a)[TileShape<T>::RPL])
+{
+    if constexpr (T == 32) {
+        a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+    } else if constexpr (T == 16) {
+        a[0] = v.x & 0xFFFFu; a[1] = v.x >> 16; a[2] = v.y & 0xFFFFu; a[3] = v.y >> 16;
+        a[4] = v.z & 0xFFFFu; a[5] = v.z >> 16; a[6] = v.w & 0xFFFFu; a[7] = v.w >> 16;
+    } else if constexpr (T == 8) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a[k] = (v.x >> (8 * k)) & 0xFFu;
+            a[4 + k] = (v.y >> (8 * k)) & 0xFFu;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = (v >> (8 * k)) & 0xFu;
+    }
+}
+
+// Tile-row holding tile t: the last r with trp[r] <= t (trp[ntr] > t).  A
+// 64-way search: every lane probes one pointer per round.
+__device__ __forceinline__ uint32_t find_row(const uint32_t *trp, uint32_t ntr, uint32_t t)
+{
+    uint32_t lo = 0, hi = ntr;  // trp[lo] <= t < trp[hi]
+    const uint32_t lane = lane_id();
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + 63) / 64;
+        const uint32_t probe = lo + (lane + 1) * step;
+        const bool le = lane < 63 && probe < hi && trp[probe] <= t;
+        const uint32_t c = (uint32_t)__popcll(__ballot(le));
+        const uint32_t nlo = lo + c * step;
+        hi = min(hi, nlo + step);
+        lo = nlo;
+    }
+    return lo;
+}
+
+// Row of this lane's tile t, given that every tile of the step lies at or after
+// row r_cur: the rows r_base+1 .. r_base+64 have their first tiles loaded one
+// per lane, and a 6-step search through them counts how many start at or
+// before t.  Repeats (rarely) when more than 64 rows end inside the step.
+__device__ __forceinline__ uint32_t lane_row(const uint32_t *trp, uint32_t ntr, uint32_t r_cur, uint32_t t)
+{
+    const uint32_t lane = lane_id();
+    uint32_t r_base = r_cur, row = 0;
+    bool done = false;
+    while (true) {
+        const uint32_t idx = r_base + 1 + lane;
+        const uint32_t rb = idx <= ntr ? trp[idx] : 0xFFFFFFFFu;
+        uint32_t cnt = 0;
+#pragma unroll
+        for (uint32_t step = 32; step >= 1; step >>= 1) {
+            const uint32_t v = shfl(rb, (int)(cnt + step - 1));
+            if (v <= t) cnt += step;
+        }
+        if (readlane(rb, 63) <= t) cnt = 64;
+        if (!done && cnt < 64) {
+            row = r_base + cnt;
+            done = true;
+        }
+        if (__all(done)) break;
+        r_base += 64;
+    }
+    return row;
+}
+
+// Rows of tile-row I that the mask keeps, as T bits.
+template <int T> __device__ __forceinline__ uint32_t keep_bits(const uint32_t *mask, unsigned flags, uint32_t I)
+{
+    constexpr uint32_t full = T == 32 ? 0xFFFFFFFFu : ((1u << T) - 1u);
+    if (!mask) return full;
+    const uint32_t w = bit_segment<T>(mask, I);
+    return (flags & B2SR_MASK_COMPLEMENT) ? (~w & full) : w;
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// Row stores
+// ---------------------------------------------------------------------------
+
+template <int T> __device__ __forceinline__ void store_bits(const SpmvArgs &p, uint32_t I, uint32_t m)
+{
+    if (!m) return;
+    const uint32_t bit = I * T;
+    atomicOr((uint32_t *)p.y + (bit >> 5), m << (bit & 31u));
+}
+
+// Stores the RPL rows [sub*RPL, sub*RPL + RPL) of tile-row I.
+template <int T, int K>
+__device__ __forceinline__ void store_values(const SpmvArgs &p, uint32_t I, uint32_t sub, uint32_t keep,
+                                             const typename KindTraits<K>::V (&v)[TileShape<T>::RPL],
+                                             bool straddles, uint32_t chunk_id, uint32_t slot)
+{
+    using S = TileShape<T>;
+    using KT = KindTraits<K>;
+#pragma unroll
+    for (int k = 0; k < S::RPL; ++k) {
+        const uint32_t r = sub * S::RPL + k;
+        const uint32_t row = I * T + r;
+        if constexpr (K == kPlusF32) {
+            if (straddles) {
+                p.ws_part[((size_t)chunk_id * 2 + slot) * T + r] = v[k];
+                continue;
+            }
+        }
+        if (row >= p.n || !((keep >> r) & 1u)) continue;
+        if constexpr (K == kCount) {
+            if (v[k]) atomicAdd((uint32_t *)p.y + row, v[k]);
+        } else if constexpr (K == kPlusF32) {
+            float *y = (float *)p.y + row;
+            if (p.flags & B2SR_ACCUMULATE) *y = *y + p.alpha * v[k];
+            else *y = p.alpha * v[k] + p.beta;
+        } else if constexpr (K == kMinF32) {
+            if (v[k] != KT::id()) atomic_min_f32((float *)p.y + row, v[k] + p.alpha);
+        } else if constexpr (K == kMinU32) {
+            if (v[k] != KT::id()) atomicMin((uint32_t *)p.y + row, sat_add_u32(v[k], p.w_u32));
+        } else {
+            if (v[k]) atomicOr((unsigned long long *)p.y + row, (unsigned long long)v[k]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The product kernel, one template for every kind
+// ---------------------------------------------------------------------------
+
+// LDS per wave for the staged kinds (8 KiB, the same for every T and kind).
+constexpr uint32_t kStageBytesPerWave = 8192;
+
+// Processes tile chunk chunk_id of the product described by p.  xs is this
+// wave's 8 KiB LDS slice (unused by bit and count products).
+template <int T, int K>
+__device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id, typename KindTraits<K>::V *xs)
+{
+    using C = Cfg<T, K>;
+    using KT = KindTraits<K>;
+    using V = typename KT::V;
+    using Piece = typename PieceT<T>::type;
+    constexpr int LPT = C::LPT, RPL = C::RPL, TPW = C::TPW, U = C::U, BT = C::BT, JK = C::JK, XW = C::XW;
+    static_assert(!C::kStage || BT * T * sizeof(V) <= kStageBytesPerWave, "LDS slice");
+    // Partials of one lane: a bit mask for kBits, RPL values otherwise.
+    constexpr int NV = K == kBits ? 1 : RPL;
+
+    const uint32_t lane = lane_id(), grp = lane / LPT, sub = lane % LPT;
+    const uint32_t t_begin = chunk_id * p.chunk;
+    const uint32_t t_end = min(t_begin + p.chunk, p.ntiles);
+
+    const uint32_t r_first = find_row(p.trp, p.ntr, t_begin);
+    uint32_t r_cur = r_first;
+    uint32_t r_end = p.trp[r_cur + 1];
+    uint32_t keep = keep_bits<T>(p.mask, p.flags, r_cur);
+    // A row straddles chunks when it starts before t_begin or ends after t_end;
+    // only the chunk's first and last rows can.
+    auto straddles = [&](uint32_t I) { return p.trp[I] < t_begin || p.trp[I + 1] > t_end; };
+    auto slot_of = [&](uint32_t I) { return I == r_first ? 0u : 1u; };
+
+    V acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = KT::id();
+
+    // Tile columns of a block, one per lane (JK registers); the next block's are
+    // prefetched while the current block computes, so its x-segment loads can
+    // leave together with its tile loads.
+    auto load_cols = [&](uint32_t b, uint32_t (&J)[JK]) {
+#pragma unroll
+        for (int k = 0; k < JK; ++k) {
+            const uint32_t tk = b + 64 * k + lane;
+            J[k] = tk < t_end ? p.tci[tk] : 0u;
+        }
+    };
+    uint32_t blk = t_begin;
+    uint32_t Jr[JK];
+    load_cols(blk, Jr);
+    while (blk < t_end) {
+        if (min(blk + BT, t_end) - 1 < r_end && !keep) {  // the block lies in a row masked out entirely
+            blk = min(r_end, t_end);
+            load_cols(blk, Jr);
+            continue;
+        }
+        const uint32_t nblk = blk + BT;
+        uint32_t Jn[JK];
+        // ---- load phase: tile pieces, x segments, next block's tile columns
+        Piece pc[U];
+        uint32_t seg[U];
+        if constexpr (!C::kStage) {
+            uint32_t Sr[JK];
+            if (p.flags & B2SR_SPARSE_X) {
+                // read a tile only when its x segment has a set bit
+#pragma unroll
+                for (int k = 0; k < JK; ++k)
+                    Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>((const uint32_t *)p.x, Jr[k]) : 0u;
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    const uint32_t ti = i * TPW + grp;
+                    seg[i] = shfl(Sr[(i * TPW) / 64], (int)(ti % 64));
+                    pc[i] = (blk + ti < t_end && seg[i]) ? load_piece<T>(p.bits, blk + ti, sub) : zero_piece<T>();
+                }
+                load_cols(nblk, Jn);
+            } else {
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    const uint32_t t = blk + i * TPW + grp;
+                    pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
+                }
+#pragma unroll
+                for (int k = 0; k < JK; ++k)
+                    Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>((const uint32_t *)p.x, Jr[k]) : 0u;
+                load_cols(nblk, Jn);
+#pragma unroll
+                for (int i = 0; i < U; ++i) seg[i] = shfl(Sr[(i * TPW) / 64], (int)((i * TPW + grp) % 64));
+            }
+        } else {
+            constexpr int QV = 16 / C::VB;  // values per 16-byte quad
+            constexpr int NQ = XW / QV;
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                const uint32_t t = blk + i * TPW + grp;
+                pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
+            }
+            // x segment quads of each step's tile (held in registers until stored to LDS)
+            u32x4 xv[U][NQ];
+            bool whole[U];
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                const uint32_t ti = i * TPW + grp;
+                const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
+                const size_t c0 = (size_t)J * T + sub * XW;
+                whole[i] = blk + ti < t_end && c0 + XW <= p.n;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    xv[i][q] = u32x4(0u);
+                    if (whole[i]) {
+                        xv[i][q] = ((const u32x4 *)((const V *)p.x + c0))[q];
+                        if constexpr (K == kPlusF32) {
+                            if (p.s) {
+                                const u32x4 sv = ((const u32x4 *)(p.s + c0))[q];
+                                xv[i][q].x = __float_as_uint(__uint_as_float(xv[i][q].x) * __uint_as_float(sv.x));
+                                xv[i][q].y = __float_as_uint(__uint_as_float(xv[i][q].y) * __uint_as_float(sv.y));
+                                xv[i][q].z = __float_as_uint(__uint_as_float(xv[i][q].z) * __uint_as_float(sv.z));
+                                xv[i][q].w = __float_as_uint(__uint_as_float(xv[i][q].w) * __uint_as_float(sv.w));
+                            }
+                        }
+                    }
+                }
+            }
+            load_cols(nblk, Jn);
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                const uint32_t ti = i * TPW + grp;
+                if (blk + ti >= t_end) continue;
+                V *dst = xs + ti * T + sub * XW;
+                if (whole[i]) {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) ((u32x4 *)dst)[q] = xv[i][q];
+                } else {
+                    // the last, partial tile column: values past n are never selected
+                    const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
+                    const size_t c0 = (size_t)J * T + sub * XW;
+                    for (int q = 0; q < XW; ++q) {
+                        V v = KT::id();
+                        if (c0 + q < p.n) {
+                            v = ((const V *)p.x)[c0 + q];
+                            if constexpr (K == kPlusF32) {
+                                if (p.s) v *= p.s[c0 + q];
+                            }
+                        }
+                        dst[q] = v;
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+
+        // ---- compute phase, one step at a time
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const uint32_t base = blk + i * TPW;
+            if (base >= t_end) break;
+            const uint32_t last = min(base + TPW, t_end) - 1;
+            const bool valid = base + grp < t_end;
+            const uint32_t t = valid ? base + grp : t_end - 1;
+            const uint32_t ti = i * TPW + grp;
+            V part[NV];
+            auto compute = [&]() {
+                uint32_t a[RPL];
+                piece_rows<T>(pc[i], a);
+                if constexpr (K == kBits) {
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) m |= (uint32_t)((a[k] & seg[i]) != 0) << (sub * RPL + k);
+                    part[0] = m;
+                } else if constexpr (K == kCount) {
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) part[k] = (uint32_t)__popc(a[k] & seg[i]);  // Listing 1's dot
+                } else {
+                    const V *xt = xs + ti * T;
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        V v = KT::id();
+                        uint32_t w = a[k];
+                        while (w) {
+                            const uint32_t c = __builtin_ctz(w);
+                            w &= w - 1;
+                            v = KT::op(v, xt[c]);
+                        }
+                        part[k] = v;
+                    }
+                }
+            };
+            if (last < r_end) {
+                compute();
+#pragma unroll
+                for (int k = 0; k < NV; ++k) acc[k] = KT::op(acc[k], part[k]);
+                continue;
+            }
+            // the step crosses the end of row r_cur
+            const uint32_t row = lane_row(p.trp, p.ntr, r_cur, t);
+            const uint32_t rkeep = row == r_cur ? keep : keep_bits<T>(p.mask, p.flags, row);
+            if (valid && rkeep) compute();
+            else {
+#pragma unroll
+                for (int k = 0; k < NV; ++k) part[k] = KT::id();
+            }
+            const uint32_t r_last = readlane(row, 63);
+            const bool first_in_cur = readlane(row, 0) == r_cur;
+            if constexpr (K == kBits) {
+                uint32_t acc_all = acc[0];
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) acc_all |= shfl_xor(acc_all, d);
+                uint32_t v = part[0];
+                if (!first_in_cur) {
+                    if (lane == 0) store_bits<T>(p, r_cur, acc_all & keep);
+                } else if (lane == 0) {
+                    v |= acc_all;
+                }
+#pragma unroll
+                for (uint32_t d = 1; d < 64; d <<= 1) {
+                    const uint32_t o = shfl_up(v, d), ro = shfl_up(row, d);
+                    if (lane >= d && ro == row) v |= o;
+                }
+                const uint32_t next_row = shfl(row, (int)min(lane + 1, 63u));
+                if ((lane == 63 || next_row != row) && row != r_last) store_bits<T>(p, row, v & rkeep);
+                acc[0] = row == r_last ? part[0] : 0u;
+            } else {
+                V v[NV], tot[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    tot[k] = acc[k];
+#pragma unroll
+                    for (int d = LPT; d < 64; d <<= 1) tot[k] = KT::op(tot[k], shfl_xor(tot[k], d));
+                    v[k] = part[k];
+                }
+                if (!first_in_cur) {
+                    if (grp == 0) store_values<T, K>(p, r_cur, sub, keep, tot, straddles(r_cur), chunk_id, slot_of(r_cur));
+                } else if (grp == 0) {
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) v[k] = KT::op(tot[k], part[k]);
+                }
+                // segmented inclusive scan over groups, keyed by row
+#pragma unroll
+                for (int d = 1; d < TPW; d <<= 1) {
+                    const uint32_t ro = shfl_up(row, d * LPT);
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) {
+                        const V o = shfl_up(v[k], d * LPT);
+                        if (grp >= (uint32_t)d && ro == row) v[k] = KT::op(v[k], o);
+                    }
+                }
+                const uint32_t next_row = shfl(row, (int)min(lane + LPT, 63u));
+                if ((grp == TPW - 1 || next_row != row) && row != r_last)
+                    store_values<T, K>(p, row, sub, rkeep, v, straddles(row), chunk_id, slot_of(row));
+#pragma unroll
+                for (int k = 0; k < NV; ++k) acc[k] = row == r_last ? part[k] : KT::id();
+            }
+            r_cur = r_last;
+            r_end = p.trp[r_cur + 1];
+            keep = keep_bits<T>(p.mask, p.flags, r_cur);
+        }
+        blk = nblk;
+#pragma unroll
+        for (int k = 0; k < JK; ++k) Jr[k] = Jn[k];
+        if constexpr (C::kStage) wave_lds_sync();  // the next block's LDS writes follow this block's reads
+    }
+    // flush the row the chunk ends in
+    if constexpr (K == kBits) {
+        uint32_t acc_all = acc[0];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) acc_all |= shfl_xor(acc_all, d);
+        if (lane == 0) store_bits<T>(p, r_cur, acc_all & keep);
+    } else {
+        V tot[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            tot[k] = acc[k];
+#pragma unroll
+            for (int d = LPT; d < 64; d <<= 1) tot[k] = KT::op(tot[k], shfl_xor(tot[k], d));
+        }
+        if (grp == 0) store_values<T, K>(p, r_cur, sub, keep, tot, straddles(r_cur), chunk_id, slot_of(r_cur));
+        if constexpr (K == kPlusF32) {
+            if (lane == 0) {
+                p.ws_rows[2 * chunk_id] = r_first;
+                p.ws_rows[2 * chunk_id + 1] = r_cur;
+            }
+        }
+    }
+}
+
+}  // namespace b2sr_core

@@ -123,3 +123,39 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(b2, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         b2.lib()
+
+
+def test_batch_argument_errors():
+    A = mat()
+    groups = (b2.b2sr_matrix * 2)(A, A)
+    p = ctypes.c_void_p(FAKE)
+    it = ctypes.c_uint32(0)
+    need = L.b2sr_msbfs_batch_workspace_bytes(64)
+    assert need >= 3 * 64 * 8
+    assert L.b2sr_msbfs_batch(64, 0, groups, 1, p, p, p, 0, p, need, ctypes.byref(it), None) == -1   # no groups
+    assert L.b2sr_msbfs_batch(64, 9, groups, 1, p, p, p, 0, p, need, ctypes.byref(it), None) == -1   # > 8 groups
+    assert L.b2sr_msbfs_batch(64, 2, groups, 1, p, p, p, 7, p, need, ctypes.byref(it), None) == -1   # bad mode
+    assert L.b2sr_msbfs_batch(64, 2, groups, 1, p, p, p, 0, p, need - 1, ctypes.byref(it), None) == -3
+    assert L.b2sr_msbfs_batch(65, 2, groups, 1, p, p, p, 0, p, 1 << 20, ctypes.byref(it), None) == -1  # n mismatch
+    assert L.b2sr_msbfs_batch(64, 2, groups, 1, None, p, p, 0, p, need, ctypes.byref(it), None) == -1  # no seeds
+    bad = (b2.b2sr_matrix * 1)(mat(tile=5))
+    assert L.b2sr_msbfs_batch(64, 1, bad, 1, p, p, p, 0, p, need, ctypes.byref(it), None) == -1
+    h = ctypes.c_void_p(0)
+    assert L.b2sr_msbfs_batch_plan_create(64, 2, groups, 1, p, p, p, p, need, None, None) == -1
+    assert L.b2sr_msbfs_batch_plan_create(64, 0, groups, 1, p, p, p, p, need, None, ctypes.byref(h)) == -1
+    assert L.b2sr_msbfs_batch_plan_launch(None, None, None) == -1
+    assert L.b2sr_msbfs_batch_plan_destroy(None) == 0
+
+
+def test_sampling_profile_closed_form():
+    """One nonzero per row: every sampled row touches one chunk, so the estimate is
+    (w + (4 + (k-1) w) / k) / 8 for each tile width k (the reading of Algorithm 1)."""
+    import graphgen as gg
+    from paper_2201_08560_amd import autotune
+    g = gg.path(2)  # rows {1}, {0}
+    est = autotune.sampling_profile(g.rowptr, g.colind, g.n, nsample=2)
+    for k, w in ((4, 1), (8, 1), (16, 2), (32, 4)):
+        assert est[k] == pytest.approx((w + (4 + (k - 1) * w) / k) / 8.0)
+    m = gg.cycle(1000)
+    est = autotune.sampling_profile(m.rowptr, m.colind, m.n, nsample=500, seed=3)
+    assert est[32] < est[4] * 8  # monotone sanity: wider tiles share chunks between neighbours
