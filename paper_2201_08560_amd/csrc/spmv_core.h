@@ -336,10 +336,12 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
             // x segment quads of each step's tile (held in registers until stored to LDS)
             u32x4 xv[U][NQ];
             bool whole[U];
+            uint32_t Js[U];  // each step's tile column, read while every lane is active
 #pragma unroll
             for (int i = 0; i < U; ++i) {
                 const uint32_t ti = i * TPW + grp;
                 const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
+                Js[i] = J;
                 const size_t c0 = (size_t)J * T + sub * XW;
                 whole[i] = blk + ti < t_end && c0 + XW <= p.n;
 #pragma unroll
@@ -370,8 +372,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                     for (int q = 0; q < NQ; ++q) ((u32x4 *)dst)[q] = xv[i][q];
                 } else {
                     // the last, partial tile column: values past n are never selected
-                    const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
-                    const size_t c0 = (size_t)J * T + sub * XW;
+                    const size_t c0 = (size_t)Js[i] * T + sub * XW;
                     for (int q = 0; q < XW; ++q) {
                         V v = KT::id();
                         if (c0 + q < p.n) {

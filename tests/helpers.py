@@ -33,6 +33,7 @@ def small_graphs():
     gs = [
         gg.er_gnm(4096, 16384, seed=1),           # the correctness-scale ER workload
         gg.er_gnm(4099, 12000, seed=2),           # ragged last tile-row
+        gg.er_gnm(2049, 6000, seed=7),            # one vertex alone in the last tile column
         gg.rmat(13, 16, seed=13),                 # power-law rows crossing wave chunks
         gg.star(20000),                           # one tile-row far longer than a chunk
         gg.king_grid(61, 67),                     # banded
