@@ -113,7 +113,7 @@ __global__ void batch_update_kernel(BatchArgs b, uint32_t level)
 template <int T> __global__ void __launch_bounds__(256) batch_product_kernel(SpmvArgs p, uint32_t nchunks)
 {
     __shared__ __align__(16) uint64_t s_x[4 * kStageBytesPerWave / sizeof(uint64_t)];
-    const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE;
+    const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     if (wave >= nchunks) return;
     spmv_chunk<T, kOr64>(p, wave, s_x + (threadIdx.x / B2SR_WAVE) * (kStageBytesPerWave / sizeof(uint64_t)));
 }
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256) batch_persistent_kernel(BatchArgs b)
 {
     __shared__ __align__(16) uint64_t s_x[4 * kStageBytesPerWave / sizeof(uint64_t)];
     uint64_t *xs = s_x + (threadIdx.x / B2SR_WAVE) * (kStageBytesPerWave / sizeof(uint64_t));
-    const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE;
+    const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     const uint32_t nwaves = gridDim.x * (blockDim.x / B2SR_WAVE);
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;

@@ -40,7 +40,7 @@ template <int T, int K> __global__ void __launch_bounds__(256) spmv_kernel(SpmvA
     using V = typename KindTraits<K>::V;
     constexpr bool stage = Cfg<T, K>::kStage;
     __shared__ __align__(16) V s_x[stage ? 4 * kStageBytesPerWave / sizeof(V) : 1];
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE;
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     if (wave * p.chunk >= p.ntiles) return;
     spmv_chunk<T, K>(p, (uint32_t)wave, s_x + (stage ? (threadIdx.x / B2SR_WAVE) * kStageBytesPerWave / sizeof(V) : 0));
 }

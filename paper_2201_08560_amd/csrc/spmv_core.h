@@ -5,9 +5,35 @@
 
 #include "common.h"
 
+// Tuning knobs (compile-time; the defaults are the measured choices).
+#ifndef B2SR_TARGET_WAVES
+#define B2SR_TARGET_WAVES 65536  // waves per product launch the chunk size aims at
+#endif
+#ifndef B2SR_BITS_STEPS
+#define B2SR_BITS_STEPS 8        // steps per block for bit and count products, T = 32
+#endif
+#ifndef B2SR_BITS_STEPS_SMALL
+#define B2SR_BITS_STEPS_SMALL 8  // the same for T <= 16
+#endif
+#ifndef B2SR_STAGE_BYTES
+#define B2SR_STAGE_BYTES 4096    // LDS bytes per wave for staged x segments
+#endif
+#ifndef B2SR_NT_TILES
+#define B2SR_NT_TILES 1          // stream tile bits with nontemporal loads
+#endif
+
 namespace b2sr_core {
 
 using namespace b2sr_dev;
+
+template <class P> __device__ __forceinline__ P load_stream(const P *p)
+{
+#if B2SR_NT_TILES
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 
 enum Kind : int { kBits = 0, kCount = 1, kPlusF32 = 2, kMinF32 = 3, kMinU32 = 4, kOr64 = 5 };
 
@@ -60,14 +86,15 @@ struct SpmvArgs {
 };
 
 // Block shape per tile width and kind.  Bit and count products read the x
-// segment as T bits; the others stage T values per tile in LDS, 8 KiB per
-// wave.
+// segment as T bits; the others stage T values per tile in LDS (a fixed budget
+// per wave, so the block shrinks as the vector values widen).
 template <int T, int K> struct Cfg {
     using S = TileShape<T>;
     static constexpr int LPT = S::LPT, RPL = S::RPL, TPW = S::TPW;
     static constexpr bool kStage = K >= kPlusF32;
     static constexpr int VB = sizeof(typename KindTraits<K>::V);
-    static constexpr int U = kStage ? 8192 / (TPW * T * VB) : 8;
+    static constexpr int U = kStage ? B2SR_STAGE_BYTES / (TPW * T * VB)
+                                    : (T == 32 ? B2SR_BITS_STEPS : B2SR_BITS_STEPS_SMALL);
     static constexpr int BT = U * TPW;                 // tiles per block
     static constexpr int JK = BT >= 64 ? BT / 64 : 1;  // tile-column registers per lane
     static constexpr int XW = T / LPT;                 // staged x values per lane per tile
@@ -80,7 +107,8 @@ template <int T, int K> struct Cfg {
 template <int T, int K> inline uint32_t chunk_tiles(uint32_t ntiles)
 {
     constexpr uint32_t bt = Cfg<T, K>::BT;
-    uint64_t nb = ((uint64_t)ntiles + 32768ull * bt - 1) / (32768ull * bt);
+    constexpr uint64_t waves = B2SR_TARGET_WAVES;
+    uint64_t nb = ((uint64_t)ntiles + waves * bt - 1) / (waves * bt);
     nb = nb < 1 ? 1 : (nb > 16 ? 16 : nb);
     return (uint32_t)(bt * nb);
 }
@@ -92,10 +120,10 @@ template <> struct PieceT<4> { using type = uint32_t; };
 
 template <int T> __device__ __forceinline__ typename PieceT<T>::type load_piece(const void *bits, uint32_t t, uint32_t sub)
 {
-    if constexpr (T == 32) return __builtin_nontemporal_load((const u32x4 *)bits + ((size_t)t * 8 + sub));
-    else if constexpr (T == 16) return __builtin_nontemporal_load((const u32x4 *)bits + ((size_t)t * 2 + sub));
-    else if constexpr (T == 8) return __builtin_nontemporal_load((const u32x2 *)bits + t);
-    else return __builtin_nontemporal_load((const uint32_t *)bits + t);
+    if constexpr (T == 32) return load_stream((const u32x4 *)bits + ((size_t)t * 8 + sub));
+    else if constexpr (T == 16) return load_stream((const u32x4 *)bits + ((size_t)t * 2 + sub));
+    else if constexpr (T == 8) return load_stream((const u32x2 *)bits + t);
+    else return load_stream((const uint32_t *)bits + t);
 }
 
 template <int T> __device__ __forceinline__ typename PieceT<T>::type zero_piece()
@@ -241,10 +269,10 @@ __device__ __forceinline__ void store_values(const SpmvArgs &p, uint32_t I, uint
 // ---------------------------------------------------------------------------
 
 // LDS per wave for the staged kinds (8 KiB, the same for every T and kind).
-constexpr uint32_t kStageBytesPerWave = 8192;
+constexpr uint32_t kStageBytesPerWave = B2SR_STAGE_BYTES;
 
-// Processes tile chunk chunk_id of the product described by p.  xs is this
-// wave's 8 KiB LDS slice (unused by bit and count products).
+// Processes tile chunk chunk_id (wave-uniform) of the product described by p.
+// xs is this wave's LDS slice (unused by bit and count products).
 template <int T, int K>
 __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id, typename KindTraits<K>::V *xs)
 {
@@ -273,29 +301,36 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
     V acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = KT::id();
-
-    // Tile columns of a block, one per lane (JK registers); the next block's are
-    // prefetched while the current block computes, so its x-segment loads can
-    // leave together with its tile loads.
-    auto load_cols = [&](uint32_t b, uint32_t (&J)[JK]) {
+    // Bit products fold raw AND words per bit-row in the common case and form
+    // the row bits only when a row is finished.
+    uint32_t raw[K == kBits ? RPL : 1];
 #pragma unroll
-        for (int k = 0; k < JK; ++k) {
-            const uint32_t tk = b + 64 * k + lane;
-            J[k] = tk < t_end ? p.tci[tk] : 0u;
+    for (int k = 0; k < (K == kBits ? RPL : 1); ++k) raw[k] = 0;
+    auto fold_raw = [&]() {
+        if constexpr (K == kBits) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                m |= (uint32_t)(raw[k] != 0) << (sub * RPL + k);
+                raw[k] = 0;
+            }
+            acc[0] |= m;
         }
     };
+
     uint32_t blk = t_begin;
-    uint32_t Jr[JK];
-    load_cols(blk, Jr);
     while (blk < t_end) {
         if (min(blk + BT, t_end) - 1 < r_end && !keep) {  // the block lies in a row masked out entirely
             blk = min(r_end, t_end);
-            load_cols(blk, Jr);
             continue;
         }
-        const uint32_t nblk = blk + BT;
-        uint32_t Jn[JK];
-        // ---- load phase: tile pieces, x segments, next block's tile columns
+        // ---- load phase: tile pieces, tile columns (one per lane), x segments
+        uint32_t Jr[JK];
+#pragma unroll
+        for (int k = 0; k < JK; ++k) {
+            const uint32_t tk = blk + 64 * k + lane;
+            Jr[k] = tk < t_end ? p.tci[tk] : 0u;
+        }
         Piece pc[U];
         uint32_t seg[U];
         if constexpr (!C::kStage) {
@@ -311,7 +346,6 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                     seg[i] = shfl(Sr[(i * TPW) / 64], (int)(ti % 64));
                     pc[i] = (blk + ti < t_end && seg[i]) ? load_piece<T>(p.bits, blk + ti, sub) : zero_piece<T>();
                 }
-                load_cols(nblk, Jn);
             } else {
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
@@ -321,58 +355,43 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
 #pragma unroll
                 for (int k = 0; k < JK; ++k)
                     Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>((const uint32_t *)p.x, Jr[k]) : 0u;
-                load_cols(nblk, Jn);
 #pragma unroll
                 for (int i = 0; i < U; ++i) seg[i] = shfl(Sr[(i * TPW) / 64], (int)((i * TPW + grp) % 64));
             }
         } else {
-            constexpr int QV = 16 / C::VB;  // values per 16-byte quad
-            constexpr int NQ = XW / QV;
 #pragma unroll
             for (int i = 0; i < U; ++i) {
                 const uint32_t t = blk + i * TPW + grp;
                 pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
             }
-            // x segment quads of each step's tile (held in registers until stored to LDS)
-            u32x4 xv[U][NQ];
-            bool whole[U];
-            uint32_t Js[U];  // each step's tile column, read while every lane is active
+            constexpr int QV = 16 / C::VB;  // values per 16-byte quad
+            constexpr int NQ = XW / QV;
 #pragma unroll
             for (int i = 0; i < U; ++i) {
                 const uint32_t ti = i * TPW + grp;
+                // every lane takes part in the shuffle; only then may lanes drop out
                 const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
-                Js[i] = J;
+                if (blk + ti >= t_end) continue;
                 const size_t c0 = (size_t)J * T + sub * XW;
-                whole[i] = blk + ti < t_end && c0 + XW <= p.n;
+                V *dst = xs + ti * T + sub * XW;
+                if (c0 + XW <= p.n) {
+                    const u32x4 *src = (const u32x4 *)((const V *)p.x + c0);
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    xv[i][q] = u32x4(0u);
-                    if (whole[i]) {
-                        xv[i][q] = ((const u32x4 *)((const V *)p.x + c0))[q];
+                    for (int q = 0; q < NQ; ++q) {
+                        u32x4 v = src[q];
                         if constexpr (K == kPlusF32) {
                             if (p.s) {
                                 const u32x4 sv = ((const u32x4 *)(p.s + c0))[q];
-                                xv[i][q].x = __float_as_uint(__uint_as_float(xv[i][q].x) * __uint_as_float(sv.x));
-                                xv[i][q].y = __float_as_uint(__uint_as_float(xv[i][q].y) * __uint_as_float(sv.y));
-                                xv[i][q].z = __float_as_uint(__uint_as_float(xv[i][q].z) * __uint_as_float(sv.z));
-                                xv[i][q].w = __float_as_uint(__uint_as_float(xv[i][q].w) * __uint_as_float(sv.w));
+                                v.x = __float_as_uint(__uint_as_float(v.x) * __uint_as_float(sv.x));
+                                v.y = __float_as_uint(__uint_as_float(v.y) * __uint_as_float(sv.y));
+                                v.z = __float_as_uint(__uint_as_float(v.z) * __uint_as_float(sv.z));
+                                v.w = __float_as_uint(__uint_as_float(v.w) * __uint_as_float(sv.w));
                             }
                         }
+                        ((u32x4 *)dst)[q] = v;
                     }
-                }
-            }
-            load_cols(nblk, Jn);
-#pragma unroll
-            for (int i = 0; i < U; ++i) {
-                const uint32_t ti = i * TPW + grp;
-                if (blk + ti >= t_end) continue;
-                V *dst = xs + ti * T + sub * XW;
-                if (whole[i]) {
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) ((u32x4 *)dst)[q] = xv[i][q];
                 } else {
                     // the last, partial tile column: values past n are never selected
-                    const size_t c0 = (size_t)Js[i] * T + sub * XW;
                     for (int q = 0; q < XW; ++q) {
                         V v = KT::id();
                         if (c0 + q < p.n) {
@@ -410,26 +429,39 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) part[k] = (uint32_t)__popc(a[k] & seg[i]);  // Listing 1's dot
                 } else {
-                    const V *xt = xs + ti * T;
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) {
-                        V v = KT::id();
-                        uint32_t w = a[k];
-                        while (w) {
-                            const uint32_t c = __builtin_ctz(w);
-                            w &= w - 1;
-                            v = KT::op(v, xt[c]);
+                    for (int k = 0; k < RPL; ++k) part[k] = KT::id();
+                    uint32_t any = 0;
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) any |= a[k];
+                    if (any) {  // most lanes of a sparse tile hold no set bit
+                        const V *xt = xs + ti * T;
+#pragma unroll
+                        for (int k = 0; k < RPL; ++k) {
+                            uint32_t w = a[k];
+                            while (w) {
+                                const uint32_t c = __builtin_ctz(w);
+                                w &= w - 1;
+                                part[k] = KT::op(part[k], xt[c]);
+                            }
                         }
-                        part[k] = v;
                     }
                 }
             };
             if (last < r_end) {
-                compute();
+                if constexpr (K == kBits) {
+                    uint32_t a[RPL];
+                    piece_rows<T>(pc[i], a);
 #pragma unroll
-                for (int k = 0; k < NV; ++k) acc[k] = KT::op(acc[k], part[k]);
+                    for (int k = 0; k < RPL; ++k) raw[k] |= a[k] & seg[i];
+                } else {
+                    compute();
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) acc[k] = KT::op(acc[k], part[k]);
+                }
                 continue;
             }
+            fold_raw();
             // the step crosses the end of row r_cur
             const uint32_t row = lane_row(p.trp, p.ntr, r_cur, t);
             const uint32_t rkeep = row == r_cur ? keep : keep_bits<T>(p.mask, p.flags, row);
@@ -493,13 +525,12 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
             r_end = p.trp[r_cur + 1];
             keep = keep_bits<T>(p.mask, p.flags, r_cur);
         }
-        blk = nblk;
-#pragma unroll
-        for (int k = 0; k < JK; ++k) Jr[k] = Jn[k];
+        blk += BT;
         if constexpr (C::kStage) wave_lds_sync();  // the next block's LDS writes follow this block's reads
     }
     // flush the row the chunk ends in
     if constexpr (K == kBits) {
+        fold_raw();
         uint32_t acc_all = acc[0];
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) acc_all |= shfl_xor(acc_all, d);
