@@ -196,6 +196,61 @@ def tc_section(reps: int = 3) -> dict:
     return out
 
 
+def batched_section(graphs, reps: int = 3) -> dict:
+    """256 Chung-Lu graphs (n log-uniform in 1K..256K, mean degree 4..32,
+    exponent 2.1), 64 sources each; a query is one graph's 64-source BFS.
+    Per-graph launches (b2sr_msbfs per graph) against the batched forms; every
+    graph's levels must be identical between them."""
+    from paper_2201_08560_amd import autotune
+    from paper_2201_08560_amd.batch import GraphBatch
+    count = len(graphs)
+    t0 = time.perf_counter()
+    tiles = [autotune.choose_tile(g, nsample=256)[0] for g in graphs]
+    tune_s = time.perf_counter() - t0
+    sources = [gg.sample_sources(g, 64, seed=1000 + i) for i, g in enumerate(graphs)]
+    B = GraphBatch(graphs, tiles)
+    B.set_sources(sources)
+    singles = [b2.B2SR.from_graph(g, t) for g, t in zip(graphs, tiles)]
+    ws_single = torch.empty(max(b2.b2sr_algo_workspace_bytes(A, b2.ALGO_MSBFS) for A in singles),
+                            dtype=torch.uint8, device="cuda")
+    outs = [torch.empty((64, g.n), dtype=torch.int32, device="cuda") for g in graphs]
+    torch.cuda.synchronize()
+
+    def per_graph():
+        for A, src, o in zip(singles, sources, outs):
+            b2.b2sr_msbfs(A, src, out=o, ws=ws_single)
+
+    lv = torch.empty((B.n, 64), dtype=torch.int32, device="cuda")
+    ws_b = torch.empty(b2.b2sr_msbfs_batch_workspace_bytes(B.n), dtype=torch.uint8, device="cuda")
+    plan = B.plan(out=torch.empty_like(lv), ws=torch.empty_like(ws_b))
+    modes = {"per_graph": per_graph,
+             "batched_levels": lambda: B.run(b2.BATCH_LEVELS, out=lv, ws=ws_b),
+             "batched_persistent": lambda: B.run(b2.BATCH_PERSISTENT, out=lv, ws=ws_b),
+             "batched_hipgraph": lambda: plan.launch(want_iters=True)}
+    res = {}
+    for name, fn in modes.items():
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        t = float(np.median(ts))
+        res[name] = {"ms": 1e3 * t, "queries_per_s": count / t}
+        log(f"batched {name}: {1e3 * t:.2f} ms")
+    same = all(torch.equal(outs[i], B.levels_of(lv, i)) and torch.equal(outs[i], B.levels_of(plan.out, i))
+               for i in range(count))
+    plan.close()
+    hist = {str(T): tiles.count(T) for T in (4, 8, 16, 32)}
+    best = min(("batched_levels", "batched_persistent", "batched_hipgraph"), key=lambda k: res[k]["ms"])
+    return {"graphs": count, "n_total": B.n, "nnz_total": int(sum(g.nnz for g in graphs)),
+            "sources_per_graph": 64, "tile_histogram": hist, "autotune_s": tune_s, "modes": res,
+            "identical_results": bool(same),
+            "speedup_best_batched_vs_per_graph": res["per_graph"]["ms"] / res[best]["ms"]}
+
+
 def cpu_baseline(w: Workload, edges_per_step: float) -> dict:
     """The oracle on the host: the same step's results (64 BFS, SSSP, CC,
     PageRank x 50 and the four single products), timed once."""
@@ -278,6 +333,13 @@ def main():
     ap.add_argument("--profile-mode", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
+    batch_graphs = None
+    if not args.no_extras and not args.profile_mode and args.gpus == 1 and world == 1:
+        # generated in worker processes before this process touches the GPU
+        t0 = time.perf_counter()
+        batch_graphs = gg.chung_lu_batch(256, 2.1, seed=1000, workers=min(8, os.cpu_count() or 1))
+        log(f"batched workload: {len(batch_graphs)} graphs in {time.perf_counter() - t0:.1f} s, "
+            f"n={sum(g.n for g in batch_graphs)} nnz={sum(g.nnz for g in batch_graphs)}")
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE={world}) is not supported: this build "
               "runs the B2SR path on a single MI355X.", file=sys.stderr)
@@ -330,6 +392,7 @@ def main():
         out["verify"] = verify(w)
         out["bfs_single_source"] = bfs_gteps(w)
         out["tc"] = tc_section()
+        out["batched"] = batched_section(batch_graphs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, edges_per_step)
     print(json.dumps(out), flush=True)

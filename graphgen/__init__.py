@@ -27,7 +27,7 @@ import numpy as np
 
 __all__ = [
     "Csr", "canonical_csr", "er_gnm", "rmat", "king_grid", "grid4", "mycielski",
-    "chung_lu", "path", "star", "complete", "cycle", "torus", "disjoint_union",
+    "chung_lu", "chung_lu_batch", "batch_params", "path", "star", "complete", "cycle", "torus", "disjoint_union",
     "random_graph_tiny", "sample_sources", "random_mask", "rng",
 ]
 
@@ -254,6 +254,32 @@ def disjoint_union(*gs: Csr) -> Csr:
         dst.append(g.colind.astype(np.int64) + off)
         off += g.n
     return canonical_csr(off, np.concatenate(src), np.concatenate(dst), name="union")
+
+
+def batch_params(count: int = 256, seed: int = 1000):
+    """Sizes and mean degrees of the batched workload: n log-uniform in
+    [1024, 262144], mean degree uniform in [4, 32]."""
+    r = rng(seed)
+    n = np.floor(np.exp(r.uniform(np.log(1024), np.log(262144), count))).astype(np.int64)
+    k = r.uniform(4, 32, count)
+    return n, k
+
+
+def _chung_lu_job(args):
+    i, n, k, gamma, seed0 = args
+    return chung_lu(int(n), float(k), gamma, seed=seed0 + i)
+
+
+def chung_lu_batch(count: int = 256, gamma: float = 2.1, seed: int = 1000, workers: int = 8):
+    """The batched workload: ``count`` Chung-Lu graphs (power-law exponent
+    gamma), graph i drawn with seed ``seed + i``; generated in worker processes."""
+    from concurrent.futures import ProcessPoolExecutor
+    n, k = batch_params(count, seed)
+    jobs = [(i, n[i], k[i], gamma, seed) for i in range(count)]
+    if workers <= 1:
+        return [_chung_lu_job(j) for j in jobs]
+    with ProcessPoolExecutor(workers) as ex:
+        return list(ex.map(_chung_lu_job, jobs, chunksize=4))
 
 
 def random_graph_tiny(n: int, p: float, seed: int) -> Csr:
