@@ -185,6 +185,12 @@ int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, 
  *       (the diagonal as a real zero, Sec. V SSSP); y_i = t_i.  For _U32,
  *       alpha must be a non-negative integer and additions saturate.
  *   B2SR_OR_U64: y_i = OR_{j : A_ij = 1} x_j over uint64_t words.
+ *   x_active (nullable bit vector over columns, the layout of x's indices):
+ *   entries x_j whose bit is 0 are treated as the semiring's identity (0, or
+ *   +infinity for min-plus) and tiles whose whole x segment is inactive are
+ *   not read; the B2SR_SELF term still reads x_i.  Iterative algorithms pass
+ *   the set of entries that changed (SSSP, CC) or are non-zero (multi-source
+ *   BFS frontier words).
  *   mask / B2SR_MASK_COMPLEMENT: as for spmv_bin_bin; a dropped row gets 0
  *   (plus-times, or-u64) or infinity (min-plus), or keeps its old value under
  *   ACCUMULATE.  B2SR_ACCUMULATE: y_i = y_i + alpha t_i + beta (plus-times),
@@ -193,14 +199,15 @@ int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, 
  *   not depend on scheduling (rows split across work chunks are combined in
  *   chunk order by a second kernel).
  *   ws/ws_bytes: workspace of at least spmv_bin_full_workspace_bytes(A,
- *   semiring) bytes (may be NULL when that is 0).  y must not alias x.
+ *   semiring) bytes (may be NULL when that is 0).  y must not alias x,
+ *   x_active or mask.
  *   x and col_scale must be 16-byte aligned (segments are read as vectors).
  *   Errors: EINVAL, ENOSPC, ENOTSUP (unknown semiring), EHIP.
  */
 size_t spmv_bin_full_workspace_bytes(const b2sr_matrix *A, int semiring);
 int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float *col_scale,
-                  const uint32_t *mask, unsigned flags, double alpha, double beta, void *y,
-                  void *ws, size_t ws_bytes, hipStream_t stream);
+                  const uint32_t *x_active, const uint32_t *mask, unsigned flags, double alpha,
+                  double beta, void *y, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---- masked matrix-matrix product, summed (Sec. IV, Table IV, Listing 2) ---
  * spgemm_masked: *d_sum (device uint64_t) receives

@@ -74,7 +74,7 @@ _SIGS = {
     "b2sr_pack_bits": (_I, [_U32, _P, _P, _P]),
     "spmv_bin_bin": (_I, [_MP, _P, _P, ctypes.c_uint, _P, _P]),
     "spmv_bin_full_workspace_bytes": (_SZ, [_MP, _I]),
-    "spmv_bin_full": (_I, [_MP, _I, _P, _P, _P, ctypes.c_uint, _D, _D, _P, _P, _SZ, _P]),
+    "spmv_bin_full": (_I, [_MP, _I, _P, _P, _P, _P, ctypes.c_uint, _D, _D, _P, _P, _SZ, _P]),
     "spgemm_masked_workspace_bytes": (_SZ, [_MP, _MP]),
     "spgemm_masked": (_I, [_MP, _MP, _MP, ctypes.c_uint, _P, _P, _SZ, _P]),
     "b2sr_algo_workspace_bytes": (_SZ, [_MP, _I]),
@@ -245,14 +245,14 @@ _FULL_DTYPE = {PLUS_TIMES_F32: torch.float32, MIN_PLUS_F32: torch.float32, MIN_P
 
 
 def spmv_bin_full(A: B2SR, semiring: int, x, col_scale=None, mask=None, complement=False, self_loop=False,
-                  accumulate=False, alpha=1.0, beta=0.0, out=None, ws=None):
+                  accumulate=False, alpha=1.0, beta=0.0, out=None, ws=None, x_active=None):
     flags = (MASK_COMPLEMENT if complement else 0) | (SELF if self_loop else 0) | (ACCUMULATE if accumulate else 0)
     if out is None:
         out = torch.empty(A.n, dtype=_FULL_DTYPE[semiring], device="cuda")
     need = spmv_bin_full_workspace_bytes(A, semiring)
     if ws is None and need:
         ws = torch.empty(need, dtype=torch.uint8, device="cuda")
-    _check(lib().spmv_bin_full(A.view, semiring, _ptr(x), _ptr(col_scale), _ptr(mask), flags, float(alpha),
+    _check(lib().spmv_bin_full(A.view, semiring, _ptr(x), _ptr(col_scale), _ptr(x_active), _ptr(mask), flags, float(alpha),
                                float(beta), _ptr(out), _ptr(ws), need if ws is not None else 0, _stream()),
            "spmv_bin_full")
     return out

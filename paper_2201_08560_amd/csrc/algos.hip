@@ -92,51 +92,85 @@ __global__ void msbfs_init_kernel(uint32_t n, uint32_t nsrc, const uint32_t *src
 }
 
 __global__ void msbfs_seed_kernel(uint32_t n, uint32_t nsrc, const uint32_t *srcs, uint64_t *F, uint64_t *V,
-                                  uint32_t *levels)
+                                  uint32_t *levels, uint32_t *act)
 {
     // one thread seeds every source so repeated vertices (rejected on the host) cannot race
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (uint32_t s = 0; s < nsrc; ++s) {
             F[srcs[s]] |= 1ull << s;
             V[srcs[s]] |= 1ull << s;
+            act[srcs[s] >> 5] |= 1u << (srcs[s] & 31);
             levels[(size_t)s * n + srcs[s]] = 0;
         }
 }
 
+// Writes the bit vector of predicate p for vertices [base, base + 64) held one
+// per lane (base is a multiple of 64): two words, the second only if it exists.
+__device__ __forceinline__ void store_pred_bits(uint32_t *bits, uint64_t base, uint32_t n, bool p)
+{
+    const uint64_t m = __ballot(p);
+    const uint64_t w = base / 32 + lane_id();
+    if (lane_id() < 2 && w < (n + 31u) / 32u) bits[w] = (uint32_t)(m >> (32 * lane_id()));
+}
+
+// New frontier words: Y & ~V.  Marks them visited, records levels, and writes
+// the active bit vector (frontier word non-zero) for the next product.  Each
+// wave walks 64 consecutive vertices at a time, so the ballot forms whole words.
 __global__ void msbfs_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, uint64_t *V, uint32_t *levels,
-                                    uint32_t level, uint32_t *flag_now, uint32_t *flag_next)
+                                    uint32_t level, uint32_t *act, uint32_t *flag_now, uint32_t *flag_next)
 {
     bool any = false;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t y = Y[i] & ~V[i];
-        F[i] = y;
-        if (!y) continue;
-        any = true;
-        V[i] |= y;
-        while (y) {
-            const uint32_t s = __builtin_ctzll(y);
-            y &= y - 1;
-            levels[(size_t)s * n + i] = level;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
+         base += waves * 64) {
+        const uint64_t i = base + lane_id();
+        uint64_t y = 0;
+        if (i < n) {
+            y = Y[i] & ~V[i];
+            F[i] = y;
+            if (y) {
+                any = true;
+                V[i] |= y;
+                uint64_t b = y;
+                while (b) {
+                    const uint32_t s = __builtin_ctzll(b);
+                    b &= b - 1;
+                    levels[(size_t)s * n + i] = level;
+                }
+            }
         }
+        store_pred_bits(act, base, n, y != 0);
     }
     if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(flag_now, 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
 }
 
 // ---------------------------------------------------------------- SSSP / CC
-__global__ void sssp_init_kernel(uint32_t n, uint32_t src, float *d, uint32_t *flags)
+__global__ void sssp_init_kernel(uint32_t n, uint32_t src, float *d, uint32_t *act, uint32_t *flags)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    const uint32_t nw = (n + 31) / 32;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
         d[i] = i == src ? 0.0f : __builtin_huge_valf();
+        if (i < nw) act[i] = i == src / 32 ? 1u << (src % 32) : 0u;
+    }
     if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
 }
 
+// Entries that changed between two iterates: the active bit vector of the next
+// product and the convergence flag.
 template <class V>
-__global__ void changed_kernel(uint32_t n, const V *a, const V *b, uint32_t *flag_now, uint32_t *flag_next)
+__global__ void changed_kernel(uint32_t n, const V *a, const V *b, uint32_t *act, uint32_t *flag_now,
+                               uint32_t *flag_next)
 {
     bool diff = false;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        diff |= a[i] != b[i];
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
+         base += waves * 64) {
+        const uint64_t i = base + lane_id();
+        const bool d = i < n && a[i] != b[i];
+        diff |= d;
+        store_pred_bits(act, base, n, d);
+    }
     if (__syncthreads_or(diff) && threadIdx.x == 0) atomicOr(flag_now, 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
 }
@@ -199,7 +233,7 @@ struct Layout {
     uint32_t *srcs = nullptr;
     // SSSP / CC / PR
     float *f0 = nullptr, *f1 = nullptr, *f2 = nullptr;
-    uint32_t *u0 = nullptr, *ones = nullptr;
+    uint32_t *u0 = nullptr, *ones = nullptr, *act = nullptr;
     void *spmv_ws = nullptr;
     size_t spmv_ws_bytes = 0;
     uint32_t *flags = nullptr;
@@ -222,13 +256,16 @@ Layout carve(const b2sr_matrix *A, int algo, void *ws)
         L.V = c.take<uint64_t>(n * 8);
         L.Y = c.take<uint64_t>(n * 8);
         L.srcs = c.take<uint32_t>(64 * 4);
+        L.act = c.take<uint32_t>(nw * 4);
         break;
     case B2SR_ALGO_SSSP:
         L.f0 = c.take<float>(n * 4);
         L.f1 = c.take<float>(n * 4);
+        L.act = c.take<uint32_t>(nw * 4);
         break;
     case B2SR_ALGO_CC:
         L.u0 = c.take<uint32_t>(n * 4);
+        L.act = c.take<uint32_t>(nw * 4);
         break;
     case B2SR_ALGO_PAGERANK:
         L.f0 = c.take<float>(n * 4);  // z = r / deg
@@ -311,15 +348,17 @@ int b2sr_msbfs(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32
         return rc;
     msbfs_init_kernel<<<vgrid((uint64_t)nsrc * n), 256, 0, stream>>>(n, nsrc, L.srcs, L.F, L.V, levels, L.flags);
     if ((rc = b2sr::check_launch("msbfs_init_kernel"))) return rc;
-    msbfs_seed_kernel<<<1, 64, 0, stream>>>(n, nsrc, L.srcs, L.F, L.V, levels);
+    if ((rc = b2sr::fill_u32(L.act, b2sr::n_words(n), 0, stream))) return rc;
+    msbfs_seed_kernel<<<1, 64, 0, stream>>>(n, nsrc, L.srcs, L.F, L.V, levels, L.act);
     if ((rc = b2sr::check_launch("msbfs_seed_kernel"))) return rc;
     uint32_t level = 0;
     for (;;) {
         ++level;
-        if ((rc = spmv_bin_full(A, B2SR_OR_U64, L.F, nullptr, nullptr, 0, 0.0, 0.0, L.Y, nullptr, 0, stream)))
+        // only frontier words that are non-zero take part in the product
+        if ((rc = spmv_bin_full(A, B2SR_OR_U64, L.F, nullptr, L.act, nullptr, 0, 0.0, 0.0, L.Y, nullptr, 0, stream)))
             return rc;
         uint32_t *fnow = L.flags + (level & 1), *fnext = L.flags + ((level + 1) & 1);
-        msbfs_update_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, levels, level, fnow, fnext);
+        msbfs_update_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, levels, level, L.act, fnow, fnext);
         if ((rc = b2sr::check_launch("msbfs_update_kernel"))) return rc;
         uint32_t any = 0;
         if ((rc = read_flag(fnow, &any, stream))) return rc;
@@ -337,17 +376,19 @@ int b2sr_sssp(const b2sr_matrix *A, uint32_t src, uint32_t *dist, void *ws, size
     if (rc) return rc;
     if (!dist || src >= A->n) return B2SR_EINVAL;
     const uint32_t n = A->n;
-    sssp_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, L.f0, L.flags);
+    sssp_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, L.f0, L.act, L.flags);
     if ((rc = b2sr::check_launch("sssp_init_kernel"))) return rc;
     float *cur = L.f0, *nxt = L.f1;
     uint32_t it = 0;
     for (;;) {
         ++it;
-        if ((rc = spmv_bin_full(A, B2SR_MIN_PLUS_F32, cur, nullptr, nullptr, B2SR_SELF, 1.0, 0.0, nxt, nullptr, 0,
-                                stream)))
+        // only distances that changed last iteration can improve a neighbour; the
+        // others were folded in when they changed (the SELF term keeps x_i)
+        if ((rc = spmv_bin_full(A, B2SR_MIN_PLUS_F32, cur, nullptr, L.act, nullptr, B2SR_SELF, 1.0, 0.0, nxt, nullptr,
+                                0, stream)))
             return rc;
         uint32_t *fnow = L.flags + (it & 1), *fnext = L.flags + ((it + 1) & 1);
-        changed_kernel<float><<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, fnow, fnext);
+        changed_kernel<float><<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, L.act, fnow, fnext);
         if ((rc = b2sr::check_launch("changed_kernel"))) return rc;
         uint32_t any = 0;
         if ((rc = read_flag(fnow, &any, stream))) return rc;
@@ -369,15 +410,17 @@ int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, u
     const uint32_t n = A->n;
     iota_kernel<<<vgrid(n), 256, 0, stream>>>(n, labels, L.flags);
     if ((rc = b2sr::check_launch("iota_kernel"))) return rc;
+    ones_bits_kernel<<<vgrid(b2sr::n_words(n)), 256, 0, stream>>>(n, L.act);  // every label starts active
+    if ((rc = b2sr::check_launch("ones_bits_kernel"))) return rc;
     uint32_t *cur = labels, *nxt = L.u0;
     uint32_t it = 0;
     for (;;) {
         ++it;
-        if ((rc = spmv_bin_full(A, B2SR_MIN_PLUS_U32, cur, nullptr, nullptr, B2SR_SELF, 0.0, 0.0, nxt, nullptr, 0,
-                                stream)))
+        if ((rc = spmv_bin_full(A, B2SR_MIN_PLUS_U32, cur, nullptr, L.act, nullptr, B2SR_SELF, 0.0, 0.0, nxt, nullptr,
+                                0, stream)))
             return rc;
         uint32_t *fnow = L.flags + (it & 1), *fnext = L.flags + ((it + 1) & 1);
-        changed_kernel<uint32_t><<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, fnow, fnext);
+        changed_kernel<uint32_t><<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, L.act, fnow, fnext);
         if ((rc = b2sr::check_launch("changed_kernel"))) return rc;
         uint32_t any = 0;
         if ((rc = read_flag(fnow, &any, stream))) return rc;
@@ -411,8 +454,8 @@ int b2sr_pagerank(const b2sr_matrix *A, float damping, uint32_t iterations, floa
     for (uint32_t it = 0; it < iterations; ++it) {
         pr_scale_kernel<<<vgrid(n), 256, 0, stream>>>(n, r, L.f1, L.f0);
         if ((rc = b2sr::check_launch("pr_scale_kernel"))) return rc;
-        if ((rc = spmv_bin_full(A, B2SR_PLUS_TIMES_F32, L.f0, nullptr, nullptr, 0, damping, beta, r_next, L.spmv_ws,
-                                L.spmv_ws_bytes, stream)))
+        if ((rc = spmv_bin_full(A, B2SR_PLUS_TIMES_F32, L.f0, nullptr, nullptr, nullptr, 0, damping, beta, r_next,
+                                L.spmv_ws, L.spmv_ws_bytes, stream)))
             return rc;
         std::swap(r, r_next);
     }

@@ -45,6 +45,7 @@ struct BatchArgs {
     uint32_t n, ngroups, nitems, max_levels;
     Group g[kMaxGroups];
     uint64_t *F, *V, *Y;
+    uint32_t *act;     // bit vector: vertices whose frontier word is non-zero
     uint32_t *levels;  // n x 64, vertex-major
     uint32_t *flags;   // [0], [1]: per-level parity flags; [2]: levels run;
                        // [3]: barrier arrivals; [4]: barrier generation; [5]: barrier timed out
@@ -62,6 +63,7 @@ __global__ void batch_init_kernel(BatchArgs b)
         b.V[i] = 0;
         b.Y[i] = 0;
     }
+    for (uint64_t w = tid; w < (b.n + 31) / 32; w += stride) b.act[w] = 0;
     if (tid < 6) b.flags[tid] = 0;
 }
 
@@ -75,33 +77,49 @@ __global__ void batch_seed_kernel(BatchArgs b)
         if (v >= b.n || s >= 64) continue;  // out-of-range seeds are ignored
         atomicOr((unsigned long long *)b.F + v, 1ull << s);
         atomicOr((unsigned long long *)b.V + v, 1ull << s);
+        atomicOr(b.act + (v >> 5), 1u << (v & 31));
         b.levels[(size_t)v * 64 + s] = 0;
     }
 }
 
 // One vertex: take the new frontier bits, mark them visited, record their
-// level, and clear Y for the next level's product.  Returns whether any bit was new.
-__device__ __forceinline__ bool update_vertex(const BatchArgs &b, uint64_t i, uint32_t level)
+// level, and clear Y for the next level's product.  Returns the new frontier word.
+__device__ __forceinline__ uint64_t update_vertex(const BatchArgs &b, uint64_t i, uint32_t level)
 {
     uint64_t y = b.Y[i] & ~b.V[i];
     b.Y[i] = 0;
     b.F[i] = y;
-    if (!y) return false;
+    if (!y) return 0;
     b.V[i] |= y;
     uint32_t *lv = b.levels + i * 64;
-    while (y) {
-        const uint32_t s = __builtin_ctzll(y);
-        y &= y - 1;
+    uint64_t m = y;
+    while (m) {
+        const uint32_t s = __builtin_ctzll(m);
+        m &= m - 1;
         lv[s] = level;
     }
-    return true;
+    return y;
+}
+
+// Updates the vertices [base, base + 64) held one per lane (base a multiple of
+// 64) and writes their two words of the active bit vector.
+__device__ __forceinline__ bool update_group(const BatchArgs &b, uint64_t base, uint32_t level)
+{
+    const uint64_t i = base + lane_id();
+    const uint64_t y = i < b.n ? update_vertex(b, i, level) : 0;
+    const uint64_t m = __ballot(y != 0);
+    const uint64_t w = base / 32 + lane_id();
+    if (lane_id() < 2 && w < (b.n + 31u) / 32u) b.act[w] = (uint32_t)(m >> (32 * lane_id()));
+    return y != 0;
 }
 
 __global__ void batch_update_kernel(BatchArgs b, uint32_t level)
 {
     bool any = false;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.n; i += (uint64_t)gridDim.x * blockDim.x)
-        any |= update_vertex(b, i, level);
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < b.n;
+         base += waves * 64)
+        any |= update_group(b, base, level);
     if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(b.flags + (level & 1), 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         b.flags[(level + 1) & 1] = 0;
@@ -166,7 +184,6 @@ __global__ void __launch_bounds__(256) batch_persistent_kernel(BatchArgs b)
     const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     const uint32_t nwaves = gridDim.x * (blockDim.x / B2SR_WAVE);
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
     for (uint32_t level = 1; level <= b.max_levels; ++level) {
         for (uint32_t item = wave; item < b.nitems; item += nwaves) {
             uint32_t gi = 0;
@@ -183,7 +200,8 @@ __global__ void __launch_bounds__(256) batch_persistent_kernel(BatchArgs b)
         grid_barrier(b.flags);
         if (__hip_atomic_load(b.flags + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         bool any = false;
-        for (uint64_t i = tid; i < b.n; i += nthreads) any |= update_vertex(b, i, level);
+        for (uint64_t base = (uint64_t)wave * 64; base < b.n; base += (uint64_t)nwaves * 64)
+            any |= update_group(b, base, level);
         if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(b.flags + (level & 1), 1u);
         if (tid == 0) {
             b.flags[(level + 1) & 1] = 0;
@@ -197,7 +215,7 @@ __global__ void __launch_bounds__(256) batch_persistent_kernel(BatchArgs b)
 
 struct Layout {
     uint64_t *F, *V, *Y;
-    uint32_t *flags;
+    uint32_t *act, *flags;
     size_t bytes;
 };
 
@@ -214,6 +232,7 @@ Layout carve(uint32_t n, void *ws)
     L.F = (uint64_t *)take((size_t)n * 8);
     L.V = (uint64_t *)take((size_t)n * 8);
     L.Y = (uint64_t *)take((size_t)n * 8);
+    L.act = (uint32_t *)take(((size_t)n + 31) / 32 * 4);
     L.flags = (uint32_t *)take(32);
     L.bytes = off;
     return L;
@@ -235,6 +254,7 @@ int make_args(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t 
     b.F = L.F;
     b.V = L.V;
     b.Y = L.Y;
+    b.act = L.act;
     b.levels = levels;
     b.flags = L.flags;
     b.seed_vertex = seed_vertex;
@@ -257,6 +277,7 @@ int make_args(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t 
         g.p.chunk = A->tile == 4 ? or64_chunk<4>(A->ntiles) : A->tile == 8 ? or64_chunk<8>(A->ntiles)
                   : A->tile == 16 ? or64_chunk<16>(A->ntiles) : or64_chunk<32>(A->ntiles);
         g.p.x = L.F;
+        g.p.xact = L.act;  // only non-zero frontier words take part
         g.p.y = L.Y;
         g.p.flags = B2SR_ACCUMULATE;
         g.tile = A->tile;

@@ -189,8 +189,8 @@ size_t spmv_bin_full_workspace_bytes(const b2sr_matrix *A, int semiring)
 }
 
 int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float *col_scale,
-                  const uint32_t *mask, unsigned flags, double alpha, double beta, void *y, void *ws,
-                  size_t ws_bytes, hipStream_t stream)
+                  const uint32_t *x_active, const uint32_t *mask, unsigned flags, double alpha, double beta,
+                  void *y, void *ws, size_t ws_bytes, hipStream_t stream)
 {
     int rc = b2sr::validate_matrix(A);
     if (rc) return rc;
@@ -202,7 +202,7 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
         return B2SR_EINVAL;
     if (A->n > 0 && (!x || !y)) return B2SR_EINVAL;
     if (A->n == 0) return B2SR_OK;
-    if (x == y) return B2SR_EINVAL;
+    if (x == y || (const void *)x_active == y || (const void *)mask == y) return B2SR_EINVAL;
     // x segments are read as 16-byte vectors
     if (((uintptr_t)x & 15) || ((uintptr_t)col_scale & 15)) return B2SR_EINVAL;
     const size_t need = spmv_bin_full_workspace_bytes(A, semiring);
@@ -210,6 +210,7 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
     SpmvArgs p = make_args(A);
     p.x = x;
     p.s = col_scale;
+    p.xact = x_active;
     p.mask = mask;
     p.flags = flags;
     p.alpha = (float)alpha;

@@ -76,6 +76,7 @@ struct SpmvArgs {
     uint32_t n, ntr, ntiles, chunk;
     const void *x;
     const float *s;
+    const uint32_t *xact;  // value products: columns whose x entries take part (nullable: all)
     const uint32_t *mask;
     unsigned flags;
     float alpha, beta;
@@ -359,10 +360,25 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 for (int i = 0; i < U; ++i) seg[i] = shfl(Sr[(i * TPW) / 64], (int)((i * TPW + grp) % 64));
             }
         } else {
+            if (p.xact) {
+                // active columns only: a tile whose x segment is wholly inactive is not read
+                uint32_t Sr[JK];
 #pragma unroll
-            for (int i = 0; i < U; ++i) {
-                const uint32_t t = blk + i * TPW + grp;
-                pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
+                for (int k = 0; k < JK; ++k)
+                    Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>(p.xact, Jr[k]) : 0u;
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    const uint32_t ti = i * TPW + grp;
+                    seg[i] = shfl(Sr[(i * TPW) / 64], (int)(ti % 64));
+                    pc[i] = (blk + ti < t_end && seg[i]) ? load_piece<T>(p.bits, blk + ti, sub) : zero_piece<T>();
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    const uint32_t t = blk + i * TPW + grp;
+                    pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
+                    seg[i] = 0xFFFFFFFFu;
+                }
             }
             constexpr int QV = 16 / C::VB;  // values per 16-byte quad
             constexpr int NQ = XW / QV;
@@ -371,7 +387,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 const uint32_t ti = i * TPW + grp;
                 // every lane takes part in the shuffle; only then may lanes drop out
                 const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
-                if (blk + ti >= t_end) continue;
+                if (blk + ti >= t_end || !seg[i]) continue;
                 const size_t c0 = (size_t)J * T + sub * XW;
                 V *dst = xs + ti * T + sub * XW;
                 if (c0 + XW <= p.n) {
@@ -433,7 +449,10 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                     for (int k = 0; k < RPL; ++k) part[k] = KT::id();
                     uint32_t any = 0;
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) any |= a[k];
+                    for (int k = 0; k < RPL; ++k) {
+                        a[k] &= seg[i];  // inactive columns contribute the identity
+                        any |= a[k];
+                    }
                     if (any) {  // most lanes of a sparse tile hold no set bit
                         const V *xt = xs + ti * T;
 #pragma unroll

@@ -53,17 +53,18 @@ def test_spmv_argument_errors():
     assert L.spmv_bin_bin(A, None, None, 0, y, None) == -1                 # x NULL
     assert L.spmv_bin_bin(A, x, None, 0, None, None) == -1                 # y NULL
     assert L.spmv_bin_bin(A, x, None, 0x100, y, None) == -1                # unknown flag
-    assert L.spmv_bin_full(A, 1, ctypes.c_void_p(FAKE + 4), None, None, 0, 1.0, 0.0, y, None, 0, None) == -1  # x misaligned
+    assert L.spmv_bin_full(A, 1, ctypes.c_void_p(FAKE + 4), None, None, None, 0, 1.0, 0.0, y, None, 0, None) == -1  # x misaligned
     assert L.spmv_bin_bin(A, x, None, 0, x, None) == -1                    # y aliases x
-    assert L.spmv_bin_full(A, 9, x, None, None, 0, 1.0, 0.0, y, None, 0, None) == -5   # unknown semiring
-    assert L.spmv_bin_full(A, 1, x, None, None, b2.SELF, 1.0, 0.0, y, None, 0, None) == -1  # SELF on plus
-    assert L.spmv_bin_full(A, 3, x, None, None, 0, 1.5, 0.0, y, None, 0, None) == -1   # non-integral u32 weight
-    assert L.spmv_bin_full(A, 3, x, ctypes.c_void_p(FAKE), None, 0, 1.0, 0.0, y, None, 0, None) == -1  # scale on min
+    assert L.spmv_bin_full(A, 9, x, None, None, None, 0, 1.0, 0.0, y, None, 0, None) == -5   # unknown semiring
+    assert L.spmv_bin_full(A, 1, x, None, None, None, b2.SELF, 1.0, 0.0, y, None, 0, None) == -1  # SELF on plus
+    assert L.spmv_bin_full(A, 3, x, None, None, None, 0, 1.5, 0.0, y, None, 0, None) == -1   # non-integral u32 weight
+    assert L.spmv_bin_full(A, 3, x, ctypes.c_void_p(FAKE), None, None, 0, 1.0, 0.0, y, None, 0, None) == -1  # scale on min
     need = L.spmv_bin_full_workspace_bytes(A, 1)
     assert need > 0
-    assert L.spmv_bin_full(A, 1, x, None, None, 0, 1.0, 0.0, y, None, 0, None) == -3   # no workspace
-    assert L.spmv_bin_full(A, 1, x, None, None, 0, 1.0, 0.0, y, x, need - 1, None) == -3
+    assert L.spmv_bin_full(A, 1, x, None, None, None, 0, 1.0, 0.0, y, None, 0, None) == -3   # no workspace
+    assert L.spmv_bin_full(A, 1, x, None, None, None, 0, 1.0, 0.0, y, x, need - 1, None) == -3
     assert L.spmv_bin_full_workspace_bytes(A, 2) == 0
+    assert L.spmv_bin_full(A, 2, x, None, y, None, 0, 1.0, 0.0, y, None, 0, None) == -1   # x_active aliases y
 
 
 def test_spgemm_and_build_argument_errors():

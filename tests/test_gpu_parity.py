@@ -172,6 +172,35 @@ def test_spmv_plus_times_f32(gi, T):
     assert np.all(np.abs(yd.cpu().numpy() - ref) <= bound)
 
 
+@pytest.mark.parametrize("T", TILES)
+@pytest.mark.parametrize("gi", range(len(GRAPHS)), ids=IDS)
+def test_spmv_full_x_active(gi, T):
+    """Inactive x entries count as the identity; inactive tiles are skipped."""
+    g = GRAPHS[gi]
+    A = b2sr(g, T)
+    r = gg.rng(991 * gi + T)
+    for density in (0.0, 0.001, 0.05, 0.6):
+        act = r.random(g.n) < density
+        ad = dev_u32(pack_bits(act))
+        print(f"x_active {g.name} T={T} density={density}", flush=True)
+        # plus-times (integer-valued, so the sum is exact)
+        x = r.integers(-8, 9, g.n).astype(np.float32)
+        y = b2.spmv_bin_full(A, b2.PLUS_TIMES_F32, dev(x, torch.float32), x_active=ad).cpu().numpy()
+        assert np.array_equal(y, orc.spmv_plus(g, np.where(act, x, 0.0)).astype(np.float32))
+        # min-plus with the diagonal term, which reads every x_i
+        xf = r.integers(0, 40, g.n).astype(np.float32)
+        yf = b2.spmv_bin_full(A, b2.MIN_PLUS_F32, dev(xf, torch.float32), self_loop=True, alpha=1.0, x_active=ad)
+        ref = np.minimum(orc.spmv_min_plus(g, np.where(act, xf, np.inf), 1.0, False), xf).astype(np.float32)
+        assert np.array_equal(yf.cpu().numpy(), ref)
+        xu = r.integers(0, 1000, g.n).astype(np.uint32)
+        yu = b2.as_u32(b2.spmv_bin_full(A, b2.MIN_PLUS_U32, dev_u32(xu), self_loop=True, alpha=0, x_active=ad))
+        refu = np.minimum(orc.spmv_min_plus(g, np.where(act, xu.astype(np.float64), np.inf), 0.0, False), xu)
+        assert np.array_equal(yu, refu.astype(np.uint32))
+        x64 = r.integers(0, 2**63, g.n, dtype=np.uint64)
+        y64 = b2.as_u64(b2.spmv_bin_full(A, b2.OR_U64, torch.from_numpy(x64.view(np.int64)).cuda(), x_active=ad))
+        assert np.array_equal(y64, orc.spmv_or64(g, np.where(act, x64, np.uint64(0))))
+
+
 def test_plus_times_deterministic():
     g = gg.rmat(14, 16, seed=3)
     x = gg.rng(1).random(g.n).astype(np.float32)
