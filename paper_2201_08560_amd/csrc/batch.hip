@@ -133,12 +133,12 @@ template <int T> __global__ void __launch_bounds__(256) batch_product_kernel(Spm
     __shared__ __align__(16) uint64_t s_x[4 * kStageBytesPerWave / sizeof(uint64_t)];
     const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     if (wave >= nchunks) return;
-    spmv_chunk<T, kOr64>(p, wave, s_x + (threadIdx.x / B2SR_WAVE) * (kStageBytesPerWave / sizeof(uint64_t)));
+    spmv_chunk<T, kOr64, true>(p, wave, s_x + (threadIdx.x / B2SR_WAVE) * (kStageBytesPerWave / sizeof(uint64_t)));
 }
 
 template <int T> __device__ __forceinline__ void run_chunk(const Group &g, uint32_t c, uint64_t *xs)
 {
-    spmv_chunk<T, kOr64>(g.p, c, xs);
+    spmv_chunk<T, kOr64, true>(g.p, c, xs);
 }
 
 // Grid-wide barrier for the persistent kernel: block leaders count arrivals;

@@ -35,14 +35,14 @@ using namespace b2sr_core;
 
 namespace {
 
-template <int T, int K> __global__ void __launch_bounds__(256) spmv_kernel(SpmvArgs p)
+template <int T, int K, bool ACT> __global__ void __launch_bounds__(256) spmv_kernel(SpmvArgs p)
 {
     using V = typename KindTraits<K>::V;
     constexpr bool stage = Cfg<T, K>::kStage;
     __shared__ __align__(16) V s_x[stage ? 4 * kStageBytesPerWave / sizeof(V) : 1];
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     if (wave * p.chunk >= p.ntiles) return;
-    spmv_chunk<T, K>(p, (uint32_t)wave, s_x + (stage ? (threadIdx.x / B2SR_WAVE) * kStageBytesPerWave / sizeof(V) : 0));
+    spmv_chunk<T, K, ACT>(p, (uint32_t)wave, s_x + (stage ? (threadIdx.x / B2SR_WAVE) * kStageBytesPerWave / sizeof(V) : 0));
 }
 
 // Float sums of rows that straddle chunks.  One thread per (chunk, row of a
@@ -116,7 +116,12 @@ template <int T, int K> int launch(SpmvArgs p, hipStream_t stream)
         if (int rc = b2sr::check_launch("init kernel")) return rc;
     }
     if (nchunks == 0) return B2SR_OK;
-    spmv_kernel<T, K><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
+    if constexpr (Cfg<T, K>::kStage) {
+        if (p.xact) spmv_kernel<T, K, true><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
+        else spmv_kernel<T, K, false><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
+    } else {
+        spmv_kernel<T, K, false><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
+    }
     if (int rc = b2sr::check_launch("spmv_kernel")) return rc;
     if constexpr (K == kPlusF32) {
         plus_fixup_kernel<T><<<b2sr::grid_for((uint64_t)nchunks * T, 256), 256, 0, stream>>>(p, nchunks);

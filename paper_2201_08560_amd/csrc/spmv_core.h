@@ -274,7 +274,7 @@ constexpr uint32_t kStageBytesPerWave = B2SR_STAGE_BYTES;
 
 // Processes tile chunk chunk_id (wave-uniform) of the product described by p.
 // xs is this wave's LDS slice (unused by bit and count products).
-template <int T, int K>
+template <int T, int K, bool ACT = false>
 __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id, typename KindTraits<K>::V *xs)
 {
     using C = Cfg<T, K>;
@@ -360,7 +360,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 for (int i = 0; i < U; ++i) seg[i] = shfl(Sr[(i * TPW) / 64], (int)((i * TPW + grp) % 64));
             }
         } else {
-            if (p.xact) {
+            if constexpr (ACT) {
                 // active columns only: a tile whose x segment is wholly inactive is not read
                 uint32_t Sr[JK];
 #pragma unroll
@@ -377,7 +377,6 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 for (int i = 0; i < U; ++i) {
                     const uint32_t t = blk + i * TPW + grp;
                     pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
-                    seg[i] = 0xFFFFFFFFu;
                 }
             }
             constexpr int QV = 16 / C::VB;  // values per 16-byte quad
@@ -387,7 +386,10 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 const uint32_t ti = i * TPW + grp;
                 // every lane takes part in the shuffle; only then may lanes drop out
                 const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
-                if (blk + ti >= t_end || !seg[i]) continue;
+                if (blk + ti >= t_end) continue;
+                if constexpr (ACT) {
+                    if (!seg[i]) continue;
+                }
                 const size_t c0 = (size_t)J * T + sub * XW;
                 V *dst = xs + ti * T + sub * XW;
                 if (c0 + XW <= p.n) {
@@ -450,7 +452,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                     uint32_t any = 0;
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
-                        a[k] &= seg[i];  // inactive columns contribute the identity
+                        if constexpr (ACT) a[k] &= seg[i];  // inactive columns contribute the identity
                         any |= a[k];
                     }
                     if (any) {  // most lanes of a sparse tile hold no set bit
