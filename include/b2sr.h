@@ -301,16 +301,21 @@ int b2sr_msbfs_batch(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, ui
                      unsigned mode, void *ws, size_t ws_bytes, uint32_t *iters,
                      hipStream_t stream);
 
-/* A plan instantiates the persistent batched BFS (initialisation, seeding and
- * the cooperative kernel) as a hipGraph once; each launch replays it with one
- * hipGraphLaunch.  The plan keeps the pointers it was created with: rewrite
- * the seed arrays in device memory between launches to run other sources.
- * plan_launch synchronises `stream` only when iters is not NULL. */
+/* A plan instantiates the batched BFS as hipGraphs once; each launch replays
+ * them.  mode B2SR_BATCH_LEVELS: the first graph holds the initialisation, the
+ * seeding and 32 levels of per-level kernels, and a second graph 32 more
+ * levels; the level count and a finished flag live on the device, so levels
+ * after the BFS has finished return at once, and plan_launch replays the second
+ * graph until the device reports the BFS finished (it synchronises `stream`).
+ * mode B2SR_BATCH_PERSISTENT: one graph of initialisation, seeding and the
+ * persistent kernel; plan_launch synchronises only when iters is not NULL.
+ * The plan keeps the pointers it was created with: rewrite the seed arrays in
+ * device memory between launches to run other sources. */
 typedef struct b2sr_msbfs_plan_s *b2sr_msbfs_plan;
 int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups,
                                  uint32_t nseeds, const uint32_t *seed_vertex,
-                                 const uint32_t *seed_bit, uint32_t *levels, void *ws,
-                                 size_t ws_bytes, hipStream_t stream, b2sr_msbfs_plan *plan);
+                                 const uint32_t *seed_bit, uint32_t *levels, unsigned mode,
+                                 void *ws, size_t ws_bytes, b2sr_msbfs_plan *plan);
 int b2sr_msbfs_batch_plan_launch(b2sr_msbfs_plan plan, uint32_t *iters, hipStream_t stream);
 int b2sr_msbfs_batch_plan_destroy(b2sr_msbfs_plan plan);
 

@@ -85,7 +85,8 @@ _SIGS = {
     "b2sr_pagerank": (_I, [_MP, ctypes.c_float, _U32, _P, _P, _SZ, _P]),
     "b2sr_msbfs_batch_workspace_bytes": (_SZ, [_U32]),
     "b2sr_msbfs_batch": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, ctypes.c_uint, _P, _SZ, ctypes.POINTER(_U32), _P]),
-    "b2sr_msbfs_batch_plan_create": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, _P, _SZ, _P, ctypes.POINTER(_P)]),
+    "b2sr_msbfs_batch_plan_create": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, ctypes.c_uint, _P, _SZ,
+                                          ctypes.POINTER(_P)]),
     "b2sr_msbfs_batch_plan_launch": (_I, [_P, ctypes.POINTER(_U32), _P]),
     "b2sr_msbfs_batch_plan_destroy": (_I, [_P]),
 }
@@ -365,10 +366,12 @@ def b2sr_msbfs_batch(n: int, groups, seed_vertex, seed_bit, mode=BATCH_LEVELS, o
 
 
 class MsbfsPlan:
-    """The persistent batched BFS instantiated once as a hipGraph (see b2sr.h)."""
+    """The batched BFS instantiated once as hipGraphs and replayed (b2sr.h):
+    per-level kernels (BATCH_LEVELS) or the persistent kernel (BATCH_PERSISTENT)."""
 
-    def __init__(self, n: int, groups, seed_vertex, seed_bit, out=None, ws=None):
+    def __init__(self, n: int, groups, seed_vertex, seed_bit, mode=BATCH_LEVELS, out=None, ws=None):
         self.n = n
+        self.mode = mode
         self.groups = list(groups)
         self.seed_vertex, self.seed_bit = seed_vertex, seed_bit
         self.out = torch.empty((n, 64), dtype=torch.int32, device="cuda") if out is None else out
@@ -377,8 +380,8 @@ class MsbfsPlan:
         self._views = _views(self.groups)
         h = _P()
         _check(lib().b2sr_msbfs_batch_plan_create(n, len(self.groups), self._views, seed_vertex.numel(),
-                                                  _ptr(seed_vertex), _ptr(seed_bit), _ptr(self.out), _ptr(self.ws),
-                                                  need, _stream(), ctypes.byref(h)), "b2sr_msbfs_batch_plan_create")
+                                                  _ptr(seed_vertex), _ptr(seed_bit), _ptr(self.out), mode,
+                                                  _ptr(self.ws), need, ctypes.byref(h)), "b2sr_msbfs_batch_plan_create")
         self._h = h
 
     def launch(self, want_iters: bool = False):

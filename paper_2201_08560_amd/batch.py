@@ -68,8 +68,8 @@ class GraphBatch:
     def run(self, mode=BATCH_LEVELS, out=None, ws=None):
         return b2sr_msbfs_batch(self.n, self.groups, self.seed_vertex, self.seed_bit, mode, out, ws)
 
-    def plan(self, out=None, ws=None) -> MsbfsPlan:
-        return MsbfsPlan(self.n, self.groups, self.seed_vertex, self.seed_bit, out, ws)
+    def plan(self, mode=BATCH_LEVELS, out=None, ws=None) -> MsbfsPlan:
+        return MsbfsPlan(self.n, self.groups, self.seed_vertex, self.seed_bit, mode, out, ws)
 
     def levels_of(self, levels: torch.Tensor, i: int) -> torch.Tensor:
         """Levels of graph i as a (nsrc, n_i) device tensor, the layout of b2sr_msbfs."""

@@ -48,7 +48,8 @@ struct BatchArgs {
     uint32_t *act;     // bit vector: vertices whose frontier word is non-zero
     uint32_t *levels;  // n x 64, vertex-major
     uint32_t *flags;   // [0], [1]: per-level parity flags; [2]: levels run;
-                       // [3]: barrier arrivals; [4]: barrier generation; [5]: barrier timed out
+                       // [3]: barrier arrivals; [4]: barrier generation; [5]: barrier timed out;
+                       // [6]: BFS finished (per-level kernels return at once)
     const uint32_t *seed_vertex, *seed_bit;
     uint32_t nseeds;
 };
@@ -64,7 +65,7 @@ __global__ void batch_init_kernel(BatchArgs b)
         b.Y[i] = 0;
     }
     for (uint64_t w = tid; w < (b.n + 31) / 32; w += stride) b.act[w] = 0;
-    if (tid < 6) b.flags[tid] = 0;
+    if (tid < 8) b.flags[tid] = 0;
 }
 
 // Seeds are distinct (vertex, bit) pairs, so the level writes never collide and
@@ -113,24 +114,38 @@ __device__ __forceinline__ bool update_group(const BatchArgs &b, uint64_t base, 
     return y != 0;
 }
 
-__global__ void batch_update_kernel(BatchArgs b, uint32_t level)
+// Per-level kernels keep the level count and the finished flag on the device,
+// so a fixed sequence of levels can be replayed from a hipGraph: once the BFS
+// has finished, every later kernel returns at once.
+__global__ void batch_update_kernel(BatchArgs b)
 {
+    if (b.flags[6]) return;
+    const uint32_t level = b.flags[2] + 1;
     bool any = false;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
     for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < b.n;
          base += waves * 64)
         any |= update_group(b, base, level);
     if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(b.flags + (level & 1), 1u);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        b.flags[(level + 1) & 1] = 0;
-        b.flags[2] = level;
-    }
 }
 
-// One group's product for one level (B2SR_BATCH_LEVELS): one wave per chunk.
-template <int T> __global__ void __launch_bounds__(256) batch_product_kernel(SpmvArgs p, uint32_t nchunks)
+// One thread: count the level, finish when it found nothing (or the level
+// bound is reached), and clear the next level's flag.
+__global__ void batch_advance_kernel(uint32_t *flags, uint32_t max_levels)
+{
+    if (flags[6]) return;
+    const uint32_t level = flags[2] + 1;
+    flags[2] = level;
+    if (!flags[level & 1] || level >= max_levels) flags[6] = 1;
+    flags[(level + 1) & 1] = 0;
+}
+
+// One group's product for one level (per-level modes): one wave per chunk.
+template <int T>
+__global__ void __launch_bounds__(256) batch_product_kernel(SpmvArgs p, uint32_t nchunks, const uint32_t *flags)
 {
     __shared__ __align__(16) uint64_t s_x[4 * kStageBytesPerWave / sizeof(uint64_t)];
+    if (flags[6]) return;
     const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     if (wave >= nchunks) return;
     spmv_chunk<T, kOr64, true>(p, wave, s_x + (threadIdx.x / B2SR_WAVE) * (kStageBytesPerWave / sizeof(uint64_t)));
@@ -348,13 +363,83 @@ int finish_persistent(const BatchArgs &b, uint32_t *iters, hipStream_t s)
     return B2SR_OK;
 }
 
+// One level: each group's product, the update, the advance (stream order).
+int launch_level(const BatchArgs &b, hipStream_t stream)
+{
+    for (uint32_t k = 0; k < b.ngroups; ++k) {
+        const Group &g = b.g[k];
+        if (!g.nchunks) continue;
+        const unsigned grid = b2sr::grid_for(g.nchunks, 4);
+        switch (g.tile) {
+        case 4: batch_product_kernel<4><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
+        case 8: batch_product_kernel<8><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
+        case 16: batch_product_kernel<16><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
+        default: batch_product_kernel<32><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
+        }
+        if (int rc = b2sr::check_launch("batch_product_kernel")) return rc;
+    }
+    batch_update_kernel<<<b2sr::grid_for(b.n, 256, 1024), 256, 0, stream>>>(b);
+    if (int rc = b2sr::check_launch("batch_update_kernel")) return rc;
+    batch_advance_kernel<<<1, 1, 0, stream>>>(b.flags, b.max_levels);
+    return b2sr::check_launch("batch_advance_kernel");
+}
+
+// Levels per graph replay of a per-level plan.
+constexpr uint32_t kPlanLevels = 32;
+
 }  // namespace
 
 struct b2sr_msbfs_plan_s {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    unsigned mode = 0;
+    hipGraph_t first = nullptr, more = nullptr;  // first replay (init, seeds, levels); continuation (levels)
+    hipGraphExec_t first_exec = nullptr, more_exec = nullptr;
     BatchArgs args{};
 };
+
+namespace {
+
+int add_node(hipGraph_t g, hipGraphNode_t *last, const void *func, unsigned grid, unsigned block, void **params,
+             hipGraphNode_t *out = nullptr)
+{
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void *>(func);
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(block);
+    kp.kernelParams = params;
+    hipGraphNode_t node = nullptr;
+    const int rc = b2sr::check(hipGraphAddKernelNode(&node, g, *last ? last : nullptr, *last ? 1 : 0, &kp),
+                               "hipGraphAddKernelNode");
+    if (!rc) {
+        *last = node;
+        if (out) *out = node;
+    }
+    return rc;
+}
+
+// Appends `levels` levels (products, update, advance) after *last.
+int add_levels(hipGraph_t g, hipGraphNode_t *last, BatchArgs &b, uint32_t levels)
+{
+    void *args_b[] = {&b};
+    void *args_adv[] = {&b.flags, &b.max_levels};
+    for (uint32_t l = 0; l < levels; ++l) {
+        for (uint32_t k = 0; k < b.ngroups; ++k) {
+            Group &gr = b.g[k];
+            if (!gr.nchunks) continue;
+            void *args_p[] = {&gr.p, &gr.nchunks, &b.flags};
+            const void *f = gr.tile == 4    ? (const void *)batch_product_kernel<4>
+                            : gr.tile == 8  ? (const void *)batch_product_kernel<8>
+                            : gr.tile == 16 ? (const void *)batch_product_kernel<16>
+                                            : (const void *)batch_product_kernel<32>;
+            if (int rc = add_node(g, last, f, b2sr::grid_for(gr.nchunks, 4), 256, args_p)) return rc;
+        }
+        if (int rc = add_node(g, last, (const void *)batch_update_kernel, b2sr::grid_for(b.n, 256, 1024), 256, args_b))
+            return rc;
+        if (int rc = add_node(g, last, (const void *)batch_advance_kernel, 1, 1, args_adv)) return rc;
+    }
+    return B2SR_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -373,81 +458,55 @@ int b2sr_msbfs_batch(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, ui
         if ((rc = launch_persistent(b, stream))) return rc;
         return finish_persistent(b, iters, stream);
     }
-    uint32_t level = 0;
-    for (;;) {
-        ++level;
-        for (uint32_t k = 0; k < b.ngroups; ++k) {
-            const Group &g = b.g[k];
-            if (!g.nchunks) continue;
-            const unsigned grid = b2sr::grid_for(g.nchunks, 4);
-            switch (g.tile) {
-            case 4: batch_product_kernel<4><<<grid, 256, 0, stream>>>(g.p, g.nchunks); break;
-            case 8: batch_product_kernel<8><<<grid, 256, 0, stream>>>(g.p, g.nchunks); break;
-            case 16: batch_product_kernel<16><<<grid, 256, 0, stream>>>(g.p, g.nchunks); break;
-            default: batch_product_kernel<32><<<grid, 256, 0, stream>>>(g.p, g.nchunks); break;
-            }
-            if ((rc = b2sr::check_launch("spmv_kernel (batch)"))) return rc;
-        }
-        batch_update_kernel<<<b2sr::grid_for(b.n, 256, 1024), 256, 0, stream>>>(b, level);
-        if ((rc = b2sr::check_launch("batch_update_kernel"))) return rc;
-        uint32_t any = 0;
-        if ((rc = read_u32(b.flags + (level & 1), &any, stream))) return rc;
-        if (!any || level > b.max_levels) break;
-    }
-    if (iters) *iters = level;
+    uint32_t h[8] = {0};
+    do {
+        if ((rc = launch_level(b, stream))) return rc;
+        if ((rc = b2sr::check(hipMemcpyAsync(h, b.flags, sizeof h, hipMemcpyDeviceToHost, stream), "hipMemcpyAsync")))
+            return rc;
+        if ((rc = b2sr::check(hipStreamSynchronize(stream), "hipStreamSynchronize"))) return rc;
+    } while (!h[6]);
+    if (iters) *iters = h[2];
     return B2SR_OK;
 }
 
 int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t nseeds,
-                                 const uint32_t *seed_vertex, const uint32_t *seed_bit, uint32_t *levels, void *ws,
-                                 size_t ws_bytes, hipStream_t stream, b2sr_msbfs_plan *plan)
+                                 const uint32_t *seed_vertex, const uint32_t *seed_bit, uint32_t *levels, unsigned mode,
+                                 void *ws, size_t ws_bytes, b2sr_msbfs_plan *plan)
 {
     if (!plan) return B2SR_EINVAL;
     *plan = nullptr;
+    if (mode != B2SR_BATCH_LEVELS && mode != B2SR_BATCH_PERSISTENT) return B2SR_EINVAL;
     b2sr_msbfs_plan_s *P = new (std::nothrow) b2sr_msbfs_plan_s();
     if (!P) return B2SR_ENOSPC;
+    P->mode = mode;
     int rc = make_args(n, ngroups, groups, nseeds, seed_vertex, seed_bit, levels, ws, ws_bytes, &P->args);
-    unsigned grid = 0;
-    if (!rc) rc = persistent_grid(&grid);
-    if (!rc) rc = b2sr::check(hipGraphCreate(&P->graph, 0), "hipGraphCreate");
-    hipGraphNode_t n_init = nullptr, n_seed = nullptr, n_run = nullptr;
-    void *args[] = {&P->args};
-    if (!rc) {
-        hipKernelNodeParams kp{};
-        kp.func = (void *)batch_init_kernel;
-        kp.gridDim = dim3(vgrid((uint64_t)n * 64));
-        kp.blockDim = dim3(256);
-        kp.kernelParams = args;
-        rc = b2sr::check(hipGraphAddKernelNode(&n_init, P->graph, nullptr, 0, &kp), "hipGraphAddKernelNode(init)");
+    BatchArgs &b = P->args;
+    void *args_b[] = {&b};
+    hipGraphNode_t last = nullptr;
+    if (!rc) rc = b2sr::check(hipGraphCreate(&P->first, 0), "hipGraphCreate");
+    if (!rc) rc = add_node(P->first, &last, (const void *)batch_init_kernel, vgrid((uint64_t)n * 64), 256, args_b);
+    if (!rc && nseeds) rc = add_node(P->first, &last, (const void *)batch_seed_kernel, vgrid(nseeds), 256, args_b);
+    if (!rc && mode == B2SR_BATCH_PERSISTENT) {
+        unsigned grid = 0;
+        hipGraphNode_t run = nullptr;
+        rc = persistent_grid(&grid);
+        if (!rc) rc = add_node(P->first, &last, (const void *)batch_persistent_kernel, grid, 256, args_b, &run);
+        if (!rc) {
+            // ask for co-residency checks where the runtime offers them; the barrier
+            // itself needs no runtime support and the grid is sized to be resident
+            hipKernelNodeAttrValue v{};
+            v.cooperative = 1;
+            if (hipGraphKernelNodeSetAttribute(run, hipKernelNodeAttributeCooperative, &v) != hipSuccess)
+                (void)hipGetLastError();
+        }
+    } else if (!rc) {
+        rc = add_levels(P->first, &last, b, kPlanLevels);
+        hipGraphNode_t last2 = nullptr;
+        if (!rc) rc = b2sr::check(hipGraphCreate(&P->more, 0), "hipGraphCreate");
+        if (!rc) rc = add_levels(P->more, &last2, b, kPlanLevels);
+        if (!rc) rc = b2sr::check(hipGraphInstantiate(&P->more_exec, P->more, nullptr, nullptr, 0), "hipGraphInstantiate");
     }
-    hipGraphNode_t last = n_init;
-    if (!rc && nseeds) {
-        hipKernelNodeParams kp{};
-        kp.func = (void *)batch_seed_kernel;
-        kp.gridDim = dim3(vgrid(nseeds));
-        kp.blockDim = dim3(256);
-        kp.kernelParams = args;
-        rc = b2sr::check(hipGraphAddKernelNode(&n_seed, P->graph, &last, 1, &kp), "hipGraphAddKernelNode(seed)");
-        last = n_seed;
-    }
-    if (!rc) {
-        hipKernelNodeParams kp{};
-        kp.func = (void *)batch_persistent_kernel;
-        kp.gridDim = dim3(grid);
-        kp.blockDim = dim3(256);
-        kp.kernelParams = args;
-        rc = b2sr::check(hipGraphAddKernelNode(&n_run, P->graph, &last, 1, &kp), "hipGraphAddKernelNode(persistent)");
-    }
-    if (!rc) {
-        // ask for co-residency checks where the runtime offers them; the barrier
-        // itself needs no runtime support and the grid is sized to be resident
-        hipKernelNodeAttrValue v{};
-        v.cooperative = 1;
-        if (hipGraphKernelNodeSetAttribute(n_run, hipKernelNodeAttributeCooperative, &v) != hipSuccess)
-            (void)hipGetLastError();
-    }
-    if (!rc) rc = b2sr::check(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-    (void)stream;
+    if (!rc) rc = b2sr::check(hipGraphInstantiate(&P->first_exec, P->first, nullptr, nullptr, 0), "hipGraphInstantiate");
     if (rc) {
         b2sr_msbfs_batch_plan_destroy(P);
         return rc;
@@ -458,10 +517,21 @@ int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix
 
 int b2sr_msbfs_batch_plan_launch(b2sr_msbfs_plan plan, uint32_t *iters, hipStream_t stream)
 {
-    if (!plan || !plan->exec) return B2SR_EINVAL;
-    int rc = b2sr::check(hipGraphLaunch(plan->exec, stream), "hipGraphLaunch");
+    if (!plan || !plan->first_exec) return B2SR_EINVAL;
+    int rc = b2sr::check(hipGraphLaunch(plan->first_exec, stream), "hipGraphLaunch");
     if (rc) return rc;
-    if (iters) return finish_persistent(plan->args, iters, stream);
+    if (plan->mode == B2SR_BATCH_PERSISTENT) return iters ? finish_persistent(plan->args, iters, stream) : B2SR_OK;
+    // per-level plan: replay the continuation until the device says the BFS finished
+    uint32_t h[8] = {0};
+    for (;;) {
+        if ((rc = b2sr::check(hipMemcpyAsync(h, plan->args.flags, sizeof h, hipMemcpyDeviceToHost, stream),
+                              "hipMemcpyAsync")))
+            return rc;
+        if ((rc = b2sr::check(hipStreamSynchronize(stream), "hipStreamSynchronize"))) return rc;
+        if (h[6]) break;
+        if ((rc = b2sr::check(hipGraphLaunch(plan->more_exec, stream), "hipGraphLaunch"))) return rc;
+    }
+    if (iters) *iters = h[2];
     return B2SR_OK;
 }
 
@@ -469,11 +539,11 @@ int b2sr_msbfs_batch_plan_destroy(b2sr_msbfs_plan plan)
 {
     if (!plan) return B2SR_OK;
     int rc = B2SR_OK;
-    if (plan->exec) rc = b2sr::check(hipGraphExecDestroy(plan->exec), "hipGraphExecDestroy");
-    if (plan->graph) {
-        int r2 = b2sr::check(hipGraphDestroy(plan->graph), "hipGraphDestroy");
-        if (!rc) rc = r2;
-    }
+    auto keep = [&](int r) { if (!rc) rc = r; };
+    if (plan->first_exec) keep(b2sr::check(hipGraphExecDestroy(plan->first_exec), "hipGraphExecDestroy"));
+    if (plan->more_exec) keep(b2sr::check(hipGraphExecDestroy(plan->more_exec), "hipGraphExecDestroy"));
+    if (plan->first) keep(b2sr::check(hipGraphDestroy(plan->first), "hipGraphDestroy"));
+    if (plan->more) keep(b2sr::check(hipGraphDestroy(plan->more), "hipGraphDestroy"));
     delete plan;
     return rc;
 }

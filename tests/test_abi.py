@@ -142,8 +142,10 @@ def test_batch_argument_errors():
     bad = (b2.b2sr_matrix * 1)(mat(tile=5))
     assert L.b2sr_msbfs_batch(64, 1, bad, 1, p, p, p, 0, p, need, ctypes.byref(it), None) == -1
     h = ctypes.c_void_p(0)
-    assert L.b2sr_msbfs_batch_plan_create(64, 2, groups, 1, p, p, p, p, need, None, None) == -1
-    assert L.b2sr_msbfs_batch_plan_create(64, 0, groups, 1, p, p, p, p, need, None, ctypes.byref(h)) == -1
+    assert L.b2sr_msbfs_batch_plan_create(64, 2, groups, 1, p, p, p, 0, p, need, None) == -1
+    assert L.b2sr_msbfs_batch_plan_create(64, 0, groups, 1, p, p, p, 0, p, need, ctypes.byref(h)) == -1
+    assert L.b2sr_msbfs_batch_plan_create(64, 2, groups, 1, p, p, p, 7, p, need, ctypes.byref(h)) == -1  # bad mode
+    assert h.value is None
     assert L.b2sr_msbfs_batch_plan_launch(None, None, None) == -1
     assert L.b2sr_msbfs_batch_plan_destroy(None) == 0
 

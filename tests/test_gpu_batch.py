@@ -68,17 +68,22 @@ def test_batch_persistent_mode(batch):
     check_all(batch, lv)
 
 
-def test_batch_graph_plan_replays(batch):
+@pytest.mark.parametrize("mode", ["levels", "persistent"])
+def test_batch_graph_plan_replays(batch, mode):
     """The hipGraph plan replayed three times, with eager work and a change of
-    sources between replays; every replay matches the eager result."""
-    eager, _ = batch.run(b2.BATCH_LEVELS)
+    sources between replays; every replay matches the eager result.  The path
+    graph needs hundreds of levels, so the per-level plan replays its
+    continuation graph many times."""
+    eager, eager_it = batch.run(b2.BATCH_LEVELS)
     eager = eager.clone()
-    plan = batch.plan()
+    plan = batch.plan(b2.BATCH_LEVELS if mode == "levels" else b2.BATCH_PERSISTENT)
     try:
         for rep in range(3):
-            plan.launch()
+            it = plan.launch(want_iters=(rep == 1))
             torch.cuda.synchronize()
             assert torch.equal(plan.out, eager), rep
+            if rep == 1:
+                assert it == eager_it
             junk = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work between replays
             torch.cuda.synchronize()
             del junk
