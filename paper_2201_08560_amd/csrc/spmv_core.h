@@ -127,6 +127,17 @@ template <int T> __device__ __forceinline__ typename PieceT<T>::type load_piece(
     else return load_stream((const uint32_t *)bits + t);
 }
 
+// 128 zero bytes, the stand-in tile of lanes that skip their tile: every lane
+// issues every load of a block, so waits count the loads exactly.
+static __device__ __align__(16) uint32_t g_zero_tile[32];
+
+// The piece of tile t when `use`, else the same piece of the zero tile.
+template <int T>
+__device__ __forceinline__ typename PieceT<T>::type load_piece_or_zero(const void *bits, uint32_t t, uint32_t sub, bool use)
+{
+    return load_piece<T>(use ? bits : (const void *)g_zero_tile, use ? t : 0u, sub);
+}
+
 template <int T> __device__ __forceinline__ typename PieceT<T>::type zero_piece()
 {
     typename PieceT<T>::type z;
@@ -325,37 +336,54 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
             blk = min(r_end, t_end);
             continue;
         }
-        // ---- load phase: tile pieces, tile columns (one per lane), x segments
+        // ---- load phase: tile columns (one per lane), tile pieces, x segments.
+        // No load sits under a per-lane branch (lanes past the chunk read its
+        // last column and the zero tile), so a wait covers just the loads it needs:
+        // the column loads come first, and the x reads that depend on them are
+        // issued while the tile pieces are still in flight.
         uint32_t Jr[JK];
 #pragma unroll
-        for (int k = 0; k < JK; ++k) {
-            const uint32_t tk = blk + 64 * k + lane;
-            Jr[k] = tk < t_end ? p.tci[tk] : 0u;
-        }
+        for (int k = 0; k < JK; ++k) Jr[k] = p.tci[min(blk + 64 * k + lane, t_end - 1)];
         Piece pc[U];
         uint32_t seg[U];
         if constexpr (!C::kStage) {
             uint32_t Sr[JK];
+            // (At T = 32 the measured best is a per-lane branch for the sparse
+            // hint and a clamped tile index for the dense case; below T = 32 the
+            // zero tile in both.)
             if (p.flags & B2SR_SPARSE_X) {
                 // read a tile only when its x segment has a set bit
 #pragma unroll
-                for (int k = 0; k < JK; ++k)
-                    Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>((const uint32_t *)p.x, Jr[k]) : 0u;
+                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k]);
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
                     const uint32_t ti = i * TPW + grp;
                     seg[i] = shfl(Sr[(i * TPW) / 64], (int)(ti % 64));
-                    pc[i] = (blk + ti < t_end && seg[i]) ? load_piece<T>(p.bits, blk + ti, sub) : zero_piece<T>();
+                    const bool use = blk + ti < t_end && seg[i];
+                    if constexpr (T == 32) pc[i] = use ? load_piece<T>(p.bits, blk + ti, sub) : zero_piece<T>();
+                    else pc[i] = load_piece_or_zero<T>(p.bits, blk + ti, sub, use);
+                }
+            } else if constexpr (T == 32) {
+                // lanes past the chunk read its last tile; their segment is cleared
+#pragma unroll
+                for (int i = 0; i < U; ++i) pc[i] = load_piece<T>(p.bits, min(blk + i * TPW + grp, t_end - 1), sub);
+#pragma unroll
+                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k]);
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    const uint32_t ti = i * TPW + grp;
+                    seg[i] = shfl(Sr[(i * TPW) / 64], (int)(ti % 64));
+                    if (blk + ti >= t_end) seg[i] = 0;
                 }
             } else {
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
                     const uint32_t t = blk + i * TPW + grp;
-                    pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
+                    pc[i] = load_piece_or_zero<T>(p.bits, t, sub, t < t_end);
                 }
+                // a tile past the chunk holds no bits, whatever its segment
 #pragma unroll
-                for (int k = 0; k < JK; ++k)
-                    Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>((const uint32_t *)p.x, Jr[k]) : 0u;
+                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k]);
 #pragma unroll
                 for (int i = 0; i < U; ++i) seg[i] = shfl(Sr[(i * TPW) / 64], (int)((i * TPW + grp) % 64));
             }
@@ -364,52 +392,81 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 // active columns only: a tile whose x segment is wholly inactive is not read
                 uint32_t Sr[JK];
 #pragma unroll
-                for (int k = 0; k < JK; ++k)
-                    Sr[k] = blk + 64 * k + lane < t_end ? bit_segment<T>(p.xact, Jr[k]) : 0u;
+                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>(p.xact, Jr[k]);
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
                     const uint32_t ti = i * TPW + grp;
                     seg[i] = shfl(Sr[(i * TPW) / 64], (int)(ti % 64));
-                    pc[i] = (blk + ti < t_end && seg[i]) ? load_piece<T>(p.bits, blk + ti, sub) : zero_piece<T>();
+                    pc[i] = load_piece_or_zero<T>(p.bits, blk + ti, sub, blk + ti < t_end && seg[i]);
                 }
             } else {
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
                     const uint32_t t = blk + i * TPW + grp;
-                    pc[i] = t < t_end ? load_piece<T>(p.bits, t, sub) : zero_piece<T>();
+                    pc[i] = load_piece_or_zero<T>(p.bits, t, sub, t < t_end);
                 }
             }
+            // x segments: every lane reads its XW values of every step's segment as
+            // 16-byte quads, all steps at once; a lane whose tile is skipped reads
+            // x's first quad instead (its tile holds no bits, so the values are
+            // never selected).  A segment cut by n (the last tile column) is
+            // completed value by value afterwards.
             constexpr int QV = 16 / C::VB;  // values per 16-byte quad
             constexpr int NQ = XW / QV;
+            const bool quads = p.n >= (uint32_t)XW;
+            u32x4 xq[U][NQ];
+            uint32_t off[U];
+            uint32_t partial = 0;
 #pragma unroll
             for (int i = 0; i < U; ++i) {
                 const uint32_t ti = i * TPW + grp;
-                // every lane takes part in the shuffle; only then may lanes drop out
                 const uint32_t J = shfl(Jr[(i * TPW) / 64], (int)(ti % 64));
-                if (blk + ti >= t_end) continue;
-                if constexpr (ACT) {
-                    if (!seg[i]) continue;
-                }
-                const size_t c0 = (size_t)J * T + sub * XW;
-                V *dst = xs + ti * T + sub * XW;
-                if (c0 + XW <= p.n) {
-                    const u32x4 *src = (const u32x4 *)((const V *)p.x + c0);
+                bool use = blk + ti < t_end;
+                if constexpr (ACT) use = use && seg[i];
+                const uint32_t c0 = J * T + sub * XW;  // < n + T <= 2^32
+                const bool full = (uint64_t)c0 + XW <= p.n;
+                off[i] = use && full ? c0 : 0u;
+                partial |= (uint32_t)(use && !full) << i;
+            }
+            if (quads) {
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
-                        u32x4 v = src[q];
-                        if constexpr (K == kPlusF32) {
-                            if (p.s) {
-                                const u32x4 sv = ((const u32x4 *)(p.s + c0))[q];
+                for (int i = 0; i < U; ++i)
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) xq[i][q] = ((const u32x4 *)((const V *)p.x + off[i]))[q];
+                if constexpr (K == kPlusF32) {
+                    if (p.s) {
+#pragma unroll
+                        for (int i = 0; i < U; ++i)
+#pragma unroll
+                            for (int q = 0; q < NQ; ++q) {
+                                const u32x4 sv = ((const u32x4 *)(p.s + off[i]))[q];
+                                u32x4 &v = xq[i][q];
                                 v.x = __float_as_uint(__uint_as_float(v.x) * __uint_as_float(sv.x));
                                 v.y = __float_as_uint(__uint_as_float(v.y) * __uint_as_float(sv.y));
                                 v.z = __float_as_uint(__uint_as_float(v.z) * __uint_as_float(sv.z));
                                 v.w = __float_as_uint(__uint_as_float(v.w) * __uint_as_float(sv.w));
                             }
-                        }
-                        ((u32x4 *)dst)[q] = v;
                     }
-                } else {
-                    // the last, partial tile column: values past n are never selected
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < U; ++i)
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) xq[i][q] = u32x4{0u, 0u, 0u, 0u};
+            }
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                V *dst = xs + (i * TPW + grp) * T + sub * XW;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) ((u32x4 *)dst)[q] = xq[i][q];
+            }
+            if (partial) {
+                // only the last tile column can be cut by n; values past n are never selected
+                const uint32_t c0 = (p.n - 1) / T * T + sub * XW;
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    if (!((partial >> i) & 1u)) continue;
+                    V *dst = xs + (i * TPW + grp) * T + sub * XW;
                     for (int q = 0; q < XW; ++q) {
                         V v = KT::id();
                         if (c0 + q < p.n) {
