@@ -326,6 +326,76 @@ def profile_mode(args):
                     "kernel_source_digest": source_digest()}))
 
 
+def serving_section(pool, qps: float, seconds: float, budget_bytes: int, seed: int = 77, mix=(0.6, 0.15, 0.15, 0.1),
+                    workers: int = 2, streams: int = 4):
+    """Poisson stream of BFS/SSSP/CC/TC queries over a resident pool of R-MAT
+    graphs; continuous batching with admission by a device-memory budget."""
+    from paper_2201_08560_amd import autotune
+    from paper_2201_08560_amd.serve import GpuExecutor, Query, Server
+    t0 = time.perf_counter()
+    tiles = [autotune.choose_tile(g, nsample=256)[0] for g in pool]
+    mats = [(b2.B2SR.from_graph(g, t), b2.B2SR.from_graph(g, GpuExecutor.tc_tile(t), lower=True))
+            for g, t in zip(pool, tiles)]
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t0
+    pool_bytes = sum(A.nbytes + L.nbytes for A, L in mats)
+    log(f"serving pool: {len(pool)} graphs resident, {pool_bytes / 2**30:.2f} GiB B2SR, {load_s:.1f} s")
+    ex = GpuExecutor(mats, pool, streams=streams, workers=workers)
+    r = np.random.default_rng(seed)
+    nq = int(qps * seconds)
+    arrivals = np.cumsum(r.exponential(1.0 / qps, nq))
+    kinds = r.choice(np.array(["bfs", "sssp", "cc", "tc"]), p=list(mix), size=nq)
+    gidx = r.integers(len(pool), size=nq)
+    cand = [np.flatnonzero(g.degrees() > 0) for g in pool]
+    queries = [Query(i, str(kinds[i]), int(gidx[i]), int(r.choice(cand[gidx[i]])), float(arrivals[i]))
+               for i in range(nq)]
+    # warm-up: one query of each kind on a small graph (first launches of each kernel)
+    small = int(np.argmin([g.n for g in pool]))
+    warm = Server(ex, budget_bytes, cache=False)
+    warm.run([Query(-1 - k, kind, small, int(cand[small][0]), 0.0) for k, kind in enumerate(("bfs", "sssp", "cc", "tc"))])
+    torch.cuda.synchronize()
+    sample = {}
+    count = [0]
+
+    def on_done(q):
+        count[0] += 1
+        if count[0] % 500 == 0:
+            log(f"serving: {count[0]}/{nq} queries finished")
+        if q.status == "done" and q.qid % 40 == 0:
+            sample[q.qid] = (q, q.result)
+
+    srv = Server(ex, budget_bytes, on_done=on_done, keep_results=False)
+    t1 = time.perf_counter()
+    srv.run(queries)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    st = srv.stats()
+    # answers of the sample against the single-query drivers, run alone afterwards
+    same = True
+    for qid, (q, res) in sorted(sample.items()):
+        A = mats[q.graph][0]
+        if q.kind == "bfs":
+            ref = b2.b2sr_bfs(A, q.source)[0]
+        elif q.kind == "sssp":
+            ref = b2.b2sr_sssp(A, q.source)[0]
+        elif q.kind == "cc":
+            ref = b2.b2sr_cc(A)[0]
+        else:
+            L = mats[q.graph][1]
+            same &= int(b2.as_u64(res)[0]) == int(b2.as_u64(b2.spgemm_masked(L, L, L))[0])
+            continue
+        same &= bool(torch.equal(res, ref))
+    ex.shutdown()
+    st["job_seconds"] = dict(ex.job_seconds)
+    st["job_count"] = dict(ex.job_count)
+    joined = sum(1 for q in srv.done if q.kind == "bfs" and q.joined_step)
+    st.update({"offered_qps": qps, "window_s": seconds, "wall_s": wall, "pool_graphs": len(pool),
+               "pool_scales": sorted({int(np.log2(g.n)) for g in pool}), "pool_bytes": pool_bytes,
+               "pool_load_s": load_s, "tile_histogram": {str(T): tiles.count(T) for T in (4, 8, 16, 32)},
+               "bfs_joined_running_session": joined, "sampled": len(sample), "sample_identical_alone": bool(same)})
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,15 +404,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-mode", action="store_true")
+    ap.add_argument("--serve-qps", type=float, default=400.0)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=1.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
-    batch_graphs = None
+    batch_graphs = pool_graphs = None
     if not args.no_extras and not args.profile_mode and args.gpus == 1 and world == 1:
         # generated in worker processes before this process touches the GPU
         t0 = time.perf_counter()
         batch_graphs = gg.chung_lu_batch(256, 2.1, seed=1000, workers=min(8, os.cpu_count() or 1))
         log(f"batched workload: {len(batch_graphs)} graphs in {time.perf_counter() - t0:.1f} s, "
             f"n={sum(g.n for g in batch_graphs)} nnz={sum(g.nnz for g in batch_graphs)}")
+        t0 = time.perf_counter()
+        pool_graphs = gg.rmat_pool(64, seed=2000, workers=min(8, os.cpu_count() or 1))
+        log(f"serving pool: {len(pool_graphs)} R-MAT graphs in {time.perf_counter() - t0:.1f} s, "
+            f"nnz={sum(g.nnz for g in pool_graphs)}")
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE={world}) is not supported: this build "
               "runs the B2SR path on a single MI355X.", file=sys.stderr)
@@ -384,7 +461,7 @@ def main():
                                "4 single products + 64-source BFS + SSSP + CC + 50 PageRank iterations",
                    "n": g.n, "nnz": g.nnz, "tile": 32, "ntiles": w.A.ntiles, "products_per_step": w.products,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "spmv_bits_kernel<32> (masked bin x bin SpMV, full frontier)",
+        "roofline": {"bound": "hbm", "kernel": "spmv_kernel<32, 0, false> (masked bin x bin SpMV, full frontier)",
                      "achieved": alg / kt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / kt / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg, "ms_per_launch": kt * 1e3, "gteps": g.nnz / kt / 1e9,
@@ -396,6 +473,8 @@ def main():
         out["bfs_single_source"] = bfs_gteps(w)
         out["tc"] = tc_section()
         out["batched"] = batched_section(batch_graphs)
+        out["serving"] = serving_section(pool_graphs, args.serve_qps, args.serve_seconds,
+                                         int(args.serve_budget_gib * 2**30))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, edges_per_step)
     print(json.dumps(out), flush=True)

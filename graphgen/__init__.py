@@ -302,3 +302,30 @@ def sample_sources(csr: Csr, k: int, seed: int) -> np.ndarray:
 def random_mask(n: int, density: float, seed: int) -> np.ndarray:
     """Boolean vector with each entry set independently with ``density``."""
     return rng(seed).random(n) < density
+
+
+def rmat_pool_params(count: int = 64, seed: int = 2000):
+    """Scales uniform in 12..20 and edge factors uniform in 8..32, seeded."""
+    g = rng(seed)
+    return g.integers(12, 21, size=count), g.integers(8, 33, size=count)
+
+
+def _rmat_job(args):
+    i, scale, ef, seed = args
+    return rmat(int(scale), int(ef), seed=seed + i)
+
+
+def rmat_pool(count: int = 64, seed: int = 2000, workers: int = 8):
+    """The serving pool: ``count`` R-MAT graphs (parameters from
+    rmat_pool_params; graph i drawn with seed ``seed + i``), generated in worker
+    processes, largest first."""
+    from concurrent.futures import ProcessPoolExecutor
+    scales, efs = rmat_pool_params(count, seed)
+    jobs = [(i, scales[i], efs[i], seed) for i in range(count)]
+    order = sorted(range(count), key=lambda i: -(int(efs[i]) << int(scales[i])))
+    if workers <= 1:
+        out = {i: _rmat_job(jobs[i]) for i in order}
+    else:
+        with ProcessPoolExecutor(workers) as ex:
+            out = dict(zip(order, ex.map(_rmat_job, [jobs[i] for i in order])))
+    return [out[i] for i in range(count)]

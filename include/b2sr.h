@@ -319,6 +319,43 @@ int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix
 int b2sr_msbfs_batch_plan_launch(b2sr_msbfs_plan plan, uint32_t *iters, hipStream_t stream);
 int b2sr_msbfs_batch_plan_destroy(b2sr_msbfs_plan plan);
 
+/* ---- serving: continuous multi-source BFS sessions ------------------------
+ * A session keeps the BFS state of up to 64 queries on one graph, one per bit
+ * of a 64-bit frontier word per vertex (the Boolean-semiring product of
+ * Sec. V's BFS, Table V, applied to 64 vectors at once).  Bit lanes are
+ * independent, so queries need not start or finish together:
+ *   join(slot, source): the query in `slot` starts from `source` at the
+ *     session's current step (the slot must be free; slot < 64, source < n);
+ *   step: one BFS level for every query in the session: Y = A (x) F over the
+ *     non-zero frontier words, new = Y & ~V, V |= new, F = new.  When
+ *     alive_host is not NULL, the 64-bit word whose bit s is set when slot s
+ *     reached a new vertex in this step is copied to *alive_host (host memory,
+ *     pinned for an asynchronous copy) in stream order; a query whose bit is 0
+ *     in the first step after it joined, or in any later one, has finished;
+ *   extract(slot, levels): writes the finished query's BFS levels (uint32_t[n],
+ *     device; 0xFFFFFFFF = unreached) and frees the slot; levels == NULL just
+ *     frees it (a cancelled query);
+ *   info: steps run so far and the mask of busy slots.
+ * ws: b2sr_bfs_session_bytes(n) bytes of device memory, owned by the caller
+ * and used until destroy.  Calls on one session must use one stream (or be
+ * ordered by the caller); sessions on different graphs or streams are
+ * independent.  create zeroes the state on `stream`; destroy frees only the
+ * host-side handle.  Errors: EINVAL (bad slot, busy slot on join, free slot on
+ * extract, source >= n, NULL handle), ENOSPC (workspace too small), ERANGE
+ * (step counter exhausted), EHIP.
+ */
+typedef struct b2sr_bfs_session_s *b2sr_bfs_session;
+size_t b2sr_bfs_session_bytes(uint32_t n);
+int b2sr_bfs_session_create(const b2sr_matrix *A, void *ws, size_t ws_bytes, hipStream_t stream,
+                            b2sr_bfs_session *session);
+int b2sr_bfs_session_join(b2sr_bfs_session session, uint32_t slot, uint32_t source,
+                          hipStream_t stream);
+int b2sr_bfs_session_step(b2sr_bfs_session session, uint64_t *alive_host, hipStream_t stream);
+int b2sr_bfs_session_extract(b2sr_bfs_session session, uint32_t slot, uint32_t *levels,
+                             hipStream_t stream);
+int b2sr_bfs_session_info(b2sr_bfs_session session, uint32_t *step, uint64_t *busy);
+int b2sr_bfs_session_destroy(b2sr_bfs_session session);
+
 #ifdef __cplusplus
 }
 #endif

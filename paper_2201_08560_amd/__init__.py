@@ -22,7 +22,8 @@ __all__ = [
     "spmv_bin_full", "spmv_bin_full_workspace_bytes", "spgemm_masked", "spgemm_masked_workspace_bytes",
     "b2sr_algo_workspace_bytes", "b2sr_bfs", "b2sr_msbfs", "b2sr_sssp", "b2sr_cc", "b2sr_pagerank",
     "triangle_count", "b2sr_strerror", "as_u32", "as_u64", "header_functions", "FLAGS", "SEMIRINGS",
-    "b2sr_msbfs_batch", "b2sr_msbfs_batch_workspace_bytes", "MsbfsPlan",
+    "b2sr_msbfs_batch", "b2sr_msbfs_batch_workspace_bytes", "MsbfsPlan", "BfsSession",
+    "b2sr_bfs_session_bytes",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -89,6 +90,13 @@ _SIGS = {
                                           ctypes.POINTER(_P)]),
     "b2sr_msbfs_batch_plan_launch": (_I, [_P, ctypes.POINTER(_U32), _P]),
     "b2sr_msbfs_batch_plan_destroy": (_I, [_P]),
+    "b2sr_bfs_session_bytes": (_SZ, [_U32]),
+    "b2sr_bfs_session_create": (_I, [_MP, _P, _SZ, _P, ctypes.POINTER(_P)]),
+    "b2sr_bfs_session_join": (_I, [_P, _U32, _U32, _P]),
+    "b2sr_bfs_session_step": (_I, [_P, _P, _P]),
+    "b2sr_bfs_session_extract": (_I, [_P, _U32, _P, _P]),
+    "b2sr_bfs_session_info": (_I, [_P, ctypes.POINTER(_U32), ctypes.POINTER(_U64)]),
+    "b2sr_bfs_session_destroy": (_I, [_P]),
 }
 
 
@@ -393,6 +401,88 @@ class MsbfsPlan:
     def close(self):
         if self._h is not None and _lib is not None:
             _check(lib().b2sr_msbfs_batch_plan_destroy(self._h), "b2sr_msbfs_batch_plan_destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- serving: continuous multi-source BFS sessions ---------------------------
+
+def b2sr_bfs_session_bytes(n: int) -> int:
+    return int(lib().b2sr_bfs_session_bytes(n))
+
+
+class BfsSession:
+    """Up to 64 BFS queries on one graph sharing 64-bit frontier words; queries
+    join and leave between levels (b2sr.h).  Every call is issued on
+    ``stream`` (a torch.cuda.Stream; the current stream when None).  One step
+    is in flight at a time: ``step()`` copies the step's alive word to pinned
+    host memory and records an event; ``ready()`` polls it."""
+
+    SLOTS = 64
+
+    def __init__(self, A: B2SR, ws=None, stream=None):
+        self.A = A
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._s = ctypes.c_void_p(self.stream.cuda_stream)
+        need = b2sr_bfs_session_bytes(A.n)
+        if ws is None:
+            with torch.cuda.stream(self.stream):  # the allocator then orders reuse after this stream's work
+                ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        self.ws = ws
+        if self.ws.numel() < need:
+            raise ValueError("session workspace too small")
+        self._alive = torch.zeros(1, dtype=torch.int64).pin_memory()
+        self._event = torch.cuda.Event()
+        self._pending = False
+        h = _P()
+        _check(lib().b2sr_bfs_session_create(A.view, _ptr(self.ws), need, self._s, ctypes.byref(h)),
+               "b2sr_bfs_session_create")
+        self._h = h
+
+    def join(self, slot: int, source: int):
+        _check(lib().b2sr_bfs_session_join(self._h, slot, source, self._s), "b2sr_bfs_session_join")
+
+    def step(self):
+        _check(lib().b2sr_bfs_session_step(self._h, ctypes.c_void_p(self._alive.data_ptr()), self._s),
+               "b2sr_bfs_session_step")
+        self._event.record(self.stream)
+        self._pending = True
+
+    def ready(self) -> bool:
+        return not self._pending or self._event.query()
+
+    def alive(self) -> int:
+        """The alive word of the last step (waits for it)."""
+        if self._pending:
+            self._event.synchronize()
+            self._pending = False
+        return int(self._alive.numpy().view(np.uint64)[0])
+
+    def extract(self, slot: int, out=None):
+        """Levels of the finished query in ``slot`` (int32 tensor with uint32
+        bits, 0xFFFFFFFF = unreached); frees the slot."""
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty(self.A.n, dtype=torch.int32, device="cuda")
+        _check(lib().b2sr_bfs_session_extract(self._h, slot, _ptr(out), self._s), "b2sr_bfs_session_extract")
+        return out
+
+    def cancel(self, slot: int):
+        _check(lib().b2sr_bfs_session_extract(self._h, slot, None, self._s), "b2sr_bfs_session_extract")
+
+    def info(self):
+        st, busy = _U32(0), _U64(0)
+        _check(lib().b2sr_bfs_session_info(self._h, ctypes.byref(st), ctypes.byref(busy)), "b2sr_bfs_session_info")
+        return st.value, busy.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _check(lib().b2sr_bfs_session_destroy(self._h), "b2sr_bfs_session_destroy")
         self._h = None
 
     def __del__(self):

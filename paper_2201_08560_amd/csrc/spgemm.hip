@@ -18,6 +18,8 @@
 //   * Lanes accumulate in 64-bit registers; one atomic add per wave at the end.
 // For triangle counting (A = Bt = M = L, the strict lower triangle) row I of L
 // is read once per workgroup and Bt's rows are re-read from L2/MALL.
+#include <type_traits>
+
 #include "common.h"
 
 using namespace b2sr_dev;
@@ -36,6 +38,11 @@ template <int T> __device__ __forceinline__ uint32_t load_word(const void *bits,
     else return ((const uint8_t *)bits)[idx];
 }
 
+#ifndef B2SR_TC_UB
+#define B2SR_TC_UB 4
+#endif
+constexpr int kUB = B2SR_TC_UB;  // Bt tile columns per lane per round
+
 struct GemmArgs {
     const uint32_t *a_rp, *a_ci;
     const void *a_bits;
@@ -46,6 +53,31 @@ struct GemmArgs {
     uint32_t ntr;
     unsigned long long *sum;
 };
+
+// sum over the listed mask bits (r, c) of popcount(A_tile[r] & Bt_tile[c]) for
+// the tiles at positions ia (A) and kb (Bt).  Tiles of T <= 8 are loaded whole
+// (T bytes) once; wider tiles are read a row at a time.
+template <int T>
+__device__ __forceinline__ uint32_t pair_sum(const GemmArgs &g, size_t ia, uint32_t kb, const uint16_t *pairs,
+                                             uint32_t npairs)
+{
+    uint32_t part = 0;
+    if constexpr (T <= 8) {
+        using W = typename std::conditional<T == 8, uint64_t, uint32_t>::type;
+        const W a = ((const W *)g.a_bits)[ia], b = ((const W *)g.b_bits)[kb];
+        for (uint32_t q = 0; q < npairs; ++q) {
+            const uint32_t rc = pairs[q];
+            part += __popc((uint32_t)((a >> (8 * (rc >> 8))) & (b >> (8 * (rc & 0xFFu)))) & 0xFFu);
+        }
+    } else {
+        const size_t abase = ia * T, bbase = (size_t)kb * T;
+        for (uint32_t q = 0; q < npairs; ++q) {
+            const uint32_t rc = pairs[q];
+            part += __popc(load_word<T>(g.a_bits, abase + (rc >> 8)) & load_word<T>(g.b_bits, bbase + (rc & 0xFFu)));
+        }
+    }
+    return part;
+}
 
 template <int T> __global__ void __launch_bounds__(kThreads) spgemm_masked_kernel(GemmArgs g)
 {
@@ -134,20 +166,24 @@ template <int T> __global__ void __launch_bounds__(kThreads) spgemm_masked_kerne
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const uint32_t b0 = g.b_rp[J], b1 = g.b_rp[J + 1];
-            for (uint32_t kb = b0 + lane; kb < b1 + ((b1 - b0) % 64 ? 64 - (b1 - b0) % 64 : 0); kb += 64) {
-                int64_t ia = -1;
-                if (kb < b1) ia = lookup(g.b_ci[kb]);
-                if (ia >= 0) {
-                    const size_t abase = (size_t)ia * T, bbase = (size_t)kb * T;
-                    uint32_t part = 0;
-                    for (uint32_t q = 0; q < npairs; ++q) {
-                        const uint32_t rc = s_pairs[wv][q];
-                        part += __popc(load_word<T>(g.a_bits, abase + (rc >> 8)) &
-                                       load_word<T>(g.b_bits, bbase + (rc & 0xFFu)));
-                    }
-                    acc += part;
+            // Bt's tile-row J, kUB tile columns per lane per round: the column
+            // loads and lookups of a round are independent, so they overlap
+            unsigned long long part = 0;
+            for (uint32_t base = b0; base < b1; base += 64 * kUB) {
+                uint32_t kb[kUB], K[kUB];
+#pragma unroll
+                for (int u = 0; u < kUB; ++u) {
+                    kb[u] = base + 64 * u + lane;
+                    K[u] = g.b_ci[min(kb[u], b1 - 1)];
                 }
+                int64_t ia[kUB];
+#pragma unroll
+                for (int u = 0; u < kUB; ++u) ia[u] = kb[u] < b1 ? lookup(K[u]) : -1;
+#pragma unroll
+                for (int u = 0; u < kUB; ++u)
+                    if (ia[u] >= 0) part += pair_sum<T>(g, (size_t)ia[u], kb[u], s_pairs[wv], npairs);
             }
+            acc += part;
             __builtin_amdgcn_wave_barrier();
         }
     }

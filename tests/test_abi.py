@@ -162,3 +162,24 @@ def test_sampling_profile_closed_form():
     m = gg.cycle(1000)
     est = autotune.sampling_profile(m.rowptr, m.colind, m.n, nsample=500, seed=3)
     assert est[32] < est[4] * 8  # monotone sanity: wider tiles share chunks between neighbours
+
+
+def test_session_argument_errors():
+    """Serving sessions reject bad handles and sizes on the host."""
+    n = 1000
+    need = L.b2sr_bfs_session_bytes(n)
+    assert need >= n * (3 * 8 + 64 * 4)
+    assert L.b2sr_bfs_session_bytes(2 * n) > need
+    A = mat(n=n, tile=8)
+    h = ctypes.c_void_p(0)
+    assert L.b2sr_bfs_session_create(ctypes.byref(A), None, need, None, None) == -1       # no handle out
+    assert L.b2sr_bfs_session_create(ctypes.byref(A), None, need, None, ctypes.byref(h)) == -3   # no workspace
+    assert L.b2sr_bfs_session_create(ctypes.byref(A), FAKE, need - 1, None, ctypes.byref(h)) == -3
+    bad = mat(n=n, tile=5)
+    assert L.b2sr_bfs_session_create(ctypes.byref(bad), FAKE, need, None, ctypes.byref(h)) == -1
+    assert h.value is None
+    assert L.b2sr_bfs_session_join(None, 0, 0, None) == -1
+    assert L.b2sr_bfs_session_step(None, None, None) == -1
+    assert L.b2sr_bfs_session_extract(None, 0, None, None) == -1
+    assert L.b2sr_bfs_session_info(None, None, None) == -1
+    assert L.b2sr_bfs_session_destroy(None) == 0
