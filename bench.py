@@ -396,6 +396,19 @@ def serving_section(pool, qps: float, seconds: float, budget_bytes: int, seed: i
     return st
 
 
+def profile_tc(args):
+    """A short fixed program for rocprofv3: --steps masked SpGEMM triangle counts
+    each on R-MAT s18 ef16 at T = 8 and on the 2048 x 2048 king grid at T = 32
+    (the best tile width of each)."""
+    for name, g, T in (("rmat18_ef16", gg.rmat(18, 16, seed=18), 8), ("king2048", gg.king_grid(2048, 2048), 32)):
+        L = b2.B2SR.from_graph(g, T, lower=True)
+        s = b2.spgemm_masked(L, L, L)
+        for _ in range(args.steps):
+            b2.spgemm_masked(L, L, L, out=s)
+        torch.cuda.synchronize()
+        log(json.dumps({"profile_tc": name, "tile": T, "triangles": int(b2.as_u64(s)[0])}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,13 +417,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-mode", action="store_true")
+    ap.add_argument("--profile-tc", action="store_true")
     ap.add_argument("--serve-qps", type=float, default=400.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-budget-gib", type=float, default=1.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     batch_graphs = pool_graphs = None
-    if not args.no_extras and not args.profile_mode and args.gpus == 1 and world == 1:
+    if not args.no_extras and not args.profile_mode and not args.profile_tc and args.gpus == 1 and world == 1:
         # generated in worker processes before this process touches the GPU
         t0 = time.perf_counter()
         batch_graphs = gg.chung_lu_batch(256, 2.1, seed=1000, workers=min(8, os.cpu_count() or 1))
@@ -430,6 +444,9 @@ def main():
     torch.cuda.set_device(0)
     if args.profile_mode:
         profile_mode(args)
+        return
+    if args.profile_tc:
+        profile_tc(args)
         return
 
     log("generating R-MAT s20 ef16 ...")
