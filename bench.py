@@ -190,7 +190,10 @@ def tc_section(reps: int = 3) -> dict:
                 torch.cuda.synchronize()
                 ts.append(e0.elapsed_time(e1) / 1e3)
             t = float(np.median(ts))
-            res[f"T{T}"] = {"triangles": int(b2.as_u64(s)[0]), "ms": 1e3 * t, "edges_per_s": g.edges / t}
+            work = b2.spgemm_masked_profile(L, L, L)
+            res[f"T{T}"] = {"triangles": int(b2.as_u64(s)[0]), "ms": 1e3 * t, "edges_per_s": g.edges / t,
+                            "work": work, "row_pairs_per_s": work["row_pairs"] / t,
+                            "lookups_per_s": work["lookups"] / t}
             del L
         out[name] = res
     return out
@@ -254,7 +257,33 @@ def batched_section(graphs, reps: int = 3) -> dict:
             "speedup_best_batched_vs_per_graph": res["per_graph"]["ms"] / res[best]["ms"]}
 
 
-def cpu_baseline(w: Workload, edges_per_step: float) -> dict:
+def cold_warm(w: "Workload", reps: int = 5) -> dict:
+    """The headline product timed warm (back to back) and cold (a 1 GiB write
+    between launches evicts the 256 MB Infinity Cache and the L2s)."""
+    scrub = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+
+    def one():
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b2.spmv_bin_bin(w.A, w.x_full, w.mask, complement=True, accumulate=True, out=w.y_bits)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    one()
+    warm = float(np.median([one() for _ in range(reps)]))
+    cold = []
+    for k in range(reps):
+        scrub.fill_(k)
+        torch.cuda.synchronize()
+        cold.append(one())
+    cold = float(np.median(cold))
+    alg = spmv_bytes(w.A, True)
+    return {"warm_ms": 1e3 * warm, "cold_ms": 1e3 * cold, "warm_frac": alg / warm / 1e9 / HBM_PEAK_GBS,
+            "cold_frac": alg / cold / 1e9 / HBM_PEAK_GBS, "scrub_bytes": scrub.numel()}
+
+
+def cpu_baseline(w: Workload, edges_per_step: float, threads: int | None = None, min_s: float = 10.0) -> dict:
     """The oracle on the host: the same step's results (64 BFS, SSSP, CC,
     PageRank x 50 and the four single products), timed once."""
     import oracle as orc
@@ -267,9 +296,12 @@ def cpu_baseline(w: Workload, edges_per_step: float) -> dict:
     xf = r.random(n)
     xd = np.where(r.random(n) < 0.5, r.integers(0, 20, n), np.inf).astype(np.float64)
     orc.lib()
+    saved = orc.num_threads()
+    if threads is not None:
+        orc.set_num_threads(threads)
     reps = 0
     t0 = time.perf_counter()
-    while True:  # whole steps until at least 10 s of host work
+    while True:  # whole steps until at least min_s of host work
         orc.spmv_or(g, ones, mask, True)
         orc.spmv_count(g, ones)
         orc.spmv_plus(g, xf)
@@ -279,10 +311,12 @@ def cpu_baseline(w: Workload, edges_per_step: float) -> dict:
         orc.cc(g)
         orc.pagerank(g, 0.85, 50)
         reps += 1
-        if time.perf_counter() - t0 >= 10.0:
+        if time.perf_counter() - t0 >= min_s:
             break
     dt = (time.perf_counter() - t0) / reps
-    return {"value": edges_per_step / dt / 1e9, "unit": "GTEPS", "cores": orc.num_threads(), "kind": "oracle",
+    cores = orc.num_threads()
+    orc.set_num_threads(saved)
+    return {"value": edges_per_step / dt / 1e9, "unit": "GTEPS", "cores": cores, "kind": "oracle",
             "sample": f"{reps} full steps of the same workload (R-MAT s20: 4 single products, 64 BFS, SSSP, CC, "
                       f"PageRank x 50), {dt:.2f} s wall each"}
 
@@ -492,8 +526,13 @@ def main():
         out["batched"] = batched_section(batch_graphs)
         out["serving"] = serving_section(pool_graphs, args.serve_qps, args.serve_seconds,
                                          int(args.serve_budget_gib * 2**30))
+    if not args.no_extras:
+        out["headline_cold_warm"] = cold_warm(w)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, edges_per_step)
+        if not args.no_extras:
+            log("cpu baseline on one thread ...")
+            out["cpu_baseline_1thread"] = cpu_baseline(w, edges_per_step, threads=1, min_s=1.0)
     print(json.dumps(out), flush=True)
 
 

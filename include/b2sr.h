@@ -226,6 +226,17 @@ size_t spgemm_masked_workspace_bytes(const b2sr_matrix *A, const b2sr_matrix *M)
 int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix *M,
                   unsigned flags, uint64_t *d_sum, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* spgemm_masked_profile: the work spgemm_masked does for the same operands
+ *   (M required), counted instead of the sum.  d_counts (device, 4 x uint64_t)
+ *   receives: [0] mask tiles visited (those whose tile-row of A is non-empty),
+ *   [1] tile columns of Bt looked up in A's tile-row, [2] matched tile pairs
+ *   (A_IK, Bt_JK) = sum over visited mask tiles of |cols(A_I) n cols(Bt_J)|,
+ *   [3] bit-row pair operations (AND + popcount of two T-bit rows) = sum over
+ *   matched pairs of the mask tile's set bits.  Overwrites d_counts.
+ *   Errors: EINVAL, EHIP. */
+int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix *M,
+                          uint64_t *d_counts, hipStream_t stream);
+
 /* ---- graph algorithms on the products above (Sec. V) ---------------------
  * Each driver runs its iteration loop on the host, launching the kernels
  * above on `stream`, and reads one device flag per iteration to test

@@ -20,6 +20,7 @@ import torch
 __all__ = [
     "B2SRError", "B2SR", "lib", "b2sr_count_tiles", "b2sr_from_csr", "b2sr_pack_bits", "spmv_bin_bin",
     "spmv_bin_full", "spmv_bin_full_workspace_bytes", "spgemm_masked", "spgemm_masked_workspace_bytes",
+    "spgemm_masked_profile",
     "b2sr_algo_workspace_bytes", "b2sr_bfs", "b2sr_msbfs", "b2sr_sssp", "b2sr_cc", "b2sr_pagerank",
     "triangle_count", "b2sr_strerror", "as_u32", "as_u64", "header_functions", "FLAGS", "SEMIRINGS",
     "b2sr_msbfs_batch", "b2sr_msbfs_batch_workspace_bytes", "MsbfsPlan", "BfsSession",
@@ -78,6 +79,7 @@ _SIGS = {
     "spmv_bin_full": (_I, [_MP, _I, _P, _P, _P, _P, ctypes.c_uint, _D, _D, _P, _P, _SZ, _P]),
     "spgemm_masked_workspace_bytes": (_SZ, [_MP, _MP]),
     "spgemm_masked": (_I, [_MP, _MP, _MP, ctypes.c_uint, _P, _P, _SZ, _P]),
+    "spgemm_masked_profile": (_I, [_MP, _MP, _MP, _P, _P]),
     "b2sr_algo_workspace_bytes": (_SZ, [_MP, _I]),
     "b2sr_bfs": (_I, [_MP, _U32, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_msbfs": (_I, [_MP, ctypes.POINTER(_U32), _U32, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
@@ -283,6 +285,15 @@ def spgemm_masked(A: B2SR, Bt: B2SR, M: B2SR | None = None, accumulate=False, ou
 
 
 # ---- algorithms -------------------------------------------------------------
+
+def spgemm_masked_profile(A: B2SR, Bt: B2SR, M: B2SR, out=None) -> dict:
+    """Work counts of spgemm_masked(A, Bt, M) (b2sr.h): mask tiles, lookups,
+    matched tile pairs, bit-row pair operations."""
+    out = torch.empty(4, dtype=torch.int64, device="cuda") if out is None else out
+    _check(lib().spgemm_masked_profile(A.view, Bt.view, M.view, _ptr(out), _stream()), "spgemm_masked_profile")
+    c = as_u64(out)
+    return {"mask_tiles": int(c[0]), "lookups": int(c[1]), "tile_pairs": int(c[2]), "row_pairs": int(c[3])}
+
 
 def b2sr_algo_workspace_bytes(A: B2SR, algo: int) -> int:
     return int(lib().b2sr_algo_workspace_bytes(A.view, algo))

@@ -79,7 +79,10 @@ __device__ __forceinline__ uint32_t pair_sum(const GemmArgs &g, size_t ia, uint3
     return part;
 }
 
-template <int T> __global__ void __launch_bounds__(kThreads) spgemm_masked_kernel(GemmArgs g)
+// PROFILE: instead of the sum, count the work into g.sum[0..3]: mask tiles
+// visited, Bt tile columns looked up, matched tile pairs, and bit-row pair
+// operations (matched pairs times the mask tile's set bits).
+template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThreads) spgemm_masked_kernel(GemmArgs g)
 {
     __shared__ uint32_t s_map[kMapWords];
     __shared__ uint32_t s_pre[kMapWords];
@@ -88,6 +91,7 @@ template <int T> __global__ void __launch_bounds__(kThreads) spgemm_masked_kerne
     __shared__ uint32_t s_cnt[kWaves][B2SR_WAVE];
     const uint32_t lane = lane_id(), wv = threadIdx.x / B2SR_WAVE;
     unsigned long long acc = 0;
+    [[maybe_unused]] unsigned long long n_tiles = 0, n_lookups = 0, n_matches = 0;
 
     for (uint32_t I = blockIdx.x; I < g.ntr; I += gridDim.x) {
         const uint32_t m0 = g.m_rp[I], m1 = g.m_rp[I + 1];
@@ -180,16 +184,40 @@ template <int T> __global__ void __launch_bounds__(kThreads) spgemm_masked_kerne
 #pragma unroll
                 for (int u = 0; u < kUB; ++u) ia[u] = kb[u] < b1 ? lookup(K[u]) : -1;
 #pragma unroll
-                for (int u = 0; u < kUB; ++u)
-                    if (ia[u] >= 0) part += pair_sum<T>(g, (size_t)ia[u], kb[u], s_pairs[wv], npairs);
+                for (int u = 0; u < kUB; ++u) {
+                    if constexpr (PROFILE) {
+                        n_lookups += kb[u] < b1;
+                        if (ia[u] >= 0) {
+                            ++n_matches;
+                            part += npairs;
+                        }
+                    } else if (ia[u] >= 0) {
+                        part += pair_sum<T>(g, (size_t)ia[u], kb[u], s_pairs[wv], npairs);
+                    }
+                }
             }
             acc += part;
+            if constexpr (PROFILE) n_tiles += lane == 0;
             __builtin_amdgcn_wave_barrier();
         }
     }
     (void)s_cnt;
     for (int d = 32; d >= 1; d >>= 1) acc += shfl_xor((uint64_t)acc, d);
-    if (lane == 0 && acc) atomicAdd(g.sum, acc);
+    if constexpr (PROFILE) {
+        for (int d = 32; d >= 1; d >>= 1) {
+            n_tiles += shfl_xor((uint64_t)n_tiles, d);
+            n_lookups += shfl_xor((uint64_t)n_lookups, d);
+            n_matches += shfl_xor((uint64_t)n_matches, d);
+        }
+        if (lane == 0) {
+            if (n_tiles) atomicAdd(g.sum, n_tiles);
+            if (n_lookups) atomicAdd(g.sum + 1, n_lookups);
+            if (n_matches) atomicAdd(g.sum + 2, n_matches);
+            if (acc) atomicAdd(g.sum + 3, acc);
+        }
+    } else if (lane == 0 && acc) {
+        atomicAdd(g.sum, acc);
+    }
 }
 
 // Unmasked sum: sum_{i,j} (A B)_ij = sum_k colsum_A(k) * colsum_Bt(k).
@@ -220,10 +248,15 @@ __global__ void __launch_bounds__(256) dot_counts_kernel(const uint32_t *__restr
 
 __global__ void zero_u64_kernel(unsigned long long *p) { *p = 0; }
 
-template <int T> int launch_masked(const GemmArgs &g, hipStream_t s)
+template <int T, bool PROFILE = false> int launch_masked(const GemmArgs &g, hipStream_t s)
 {
-    spgemm_masked_kernel<T><<<b2sr::grid_for(g.ntr, 1, 1u << 16), kThreads, 0, s>>>(g);
+    spgemm_masked_kernel<T, PROFILE><<<b2sr::grid_for(g.ntr, 1, 1u << 16), kThreads, 0, s>>>(g);
     return b2sr::check_launch("spgemm_masked_kernel");
+}
+
+__global__ void zero_u64x4_kernel(unsigned long long *p)
+{
+    if (threadIdx.x < 4) p[threadIdx.x] = 0;
 }
 
 template <int T>
@@ -252,6 +285,29 @@ size_t spgemm_masked_workspace_bytes(const b2sr_matrix *A, const b2sr_matrix *M)
 {
     if (!A || !b2sr::valid_tile(A->tile) || M) return 0;
     return (size_t)2 * b2sr::n_tile_rows(A->n, A->tile) * A->tile * sizeof(uint32_t);
+}
+
+int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix *M, uint64_t *d_counts,
+                          hipStream_t stream)
+{
+    int rc = b2sr::validate_matrix(A);
+    if (rc) return rc;
+    if ((rc = b2sr::validate_matrix(Bt))) return rc;
+    if (!M || (rc = b2sr::validate_matrix(M))) return rc ? rc : B2SR_EINVAL;
+    if (!d_counts) return B2SR_EINVAL;
+    if (Bt->n != A->n || Bt->tile != A->tile || M->n != A->n || M->tile != A->tile) return B2SR_EINVAL;
+    unsigned long long *c = (unsigned long long *)d_counts;
+    zero_u64x4_kernel<<<1, 64, 0, stream>>>(c);
+    if ((rc = b2sr::check_launch("zero_u64x4_kernel"))) return rc;
+    if (A->n == 0 || A->ntiles == 0 || Bt->ntiles == 0 || M->ntiles == 0) return B2SR_OK;
+    GemmArgs g{A->tile_rowptr, A->tile_colind, A->bits, Bt->tile_rowptr, Bt->tile_colind, Bt->bits,
+               M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), c};
+    switch (A->tile) {
+    case 4: return launch_masked<4, true>(g, stream);
+    case 8: return launch_masked<8, true>(g, stream);
+    case 16: return launch_masked<16, true>(g, stream);
+    default: return launch_masked<32, true>(g, stream);
+    }
 }
 
 int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix *M, unsigned flags,

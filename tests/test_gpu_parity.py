@@ -283,6 +283,43 @@ def test_spgemm_masked(gi, T):
     assert int(b2.as_u64(acc)[0]) == 2 * orc.masked_sum(g, g, g)
 
 
+def _tiles(c, T):
+    """(tile-row, tile-column, set bits) of every non-empty T x T tile of CSR c."""
+    rows = np.repeat(np.arange(c.n, dtype=np.int64), np.diff(c.rowptr.astype(np.int64)))
+    key, cnt = np.unique((rows // T) * (1 << 32) + c.colind.astype(np.int64) // T, return_counts=True)
+    return key >> 32, key & 0xFFFFFFFF, cnt
+
+
+def _profile_expected(a, bt, m, T):
+    import scipy.sparse as sp
+    ntr = (a.n + T - 1) // T
+    ai, ak, _ = _tiles(a, T)
+    bj, bk, _ = _tiles(bt, T)
+    mi, mj, mc = _tiles(m, T)
+    At = sp.csr_matrix((np.ones(ai.size, np.int64), (ai, ak)), shape=(ntr, ntr))
+    Bt = sp.csr_matrix((np.ones(bj.size, np.int64), (bj, bk)), shape=(ntr, ntr))
+    common = np.asarray((At @ Bt.T).tocsr()[mi, mj]).ravel() if mi.size else np.zeros(0, np.int64)
+    visit = np.bincount(ai, minlength=ntr)[mi] > 0
+    brow = np.bincount(bj, minlength=ntr)
+    return {"mask_tiles": int(visit.sum()), "lookups": int(brow[mj][visit].sum()),
+            "tile_pairs": int(common[visit].sum()), "row_pairs": int((common * mc)[visit].sum())}
+
+
+@pytest.mark.parametrize("T", TILES)
+@pytest.mark.parametrize("gi", [i for i, g in enumerate(GRAPHS) if 0 < g.n <= 5000], ids=lambda i: IDS[i])
+def test_spgemm_profile_counts(gi, T):
+    """The work counts of the masked product equal those read off the tile
+    structure on the host: for triangle counting and for unrelated operands."""
+    g = GRAPHS[gi]
+    L = orc.tril(g)
+    Ld = b2sr(g, T, lower=True)
+    assert b2.spgemm_masked_profile(Ld, Ld, Ld) == _profile_expected(L, L, L, T)
+    h = gg.random_graph_tiny(g.n, min(1.0, 8.0 / g.n), 55 + gi)
+    M = gg.random_graph_tiny(g.n, min(1.0, 5.0 / g.n), 77 + gi)
+    A = b2sr(g, T)
+    assert b2.spgemm_masked_profile(A, b2sr(h, T), b2sr(M, T)) == _profile_expected(g, h, M, T)
+
+
 def test_triangle_count_closed_forms():
     for T in TILES:
         for R, C in ((2, 2), (17, 90), (64, 64)):
