@@ -98,6 +98,54 @@ def canonical_csr(n: int, src, dst, name: str = "") -> Csr:
     return Csr(n, rowptr.astype(np.uint32), cols.astype(np.uint32), name)
 
 
+def directed_csr(n: int, src, dst, name: str = "") -> Csr:
+    """A directed graph: row u lists v for every arc u -> v; self-loops are
+    dropped, repeated arcs kept once, rows sorted."""
+    src = np.asarray(src, dtype=np.int64).ravel()
+    dst = np.asarray(dst, dtype=np.int64).ravel()
+    if src.size and (src.min() < 0 or dst.min() < 0 or src.max() >= n or dst.max() >= n):
+        raise ValueError("arc endpoint out of range")
+    keep = src != dst
+    key = np.unique(src[keep] * np.int64(n) + dst[keep])
+    rows = key // n
+    cols = key - rows * n
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+    if rowptr[-1] >= 2**32:
+        raise ValueError("nnz does not fit uint32")
+    return Csr(n, rowptr.astype(np.uint32), cols.astype(np.uint32), name)
+
+
+def transpose(g: Csr) -> Csr:
+    """The reversed graph (CSR of the transposed adjacency)."""
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), g.degrees())
+    return directed_csr(g.n, g.colind.astype(np.int64), rows, name=g.name + "_T")
+
+
+def rmat_directed(scale: int, edge_factor: int, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+                  seed: int = 0) -> Csr:
+    """R-MAT arcs as drawn (tuple (i, j) is the arc i -> j), no symmetrisation."""
+    n = 1 << scale
+    m = edge_factor * n
+    g = rng(seed)
+    i = np.zeros(m, dtype=np.int64)
+    j = np.zeros(m, dtype=np.int64)
+    ab, abc = a + b, a + b + c
+    for level in range(scale):
+        r = g.random(m)
+        bit = np.int64(1) << np.int64(scale - 1 - level)
+        i |= np.where(r >= ab, bit, 0)
+        j |= np.where(((r >= a) & (r < ab)) | (r >= abc), bit, 0)
+    return directed_csr(n, i, j, name=f"rmat_dir_s{scale}_ef{edge_factor}_s{seed}")
+
+
+def random_digraph(n: int, p: float, seed: int) -> Csr:
+    """Each ordered pair (u, v), u != v, is an arc with probability p."""
+    g = rng(seed)
+    u, v = np.nonzero(g.random((n, n)) < p)
+    return directed_csr(n, u, v, name=f"digraph_n{n}_p{p:g}_s{seed}")
+
+
 def er_gnm(n: int, m: int, seed: int) -> Csr:
     """Erdos-Renyi G(n, m): exactly ``m`` distinct undirected edges, uniform."""
     if m > n * (n - 1) // 2:

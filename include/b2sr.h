@@ -148,6 +148,22 @@ int b2sr_from_csr(uint32_t n, uint64_t nnz, const uint32_t *rowptr, const uint32
                   uint32_t *tile_colind, void *bits, hipStream_t stream);
 
 /*
+ * b2sr_csr_transpose: the CSR of the transposed matrix (for a directed graph,
+ *   the pull matrix whose row v lists the tails u of the arcs u -> v).  Inputs
+ *   as for b2sr_count_tiles (every column index < n, not checked on the
+ *   device); outputs t_rowptr[n + 1] and t_colind[nnz] (device, caller
+ *   allocated).  The columns within an output row come in no particular order
+ *   (the B2SR build accepts that).  ws: b2sr_csr_transpose_workspace_bytes(n)
+ *   bytes of device memory.  Does not synchronise.
+ *   Errors: EINVAL (NULL pointer with n > 0 or nnz > 0), ENOSPC (workspace),
+ *   ERANGE (nnz >= 2^32), EHIP.
+ */
+size_t b2sr_csr_transpose_workspace_bytes(uint32_t n);
+int b2sr_csr_transpose(uint32_t n, uint64_t nnz, const uint32_t *rowptr, const uint32_t *colind,
+                       uint32_t *t_rowptr, uint32_t *t_colind, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
+
+/*
  * b2sr_pack_bits: vector binarisation (Sec. IV, Listing 1's packed operand):
  *   bits[ceil(n/32)] (device) receives bit v = (pred[v] != 0) for v < n, zero
  *   padding above n.  pred is n bytes (device).
@@ -242,8 +258,15 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
  * above on `stream`, and reads one device flag per iteration to test
  * convergence (so it synchronises `stream`).  The number of iterations run is
  * written to the HOST pointer *iters when it is not NULL.  ws is a workspace
- * of b2sr_algo_workspace_bytes(A, algo) bytes.  A must be symmetric (an
- * undirected graph), which makes vxm and mxv the same product.
+ * of b2sr_algo_workspace_bytes(A, algo) bytes.  The drivers read A as the
+ * pull matrix: row i lists the vertices whose edges reach i, so each product
+ * y = A x moves the frontier one step along the edges.  For an undirected
+ * graph that is its symmetric adjacency matrix (vxm and mxv are then the same
+ * product); for a directed graph it is the transpose of the arc matrix
+ * (row u of the arc matrix lists the heads of u's arcs), which
+ * b2sr_csr_transpose forms from the arc CSR: BFS and SSSP then follow arcs
+ * forward, and b2sr_pagerank_directed takes out-degrees from A's columns.
+ * b2sr_cc needs an undirected graph.
  */
 #define B2SR_ALGO_BFS 1
 #define B2SR_ALGO_SSSP 2
@@ -282,6 +305,14 @@ int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, u
  * vertices contributing nothing.  rank is float[n]. */
 int b2sr_pagerank(const b2sr_matrix *A, float damping, uint32_t iterations, float *rank, void *ws,
                   size_t ws_bytes, hipStream_t stream);
+
+/* PageRank of a directed graph: At is the transpose of the arc matrix (the
+ * pull matrix), r_0 = 1/n, then r_i(v) = (1 - d)/n + d * sum_{u -> v} r(u) / o(u)
+ * with o(u) the out-degree of u, taken as the set bits of column u of At;
+ * vertices without out-arcs contribute nothing.  Workspace as for
+ * B2SR_ALGO_PAGERANK. */
+int b2sr_pagerank_directed(const b2sr_matrix *At, float damping, uint32_t iterations, float *rank,
+                           void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---- batched multi-source BFS over many graphs ---------------------------
  * Many graphs are placed in one vertex space of n vertices (each graph's ids

@@ -72,6 +72,7 @@ def lib():
         L.orc_sssp_unit.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_uint32, _u32p]
         L.orc_cc.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u32p]
         L.orc_pagerank.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_double, ctypes.c_uint32, _f64p]
+        L.orc_pagerank_directed.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_double, ctypes.c_uint32, _f64p]
         L.orc_tc.restype = ctypes.c_uint64
         L.orc_tc.argtypes = [ctypes.c_uint32, _u32p, _u32p]
         _lib = L
@@ -210,6 +211,13 @@ def cc(g):
 def pagerank(g, d: float = 0.85, iters: int = 20):
     r = np.zeros(g.n, dtype=np.float64)
     lib().orc_pagerank(g.n, g.rowptr, g.colind, float(d), int(iters), r)
+    return r
+
+
+def pagerank_directed(g, d: float = 0.85, iters: int = 20):
+    """PageRank of the directed graph whose CSR row u lists the heads of u's arcs."""
+    r = np.zeros(g.n, dtype=np.float64)
+    lib().orc_pagerank_directed(g.n, g.rowptr, g.colind, float(d), int(iters), r)
     return r
 
 

@@ -416,6 +416,28 @@ void orc_pagerank(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, do
     free(z);
 }
 
+/* PageRank of a directed graph from its definition: with out-degree o(u) and
+ * arcs u -> v (row u of the CSR lists the heads v),
+ *     r'(v) = (1 - d) / n + d * sum_{u -> v} r(u) / o(u),
+ * starting from r = 1/n.  Rank at vertices without out-arcs is not
+ * redistributed (the reading taken for the undirected case too).  The sums
+ * are pushed along rows in CSR order, one thread, so the result is fixed. */
+void orc_pagerank_directed(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, double d,
+                           uint32_t iters, double *r)
+{
+    double *acc = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    for (uint32_t i = 0; i < n; ++i) r[i] = 1.0 / (double)n;
+    for (uint32_t it = 0; it < iters; ++it) {
+        for (uint32_t v = 0; v < n; ++v) acc[v] = 0.0;
+        for (uint32_t u = 0; u < n; ++u) {
+            const uint32_t o = rowptr[u + 1] - rowptr[u];
+            for (uint32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) acc[colind[e]] += r[u] / (double)o;
+        }
+        for (uint32_t v = 0; v < n; ++v) r[v] = (1.0 - d) / (double)n + d * acc[v];
+    }
+    free(acc);
+}
+
 /* Triangles of a simple undirected graph: for every edge (i, j) with j < i,
  * count the common neighbours k with k < j.  Each triangle k < j < i is
  * counted exactly once.  (Sec. V: the sum of (L L^T) masked by L.) */

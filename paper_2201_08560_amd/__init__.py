@@ -20,7 +20,7 @@ import torch
 __all__ = [
     "B2SRError", "B2SR", "lib", "b2sr_count_tiles", "b2sr_from_csr", "b2sr_pack_bits", "spmv_bin_bin",
     "spmv_bin_full", "spmv_bin_full_workspace_bytes", "spgemm_masked", "spgemm_masked_workspace_bytes",
-    "spgemm_masked_profile",
+    "spgemm_masked_profile", "b2sr_pagerank_directed", "b2sr_csr_transpose",
     "b2sr_algo_workspace_bytes", "b2sr_bfs", "b2sr_msbfs", "b2sr_sssp", "b2sr_cc", "b2sr_pagerank",
     "triangle_count", "b2sr_strerror", "as_u32", "as_u64", "header_functions", "FLAGS", "SEMIRINGS",
     "b2sr_msbfs_batch", "b2sr_msbfs_batch_workspace_bytes", "MsbfsPlan", "BfsSession",
@@ -86,6 +86,9 @@ _SIGS = {
     "b2sr_sssp": (_I, [_MP, _U32, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_cc": (_I, [_MP, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_pagerank": (_I, [_MP, ctypes.c_float, _U32, _P, _P, _SZ, _P]),
+    "b2sr_pagerank_directed": (_I, [_MP, ctypes.c_float, _U32, _P, _P, _SZ, _P]),
+    "b2sr_csr_transpose_workspace_bytes": (_SZ, [_U32]),
+    "b2sr_csr_transpose": (_I, [_U32, _U64, _P, _P, _P, _P, _P, _SZ, _P]),
     "b2sr_msbfs_batch_workspace_bytes": (_SZ, [_U32]),
     "b2sr_msbfs_batch": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, ctypes.c_uint, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_msbfs_batch_plan_create": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, ctypes.c_uint, _P, _SZ,
@@ -187,8 +190,12 @@ class B2SR:
         return 4 * (self.ntile_rows + 1) + 4 * self.ntiles + self.ntiles * self.tile * _ROW_BYTES[self.tile]
 
     @classmethod
-    def from_csr(cls, rowptr, colind, n: int, tile: int, lower: bool = False):
-        """Builds B2SR on the device from CSR (uint32 numpy arrays or int32 device tensors)."""
+    def from_csr(cls, rowptr, colind, n: int, tile: int, lower: bool = False, transpose: bool = False):
+        """Builds B2SR on the device from CSR (uint32 numpy arrays or int32 device
+        tensors); ``transpose`` builds the transposed matrix (a directed graph's
+        pull matrix)."""
+        if transpose:
+            rowptr, colind = b2sr_csr_transpose(n, rowptr, colind)
         rp, ci = _i32(rowptr), _i32(colind)
         nnz = int(ci.numel())
         flags = BUILD_LOWER if lower else 0
@@ -200,8 +207,8 @@ class B2SR:
         return cls(n, tile, trp, tci, bits, nt)
 
     @classmethod
-    def from_graph(cls, g, tile: int, lower: bool = False):
-        return cls.from_csr(g.rowptr, g.colind, g.n, tile, lower)
+    def from_graph(cls, g, tile: int, lower: bool = False, transpose: bool = False):
+        return cls.from_csr(g.rowptr, g.colind, g.n, tile, lower, transpose)
 
     def to_host(self):
         """(tile_rowptr u32, tile_colind u32, bits as u8/u8/u16/u32 words)."""
@@ -348,6 +355,29 @@ def b2sr_pagerank(A: B2SR, damping=0.85, iterations=20, out=None, ws=None):
     _check(lib().b2sr_pagerank(A.view, float(damping), int(iterations), _ptr(out), _ptr(ws), need, _stream()),
            "b2sr_pagerank")
     return out
+
+
+def b2sr_pagerank_directed(At: B2SR, damping=0.85, iterations=20, out=None, ws=None):
+    """PageRank of a directed graph given its pull matrix At (B2SR.from_csr(..., transpose=True))."""
+    out = torch.empty(At.n, dtype=torch.float32, device="cuda") if out is None else out
+    ws, need = _ws(At, ALGO_PAGERANK, ws)
+    _check(lib().b2sr_pagerank_directed(At.view, float(damping), int(iterations), _ptr(out), _ptr(ws), need,
+                                        _stream()), "b2sr_pagerank_directed")
+    return out
+
+
+def b2sr_csr_transpose(n: int, rowptr, colind):
+    """(t_rowptr, t_colind) int32 device tensors of the transposed CSR; the
+    columns within a row are in no particular order."""
+    rp, ci = _i32(rowptr), _i32(colind)
+    nnz = int(ci.numel())
+    trp = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    tci = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+    need = int(lib().b2sr_csr_transpose_workspace_bytes(n))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+    _check(lib().b2sr_csr_transpose(n, nnz, _ptr(rp), _ptr(ci), _ptr(trp), _ptr(tci), _ptr(ws), need, _stream()),
+           "b2sr_csr_transpose")
+    return trp, tci[:nnz]
 
 
 def triangle_count(rowptr, colind, n: int, tile: int) -> int:

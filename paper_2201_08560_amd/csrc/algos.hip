@@ -12,6 +12,7 @@ using namespace b2sr_dev;
 
 namespace b2sr {
 int fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
+int column_counts(const b2sr_matrix *A, uint32_t *colsum, hipStream_t s);
 }
 
 namespace {
@@ -271,7 +272,8 @@ Layout carve(const b2sr_matrix *A, int algo, void *ws)
         L.f0 = c.take<float>(n * 4);  // z = r / deg
         L.f1 = c.take<float>(n * 4);  // 1 / deg
         L.f2 = c.take<float>(n * 4);  // second rank buffer
-        L.u0 = c.take<uint32_t>(n * 4);
+        // degrees; column counts (directed graphs) cover every column of the last tile
+        L.u0 = c.take<uint32_t>((size_t)b2sr::n_tile_rows(A->n, A->tile) * A->tile * 4);
         L.ones = c.take<uint32_t>(nw * 4);
         L.spmv_ws_bytes = spmv_bin_full_workspace_bytes(A, B2SR_PLUS_TIMES_F32);
         L.spmv_ws = c.take<char>(L.spmv_ws_bytes);
@@ -435,18 +437,29 @@ int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, u
     return B2SR_OK;
 }
 
-int b2sr_pagerank(const b2sr_matrix *A, float damping, uint32_t iterations, float *rank, void *ws, size_t ws_bytes,
-                  hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+// PageRank on A read as the pull matrix: r'(i) = (1-d)/n + d * sum_{j : A_ij} r(j) / o(j).
+// Undirected graphs: o = row degrees of A.  Directed graphs (A = the transpose
+// of the arc matrix): o = out-degrees = column counts of A.
+int pagerank(const b2sr_matrix *A, bool directed, float damping, uint32_t iterations, float *rank, void *ws,
+             size_t ws_bytes, hipStream_t stream)
 {
     Layout L;
     int rc = check_algo_args(A, B2SR_ALGO_PAGERANK, ws, ws_bytes, &L);
     if (rc) return rc;
     if (!rank || !(damping >= 0.0f && damping <= 1.0f)) return B2SR_EINVAL;
     const uint32_t n = A->n, nw = b2sr::n_words(n);
-    // out-degrees as a count product with the all-ones vector (bmv_bin_bin_full)
-    ones_bits_kernel<<<vgrid(nw), 256, 0, stream>>>(n, L.ones);
-    if ((rc = b2sr::check_launch("ones_bits_kernel"))) return rc;
-    if ((rc = spmv_bin_bin(A, L.ones, nullptr, B2SR_OUT_COUNT, L.u0, stream))) return rc;
+    if (directed) {
+        if ((rc = b2sr::column_counts(A, L.u0, stream))) return rc;
+    } else {
+        // degrees as a count product with the all-ones vector (bmv_bin_bin_full)
+        ones_bits_kernel<<<vgrid(nw), 256, 0, stream>>>(n, L.ones);
+        if ((rc = b2sr::check_launch("ones_bits_kernel"))) return rc;
+        if ((rc = spmv_bin_bin(A, L.ones, nullptr, B2SR_OUT_COUNT, L.u0, stream))) return rc;
+    }
     float *r = rank, *r_next = L.f2;
     pr_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, L.u0, L.f1, r);
     if ((rc = b2sr::check_launch("pr_init_kernel"))) return rc;
@@ -464,6 +477,22 @@ int b2sr_pagerank(const b2sr_matrix *A, float damping, uint32_t iterations, floa
         if ((rc = b2sr::check_launch("copy_u32_kernel"))) return rc;
     }
     return B2SR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int b2sr_pagerank(const b2sr_matrix *A, float damping, uint32_t iterations, float *rank, void *ws, size_t ws_bytes,
+                  hipStream_t stream)
+{
+    return pagerank(A, false, damping, iterations, rank, ws, ws_bytes, stream);
+}
+
+int b2sr_pagerank_directed(const b2sr_matrix *At, float damping, uint32_t iterations, float *rank, void *ws,
+                           size_t ws_bytes, hipStream_t stream)
+{
+    return pagerank(At, true, damping, iterations, rank, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

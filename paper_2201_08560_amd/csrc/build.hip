@@ -279,6 +279,35 @@ __global__ void __launch_bounds__(256) pack_bits_kernel(uint32_t n, const uint8_
 
 inline uint32_t log2_tile(uint32_t T) { return T == 4 ? 2 : T == 8 ? 3 : T == 16 ? 4 : 5; }
 
+// ---- CSR transpose (directed graphs: the pull matrix A^T from the CSR of A)
+// Counts land at t_rowptr[v + 1]; the in-place scan above turns them into row
+// pointers; each arc u -> v then takes the next free position of row v.
+__global__ void transpose_count_kernel(uint64_t nnz, const uint32_t *__restrict__ colind, uint32_t *t_rowptr)
+{
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(t_rowptr + colind[e] + 1, 1u);
+}
+
+__global__ void transpose_cursor_kernel(uint32_t n, const uint32_t *__restrict__ t_rowptr, uint32_t *cursor)
+{
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+        cursor[v] = t_rowptr[v];
+}
+
+// One wave per source row, lanes striding over its arcs.
+__global__ void transpose_scatter_kernel(uint32_t n, const uint32_t *__restrict__ rowptr,
+                                         const uint32_t *__restrict__ colind, uint32_t *cursor, uint32_t *t_colind)
+{
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t u = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE; u < n; u += waves) {
+        const uint32_t e1 = rowptr[u + 1];
+        for (uint32_t e = rowptr[u] + lane_id(); e < e1; e += B2SR_WAVE) {
+            const uint32_t v = colind[e];
+            t_colind[atomicAdd(cursor + v, 1u)] = (uint32_t)u;
+        }
+    }
+}
+
 int validate_csr(uint32_t n, uint64_t nnz, const uint32_t *rowptr, const uint32_t *colind, uint32_t tile,
                  unsigned flags)
 {
@@ -355,6 +384,35 @@ int b2sr_from_csr(uint32_t n, uint64_t nnz, const uint32_t *rowptr, const uint32
                                                                      b2sr::row_bytes(tile), ntr, tile_rowptr,
                                                                      tile_colind, (uint32_t *)bits);
     return b2sr::check_launch("fill_tiles_kernel");
+}
+
+size_t b2sr_csr_transpose_workspace_bytes(uint32_t n) { return ((size_t)n * 4 + 255) & ~(size_t)255; }
+
+int b2sr_csr_transpose(uint32_t n, uint64_t nnz, const uint32_t *rowptr, const uint32_t *colind, uint32_t *t_rowptr,
+                       uint32_t *t_colind, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (nnz >= (1ull << 32)) return B2SR_ERANGE;
+    if (n > 0 && (!rowptr || !t_rowptr)) return B2SR_EINVAL;
+    if (nnz > 0 && (!colind || !t_colind)) return B2SR_EINVAL;
+    if (n > 0 && (!ws || ws_bytes < b2sr_csr_transpose_workspace_bytes(n))) return B2SR_ENOSPC;
+    if (n == 0) {
+        if (t_rowptr) return b2sr::fill_u32(t_rowptr, 1, 0, stream);
+        return B2SR_OK;
+    }
+    int rc = b2sr::fill_u32(t_rowptr, (uint64_t)n + 1, 0, stream);
+    if (rc) return rc;
+    if (nnz) {
+        transpose_count_kernel<<<b2sr::grid_for(nnz, 256, 8192), 256, 0, stream>>>(nnz, colind, t_rowptr);
+        if ((rc = b2sr::check_launch("transpose_count_kernel"))) return rc;
+    }
+    scan_counts_kernel<<<1, 1024, 0, stream>>>(n, t_rowptr);
+    if ((rc = b2sr::check_launch("scan_counts_kernel"))) return rc;
+    if (!nnz) return B2SR_OK;
+    uint32_t *cursor = (uint32_t *)ws;
+    transpose_cursor_kernel<<<b2sr::grid_for(n, 256, 8192), 256, 0, stream>>>(n, t_rowptr, cursor);
+    if ((rc = b2sr::check_launch("transpose_cursor_kernel"))) return rc;
+    transpose_scatter_kernel<<<b2sr::grid_for(n, 4, 16384), 256, 0, stream>>>(n, rowptr, colind, cursor, t_colind);
+    return b2sr::check_launch("transpose_scatter_kernel");
 }
 
 int b2sr_pack_bits(uint32_t n, const uint8_t *pred, uint32_t *bits, hipStream_t stream)

@@ -279,6 +279,25 @@ namespace b2sr {
 int fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
 }
 
+namespace b2sr {
+// colsum[c] = number of set bits in column c, for c < nTR * T (the columns of
+// A's last tile column past n count nothing).
+int column_counts(const b2sr_matrix *A, uint32_t *colsum, hipStream_t s)
+{
+    const uint64_t len = (uint64_t)n_tile_rows(A->n, A->tile) * A->tile;
+    if (int rc = fill_u32(colsum, len, 0, s)) return rc;
+    if (!A->ntiles) return B2SR_OK;
+    const unsigned grid = grid_for((uint64_t)A->ntiles * A->tile, 256, 65536);
+    switch (A->tile) {
+    case 4: column_counts_kernel<4><<<grid, 256, 0, s>>>(A->tile_colind, A->bits, A->ntiles, colsum); break;
+    case 8: column_counts_kernel<8><<<grid, 256, 0, s>>>(A->tile_colind, A->bits, A->ntiles, colsum); break;
+    case 16: column_counts_kernel<16><<<grid, 256, 0, s>>>(A->tile_colind, A->bits, A->ntiles, colsum); break;
+    default: column_counts_kernel<32><<<grid, 256, 0, s>>>(A->tile_colind, A->bits, A->ntiles, colsum); break;
+    }
+    return check_launch("column_counts_kernel");
+}
+}  // namespace b2sr
+
 extern "C" {
 
 size_t spgemm_masked_workspace_bytes(const b2sr_matrix *A, const b2sr_matrix *M)

@@ -183,3 +183,17 @@ def test_session_argument_errors():
     assert L.b2sr_bfs_session_extract(None, 0, None, None) == -1
     assert L.b2sr_bfs_session_info(None, None, None) == -1
     assert L.b2sr_bfs_session_destroy(None) == 0
+
+
+def test_transpose_argument_errors():
+    need = L.b2sr_csr_transpose_workspace_bytes(100)
+    assert need >= 400
+    p = FAKE
+    assert L.b2sr_csr_transpose(100, 10, None, p, p, p, p, need, None) == -1
+    assert L.b2sr_csr_transpose(100, 10, p, None, p, p, p, need, None) == -1
+    assert L.b2sr_csr_transpose(100, 10, p, p, p, None, p, need, None) == -1
+    assert L.b2sr_csr_transpose(100, 10, p, p, p, p, None, need, None) == -3
+    assert L.b2sr_csr_transpose(100, 10, p, p, p, p, p, need - 1, None) == -3
+    assert L.b2sr_csr_transpose(100, 1 << 32, p, p, p, p, p, need, None) == -2
+    A = mat(n=64, tile=5)
+    assert L.b2sr_pagerank_directed(ctypes.byref(A), 0.85, 1, p, p, 1 << 20, None) == -1

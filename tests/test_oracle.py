@@ -393,3 +393,54 @@ def test_pins_catch_planted_mistakes():
     right = orc.masked_sum(directed_csr(A), directed_csr(B.T), directed_csr(M))
     wrong = orc.masked_sum(directed_csr(A), directed_csr(B), directed_csr(M))
     assert right == int(((A @ B) * M).sum()) != wrong
+
+
+# ---- directed graphs -----------------------------------------------------------
+
+def test_transpose_generator():
+    for g in (gg.random_digraph(40, 0.1, 3), gg.rmat_directed(8, 8, seed=2), gg.path(30)):
+        t = gg.transpose(g)
+        assert np.array_equal(t.dense(), g.dense().T)
+        tt = gg.transpose(t)
+        assert np.array_equal(tt.rowptr, g.rowptr) and np.array_equal(tt.colind, g.colind)
+
+
+def test_directed_bfs_pins():
+    """BFS along arcs: a directed path reaches forward only; BFS (push along the
+    arc rows) equals unit-weight Bellman-Ford pulled over the reversed rows."""
+    n = 50
+    p = gg.directed_csr(n, np.arange(n - 1), np.arange(1, n))
+    assert np.array_equal(orc.bfs(p, 0), np.arange(n, dtype=np.uint32))
+    lv = orc.bfs(p, 20)
+    assert np.all(lv[:20] == UNR) and np.array_equal(lv[20:], np.arange(n - 20, dtype=np.uint32))
+    for seed in range(4):
+        g = gg.random_digraph(60, 0.04, 100 + seed)
+        gt = gg.transpose(g)
+        for s in (0, 7, 59):
+            assert np.array_equal(orc.bfs(g, s), orc.sssp_unit(gt, s))
+
+
+def test_directed_pagerank_pins():
+    d = 0.85
+    # an undirected graph given as both arcs of every edge: the undirected PageRank
+    g = gg.er_gnm(200, 700, seed=5)
+    assert np.allclose(orc.pagerank_directed(g, d, 15), orc.pagerank(g, d, 15), rtol=1e-13, atol=0)
+    # a directed cycle keeps the uniform vector
+    n = 17
+    cyc = gg.directed_csr(n, np.arange(n), (np.arange(n) + 1) % n)
+    assert np.allclose(orc.pagerank_directed(cyc, d, 9), np.full(n, 1.0 / n), rtol=1e-14, atol=0)
+    # an inward star: leaves keep (1-d)/n; the centre, a sink, gets d (n-1)/n, then d (n-1)(1-d)/n
+    n = 9
+    star = gg.directed_csr(n, np.arange(1, n), np.zeros(n - 1, dtype=np.int64))
+    r1, r2 = orc.pagerank_directed(star, d, 1), orc.pagerank_directed(star, d, 2)
+    assert np.allclose(r1[1:], (1 - d) / n) and np.isclose(r1[0], (1 - d) / n + d * (n - 1) / n)
+    assert np.allclose(r2[1:], (1 - d) / n) and np.isclose(r2[0], (1 - d) / n + d * (n - 1) * (1 - d) / n)
+    # small random digraphs: the matrix form r' = (1-d)/n + d P (r / o), P = A^T
+    for seed in range(3):
+        g = gg.random_digraph(30, 0.1, 40 + seed)
+        A = g.dense().astype(np.float64)
+        o = A.sum(1)
+        r = np.full(g.n, 1.0 / g.n)
+        for _ in range(6):
+            r = (1 - d) / g.n + d * A.T @ np.divide(r, o, out=np.zeros_like(r), where=o > 0)
+        assert np.allclose(orc.pagerank_directed(g, d, 6), r, rtol=1e-12, atol=0)
