@@ -99,6 +99,9 @@ extern "C" {
                                  saturating addition                                */
 #define B2SR_OR_U64 4         /* Boolean on 64 vectors at once: uint64_t x / y,
                                  y_i = OR_{A_ij = 1} x_j (multi-source BFS frontier) */
+#define B2SR_MAX_TIMES_U64 5  /* the max-times semiring (Table V) on a binary matrix:
+                                 y_i = max_{j : A_ij = 1} x_j over uint64_t, the empty
+                                 maximum being 0 (MIS and colouring keys) */
 
 /* A non-owning view of a B2SR matrix in device memory (layout above). */
 typedef struct b2sr_matrix {
@@ -201,6 +204,8 @@ int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, 
  *       (the diagonal as a real zero, Sec. V SSSP); y_i = t_i.  For _U32,
  *       alpha must be a non-negative integer and additions saturate.
  *   B2SR_OR_U64: y_i = OR_{j : A_ij = 1} x_j over uint64_t words.
+ *   B2SR_MAX_TIMES_U64: y_i = max_{j : A_ij = 1} x_j over uint64_t (0 when
+ *       row i has no set bit).
  *   x_active (nullable bit vector over columns, the layout of x's indices):
  *   entries x_j whose bit is 0 are treated as the semiring's identity (0, or
  *   +infinity for min-plus) and tiles whose whole x segment is inactive are
@@ -208,9 +213,9 @@ int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, 
  *   the set of entries that changed (SSSP, CC) or are non-zero (multi-source
  *   BFS frontier words).
  *   mask / B2SR_MASK_COMPLEMENT: as for spmv_bin_bin; a dropped row gets 0
- *   (plus-times, or-u64) or infinity (min-plus), or keeps its old value under
+ *   (plus-times, or-u64, max-times) or infinity (min-plus), or keeps its old value under
  *   ACCUMULATE.  B2SR_ACCUMULATE: y_i = y_i + alpha t_i + beta (plus-times),
- *   min(y_i, t_i) (min-plus), y_i | t_i (or-u64).
+ *   min(y_i, t_i) (min-plus), y_i | t_i (or-u64), max(y_i, t_i) (max-times).
  *   Floating-point sums are deterministic: a fixed reduction order that does
  *   not depend on scheduling (rows split across work chunks are combined in
  *   chunk order by a second kernel).
@@ -273,6 +278,8 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
 #define B2SR_ALGO_CC 3
 #define B2SR_ALGO_PAGERANK 4
 #define B2SR_ALGO_MSBFS 5
+#define B2SR_ALGO_MIS 6
+#define B2SR_ALGO_COLOR 7
 size_t b2sr_algo_workspace_bytes(const b2sr_matrix *A, int algo);
 
 /* BFS (Sec. V): Boolean semiring, masked bin_bin_bin product per level with
@@ -305,6 +312,24 @@ int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, u
  * vertices contributing nothing.  rank is float[n]. */
 int b2sr_pagerank(const b2sr_matrix *A, float damping, uint32_t iterations, float *rank, void *ws,
                   size_t ws_bytes, hipStream_t stream);
+
+/* Maximal independent set (max-times, Table V): rounds of local maxima.  key
+ * (device uint64_t[n], nonzero, distinct; ties let adjacent vertices both in)
+ * ranks the vertices: a candidate whose key is at least every candidate
+ * neighbour's (y = A max-times x over the candidates' keys) joins, then it and
+ * its neighbours (an OR product) stop being candidates; repeat while any
+ * remain.  With distinct keys the set equals the greedy one taken in
+ * decreasing key order.  mis_bits: the set as a bit vector (device,
+ * ceil(n/32) words).  *iters: rounds.  A must be undirected (symmetric). */
+int b2sr_mis(const b2sr_matrix *A, const uint64_t *key, uint32_t *mis_bits, void *ws,
+             size_t ws_bytes, uint32_t *iters, hipStream_t stream);
+
+/* Graph colouring by successive independent sets (max-times, Table V): colour
+ * c = 0, 1, ... is the b2sr_mis set of the vertices still uncoloured, with the
+ * same keys.  colors: device uint32_t[n].  *ncolors: colours used.  A must be
+ * undirected.  Workspace: b2sr_algo_workspace_bytes(A, B2SR_ALGO_COLOR). */
+int b2sr_color(const b2sr_matrix *A, const uint64_t *key, uint32_t *colors, void *ws,
+               size_t ws_bytes, uint32_t *ncolors, hipStream_t stream);
 
 /* PageRank of a directed graph: At is the transpose of the arc matrix (the
  * pull matrix), r_0 = 1/n, then r_i(v) = (1 - d)/n + d * sum_{u -> v} r(u) / o(u)

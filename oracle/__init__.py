@@ -73,6 +73,12 @@ def lib():
         L.orc_cc.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u32p]
         L.orc_pagerank.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_double, ctypes.c_uint32, _f64p]
         L.orc_pagerank_directed.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_double, ctypes.c_uint32, _f64p]
+        L.orc_spmv_max.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u64p, _u64p]
+        L.orc_mis.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u64p, _u8p]
+        L.orc_mis.restype = ctypes.c_uint32
+        L.orc_mis_greedy.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u64p, _u8p]
+        L.orc_color.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u64p, _u32p]
+        L.orc_color.restype = ctypes.c_uint32
         L.orc_tc.restype = ctypes.c_uint64
         L.orc_tc.argtypes = [ctypes.c_uint32, _u32p, _u32p]
         _lib = L
@@ -219,6 +225,32 @@ def pagerank_directed(g, d: float = 0.85, iters: int = 20):
     r = np.zeros(g.n, dtype=np.float64)
     lib().orc_pagerank_directed(g.n, g.rowptr, g.colind, float(d), int(iters), r)
     return r
+
+
+def spmv_max(g, x):
+    y = np.zeros(g.n, dtype=np.uint64)
+    lib().orc_spmv_max(g.n, g.rowptr, g.colind, np.ascontiguousarray(x, dtype=np.uint64), y)
+    return y
+
+
+def mis(g, key):
+    """(membership bool array, rounds) of the local-maxima independent set."""
+    out = np.zeros(g.n, dtype=np.uint8)
+    r = lib().orc_mis(g.n, g.rowptr, g.colind, np.ascontiguousarray(key, dtype=np.uint64), out)
+    return out.astype(bool), int(r)
+
+
+def mis_greedy(g, key):
+    out = np.zeros(g.n, dtype=np.uint8)
+    lib().orc_mis_greedy(g.n, g.rowptr, g.colind, np.ascontiguousarray(key, dtype=np.uint64), out)
+    return out.astype(bool)
+
+
+def color(g, key):
+    """(colour per vertex, number of colours) by successive independent sets."""
+    out = np.zeros(g.n, dtype=np.uint32)
+    c = lib().orc_color(g.n, g.rowptr, g.colind, np.ascontiguousarray(key, dtype=np.uint64), out)
+    return out, int(c)
 
 
 def tc(g) -> int:

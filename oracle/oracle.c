@@ -438,6 +438,110 @@ void orc_pagerank_directed(uint32_t n, const uint32_t *rowptr, const uint32_t *c
     free(acc);
 }
 
+/* Max-times on a binary matrix (Table V): y_i = max_{j in row i} x_j, 0 for an
+ * empty row. */
+void orc_spmv_max(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, const uint64_t *x, uint64_t *y)
+{
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+        uint64_t m = 0;
+        for (uint32_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+            if (x[colind[e]] > m) m = x[colind[e]];
+        y[i] = m;
+    }
+}
+
+/* Maximal independent set by rounds of local maxima (Luby's scheme with fixed
+ * keys, the max-times use of Table V): a candidate whose key is at least every
+ * candidate neighbour's joins the set; it and its neighbours stop being
+ * candidates; repeat while candidates remain.  Vertices with key 0 are never
+ * candidates.  in[v] = 1 for members.  Returns the number of rounds. */
+uint32_t orc_mis(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, const uint64_t *key, uint8_t *in)
+{
+    uint8_t *cand = (uint8_t *)malloc(n ? n : 1), *join = (uint8_t *)malloc(n ? n : 1);
+    for (uint32_t v = 0; v < n; ++v) {
+        cand[v] = key[v] != 0;
+        in[v] = 0;
+    }
+    uint32_t rounds = 0;
+    for (;;) {
+        int any = 0;
+        for (uint32_t v = 0; v < n; ++v) any |= cand[v];
+        if (!any) break;
+        ++rounds;
+        for (uint32_t v = 0; v < n; ++v) {
+            join[v] = cand[v];
+            for (uint32_t e = rowptr[v]; e < rowptr[v + 1] && join[v]; ++e)
+                if (cand[colind[e]] && key[colind[e]] > key[v]) join[v] = 0;
+        }
+        for (uint32_t v = 0; v < n; ++v)
+            if (join[v]) {
+                in[v] = 1;
+                cand[v] = 0;
+                for (uint32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) cand[colind[e]] = 0;
+            }
+    }
+    free(cand);
+    free(join);
+    return rounds;
+}
+
+/* The sequential greedy independent set in decreasing key order: take a vertex
+ * unless a neighbour was taken.  (With distinct keys it equals orc_mis.) */
+void orc_mis_greedy(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, const uint64_t *key, uint8_t *in)
+{
+    uint32_t *order = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    for (uint32_t v = 0; v < n; ++v) {
+        order[v] = v;
+        in[v] = 0;
+    }
+    /* insertion sort by decreasing key: small inputs only */
+    for (uint32_t i = 1; i < n; ++i) {
+        uint32_t v = order[i], j = i;
+        while (j > 0 && key[order[j - 1]] < key[v]) {
+            order[j] = order[j - 1];
+            --j;
+        }
+        order[j] = v;
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t v = order[i];
+        if (!key[v]) continue;
+        int free_v = 1;
+        for (uint32_t e = rowptr[v]; e < rowptr[v + 1]; ++e)
+            if (in[colind[e]]) free_v = 0;
+        in[v] = (uint8_t)free_v;
+    }
+    free(order);
+}
+
+/* Colouring by successive independent sets: colour c is the orc_mis set of the
+ * vertices still uncoloured (with the same keys).  colors[v] = colour of v;
+ * returns the number of colours. */
+uint32_t orc_color(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, const uint64_t *key,
+                   uint32_t *colors)
+{
+    uint64_t *k = (uint64_t *)malloc((size_t)(n ? n : 1) * sizeof(uint64_t));
+    uint8_t *in = (uint8_t *)malloc(n ? n : 1);
+    for (uint32_t v = 0; v < n; ++v) colors[v] = ORC_UNREACHED;
+    uint32_t c = 0;
+    for (;;) {
+        int left = 0;
+        for (uint32_t v = 0; v < n; ++v) {
+            k[v] = colors[v] == ORC_UNREACHED ? key[v] : 0;
+            left |= k[v] != 0;
+        }
+        if (!left) break;
+        orc_mis(n, rowptr, colind, k, in);
+        for (uint32_t v = 0; v < n; ++v)
+            if (in[v]) colors[v] = c;
+        ++c;
+    }
+    free(k);
+    free(in);
+    return c;
+}
+
 /* Triangles of a simple undirected graph: for every edge (i, j) with j < i,
  * count the common neighbours k with k < j.  Each triangle k < j < i is
  * counted exactly once.  (Sec. V: the sum of (L L^T) masked by L.) */

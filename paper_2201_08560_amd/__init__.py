@@ -20,7 +20,8 @@ import torch
 __all__ = [
     "B2SRError", "B2SR", "lib", "b2sr_count_tiles", "b2sr_from_csr", "b2sr_pack_bits", "spmv_bin_bin",
     "spmv_bin_full", "spmv_bin_full_workspace_bytes", "spgemm_masked", "spgemm_masked_workspace_bytes",
-    "spgemm_masked_profile", "b2sr_pagerank_directed", "b2sr_csr_transpose",
+    "spgemm_masked_profile", "b2sr_pagerank_directed", "b2sr_csr_transpose", "b2sr_mis", "b2sr_color",
+    "mis_keys",
     "b2sr_algo_workspace_bytes", "b2sr_bfs", "b2sr_msbfs", "b2sr_sssp", "b2sr_cc", "b2sr_pagerank",
     "triangle_count", "b2sr_strerror", "as_u32", "as_u64", "header_functions", "FLAGS", "SEMIRINGS",
     "b2sr_msbfs_batch", "b2sr_msbfs_batch_workspace_bytes", "MsbfsPlan", "BfsSession",
@@ -38,13 +39,13 @@ OUT_COUNT = 0x2
 ACCUMULATE = 0x4
 SELF = 0x8
 SPARSE_X = 0x10
-PLUS_TIMES_F32, MIN_PLUS_F32, MIN_PLUS_U32, OR_U64 = 1, 2, 3, 4
-ALGO_BFS, ALGO_SSSP, ALGO_CC, ALGO_PAGERANK, ALGO_MSBFS = 1, 2, 3, 4, 5
+PLUS_TIMES_F32, MIN_PLUS_F32, MIN_PLUS_U32, OR_U64, MAX_TIMES_U64 = 1, 2, 3, 4, 5
+ALGO_BFS, ALGO_SSSP, ALGO_CC, ALGO_PAGERANK, ALGO_MSBFS, ALGO_MIS, ALGO_COLOR = 1, 2, 3, 4, 5, 6, 7
 BATCH_LEVELS, BATCH_PERSISTENT = 0, 1
 FLAGS = {"BUILD_LOWER": BUILD_LOWER, "MASK_COMPLEMENT": MASK_COMPLEMENT, "OUT_COUNT": OUT_COUNT,
          "ACCUMULATE": ACCUMULATE, "SELF": SELF, "SPARSE_X": SPARSE_X}
 SEMIRINGS = {"plus_times_f32": PLUS_TIMES_F32, "min_plus_f32": MIN_PLUS_F32, "min_plus_u32": MIN_PLUS_U32,
-             "or_u64": OR_U64}
+             "or_u64": OR_U64, "max_times_u64": MAX_TIMES_U64}
 UNREACHED = 0xFFFFFFFF
 
 
@@ -87,6 +88,8 @@ _SIGS = {
     "b2sr_cc": (_I, [_MP, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_pagerank": (_I, [_MP, ctypes.c_float, _U32, _P, _P, _SZ, _P]),
     "b2sr_pagerank_directed": (_I, [_MP, ctypes.c_float, _U32, _P, _P, _SZ, _P]),
+    "b2sr_mis": (_I, [_MP, _P, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
+    "b2sr_color": (_I, [_MP, _P, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_csr_transpose_workspace_bytes": (_SZ, [_U32]),
     "b2sr_csr_transpose": (_I, [_U32, _U64, _P, _P, _P, _P, _P, _SZ, _P]),
     "b2sr_msbfs_batch_workspace_bytes": (_SZ, [_U32]),
@@ -259,7 +262,7 @@ def spmv_bin_full_workspace_bytes(A: B2SR, semiring: int) -> int:
 
 
 _FULL_DTYPE = {PLUS_TIMES_F32: torch.float32, MIN_PLUS_F32: torch.float32, MIN_PLUS_U32: torch.int32,
-               OR_U64: torch.int64}
+               OR_U64: torch.int64, MAX_TIMES_U64: torch.int64}
 
 
 def spmv_bin_full(A: B2SR, semiring: int, x, col_scale=None, mask=None, complement=False, self_loop=False,
@@ -364,6 +367,34 @@ def b2sr_pagerank_directed(At: B2SR, damping=0.85, iterations=20, out=None, ws=N
     _check(lib().b2sr_pagerank_directed(At.view, float(damping), int(iterations), _ptr(out), _ptr(ws), need,
                                         _stream()), "b2sr_pagerank_directed")
     return out
+
+
+def mis_keys(n: int, seed: int) -> torch.Tensor:
+    """Distinct nonzero keys for b2sr_mis / b2sr_color: a random 32-bit
+    priority above the vertex id + 1 (so ties are impossible), as an int64
+    device tensor holding the uint64 bits."""
+    r = np.random.Generator(np.random.PCG64(seed)).integers(0, 1 << 31, size=n, dtype=np.uint64)
+    k = (r << np.uint64(32)) | (np.arange(n, dtype=np.uint64) + np.uint64(1))
+    return torch.from_numpy(k.view(np.int64)).cuda()
+
+
+def b2sr_mis(A: B2SR, key, out=None, ws=None):
+    """(membership bit vector int32 tensor, rounds) of the max-times independent set."""
+    out = torch.empty(max(_words(A.n), 1), dtype=torch.int32, device="cuda") if out is None else out
+    ws, need = _ws(A, ALGO_MIS, ws)
+    it = _U32(0)
+    _check(lib().b2sr_mis(A.view, _ptr(key), _ptr(out), _ptr(ws), need, ctypes.byref(it), _stream()), "b2sr_mis")
+    return out, it.value
+
+
+def b2sr_color(A: B2SR, key, out=None, ws=None):
+    """(colour per vertex int32 tensor with uint32 bits, colours used)."""
+    out = torch.empty(A.n, dtype=torch.int32, device="cuda") if out is None else out
+    ws, need = _ws(A, ALGO_COLOR, ws)
+    nc = _U32(0)
+    _check(lib().b2sr_color(A.view, _ptr(key), _ptr(out), _ptr(ws), need, ctypes.byref(nc), _stream()),
+           "b2sr_color")
+    return out, nc.value
 
 
 def b2sr_csr_transpose(n: int, rowptr, colind):

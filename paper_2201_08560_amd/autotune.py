@@ -67,3 +67,53 @@ def choose_tile(g, value_bytes: int = 8, beta: float = 0.25, nsample: int = 1024
     cost = product_cost(tiles, value_bytes, beta)
     best = min(cost, key=lambda k: (cost[k], k))
     return best, {"sampling_estimate": prof, "ntiles": tiles, "cost": cost}
+
+
+def _load_graph(spec: str):
+    """A graph from a generator spec (rmat:SCALE:EF[:SEED], rmat_dir:SCALE:EF[:SEED],
+    er:N:M[:SEED], king:R:C) or an .npz file holding n, rowptr and colind."""
+    import graphgen as gg
+    if spec.endswith(".npz"):
+        z = np.load(spec, allow_pickle=False)
+        return gg.Csr(int(z["n"]), z["rowptr"].astype(np.uint32), z["colind"].astype(np.uint32), spec)
+    kind, *args = spec.split(":")
+    a = [int(v) for v in args]
+    if kind == "rmat":
+        return gg.rmat(a[0], a[1], seed=a[2] if len(a) > 2 else 0)
+    if kind == "rmat_dir":
+        return gg.rmat_directed(a[0], a[1], seed=a[2] if len(a) > 2 else 0)
+    if kind == "er":
+        return gg.er_gnm(a[0], a[1], seed=a[2] if len(a) > 2 else 0)
+    if kind == "king":
+        return gg.king_grid(a[0], a[1])
+    raise ValueError(f"unknown graph spec {spec!r}")
+
+
+def main(argv=None) -> int:
+    """Command line: the sampling profile of Algorithm 1 for a graph, and with
+    a GPU the exact tile counts, the modelled product costs and the choice."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(prog="python -m paper_2201_08560_amd.autotune", description=main.__doc__)
+    ap.add_argument("graph", help="rmat:S:EF[:SEED] | rmat_dir:S:EF[:SEED] | er:N:M[:SEED] | king:R:C | file.npz")
+    ap.add_argument("--sample", type=int, default=1024, help="rows sampled for the profile")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--value-bytes", type=int, default=8, help="bytes of a vector value staged per tile column")
+    ap.add_argument("--no-exact", action="store_true", help="only the sampling profile (no GPU needed)")
+    args = ap.parse_args(argv)
+    g = _load_graph(args.graph)
+    out = {"graph": g.name, "n": g.n, "nnz": g.nnz,
+           "sampling_estimate_b2sr_over_csr": sampling_profile(g.rowptr, g.colind, g.n, args.sample, args.seed)}
+    if not args.no_exact:
+        tiles = exact_tiles(g.rowptr, g.colind, g.n)
+        cost = product_cost(tiles, args.value_bytes)
+        out.update({"ntiles": tiles, "exact_b2sr_over_csr": {
+            k: (4 * ((g.n + k - 1) // k + 1) + tiles[k] * (4 + k * ROW_BYTES[k])) / (8.0 * g.nnz + 4.0 * (g.n + 1))
+            for k in TILES} if g.nnz else {}, "product_cost_bytes": cost,
+            "choice": min(cost, key=lambda k: (cost[k], k))})
+    print(json.dumps(out, indent=1))
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

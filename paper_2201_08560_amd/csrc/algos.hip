@@ -221,6 +221,80 @@ __global__ void pr_scale_kernel(uint32_t n, const float *r, const float *inv, fl
         z[i] = r[i] * inv[i];
 }
 
+// ---------------------------------------------------------------- MIS / colouring
+// Candidates carry their key in X (0 = not a candidate).  Each wave walks 64
+// consecutive vertices at a time so ballots form whole bit-vector words.
+
+// X = key for the vertices still to place (uncoloured when colors is given).
+__global__ void mis_start_kernel(uint32_t n, const uint64_t *key, const uint32_t *colors, uint64_t *X, uint32_t *act,
+                                 uint32_t *flag_now, uint32_t *flag_next)
+{
+    bool any = false;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
+         base += waves * 64) {
+        const uint64_t i = base + lane_id();
+        uint64_t x = 0;
+        if (i < n) {
+            x = (!colors || colors[i] == kUnreached) ? key[i] : 0ull;
+            X[i] = x;
+        }
+        any |= x != 0;
+        store_pred_bits(act, base, n, x != 0);
+    }
+    if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(flag_now, 1u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
+}
+
+// A candidate joins when its key is at least the largest candidate key among
+// its neighbours (Y = A max-times X).
+__global__ void mis_join_kernel(uint32_t n, const uint64_t *X, const uint64_t *Y, uint32_t *joined, uint32_t *mis_bits,
+                                uint32_t *colors, uint32_t color)
+{
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
+         base += waves * 64) {
+        const uint64_t i = base + lane_id();
+        bool j = false;
+        if (i < n) {
+            const uint64_t x = X[i];
+            j = x != 0 && x >= Y[i];
+            if (j && colors) colors[i] = color;
+        }
+        const uint64_t m = __ballot(j);
+        const uint64_t w = base / 32 + lane_id();
+        if (lane_id() < 2 && w < (n + 31u) / 32u) {
+            const uint32_t word = (uint32_t)(m >> (32 * lane_id()));
+            joined[w] = word;
+            if (mis_bits) mis_bits[w] |= word;  // this wave owns the word
+        }
+    }
+}
+
+// Joined vertices and their neighbours (nb = A OR joined) stop being candidates.
+__global__ void mis_remove_kernel(uint32_t n, uint64_t *X, const uint32_t *joined, const uint32_t *nb, uint32_t *act,
+                                  uint32_t *flag_now, uint32_t *flag_next)
+{
+    bool any = false;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
+         base += waves * 64) {
+        const uint64_t i = base + lane_id();
+        uint64_t x = 0;
+        if (i < n) {
+            x = X[i];
+            if (x && (((joined[i >> 5] | nb[i >> 5]) >> (i & 31)) & 1u)) {
+                x = 0;
+                X[i] = 0;
+            }
+        }
+        any |= x != 0;
+        store_pred_bits(act, base, n, x != 0);
+    }
+    if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(flag_now, 1u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
+}
+
 unsigned vgrid(uint64_t n) { return b2sr::grid_for(n, 256, 8192); }
 // Grids of the kernels that raise a convergence flag: at most 1024 blocks, so
 // at most 1024 atomics on the flag word.
@@ -268,6 +342,14 @@ Layout carve(const b2sr_matrix *A, int algo, void *ws)
         L.u0 = c.take<uint32_t>(n * 4);
         L.act = c.take<uint32_t>(nw * 4);
         break;
+    case B2SR_ALGO_MIS:
+    case B2SR_ALGO_COLOR:
+        L.F = c.take<uint64_t>(n * 8);  // candidate keys X
+        L.Y = c.take<uint64_t>(n * 8);  // max-times product
+        L.frontier = c.take<uint32_t>(nw * 4);  // joined this round
+        L.next = c.take<uint32_t>(nw * 4);      // neighbours of the joined
+        L.act = c.take<uint32_t>(nw * 4);       // candidates
+        break;
     case B2SR_ALGO_PAGERANK:
         L.f0 = c.take<float>(n * 4);  // z = r / deg
         L.f1 = c.take<float>(n * 4);  // 1 / deg
@@ -300,7 +382,7 @@ extern "C" {
 
 size_t b2sr_algo_workspace_bytes(const b2sr_matrix *A, int algo)
 {
-    if (!A || !b2sr::valid_tile(A->tile) || algo < B2SR_ALGO_BFS || algo > B2SR_ALGO_MSBFS) return 0;
+    if (!A || !b2sr::valid_tile(A->tile) || algo < B2SR_ALGO_BFS || algo > B2SR_ALGO_COLOR) return 0;
     return carve(A, algo, nullptr).bytes;
 }
 
@@ -493,6 +575,76 @@ int b2sr_pagerank_directed(const b2sr_matrix *At, float damping, uint32_t iterat
                            size_t ws_bytes, hipStream_t stream)
 {
     return pagerank(At, true, damping, iterations, rank, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Rounds of local maxima under max-times (Table V: MIS and colouring).  With
+// colors == nullptr: one independent set into mis_bits.  Otherwise colour c is
+// the independent set of the vertices still uncoloured, c = 0, 1, ...
+int independent_sets(const b2sr_matrix *A, const uint64_t *key, uint32_t *mis_bits, uint32_t *colors, void *ws,
+                     size_t ws_bytes, uint32_t *iters, uint32_t *ncolors, hipStream_t stream)
+{
+    Layout L;
+    int rc = check_algo_args(A, colors ? B2SR_ALGO_COLOR : B2SR_ALGO_MIS, ws, ws_bytes, &L);
+    if (rc) return rc;
+    const uint32_t n = A->n, nw = b2sr::n_words(n);
+    if (n > 0 && (!key || (!mis_bits && !colors))) return B2SR_EINVAL;
+    if (mis_bits && (rc = b2sr::fill_u32(mis_bits, nw, 0, stream))) return rc;
+    if (colors && (rc = b2sr::fill_u32(colors, n, kUnreached, stream))) return rc;
+    if ((rc = b2sr::fill_u32(L.flags, 2, 0, stream))) return rc;
+    uint32_t rounds = 0, color = 0, f = 0;
+    auto flags = [&](uint32_t **now, uint32_t **next) {
+        *now = L.flags + (f & 1);
+        *next = L.flags + ((f + 1) & 1);
+        ++f;
+    };
+    while (n > 0) {  // one colour per pass (a single pass for MIS)
+        uint32_t *fnow, *fnext, any = 0;
+        flags(&fnow, &fnext);
+        mis_start_kernel<<<fgrid(n), 256, 0, stream>>>(n, key, colors, L.F, L.act, fnow, fnext);
+        if ((rc = b2sr::check_launch("mis_start_kernel"))) return rc;
+        if ((rc = read_flag(fnow, &any, stream))) return rc;
+        if (!any) break;
+        // every round places at least the candidate of largest key, so a pass ends
+        for (;;) {
+            ++rounds;
+            if ((rc = spmv_bin_full(A, B2SR_MAX_TIMES_U64, L.F, nullptr, L.act, nullptr, 0, 0.0, 0.0, L.Y, nullptr,
+                                    0, stream)))
+                return rc;
+            mis_join_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.F, L.Y, L.frontier, mis_bits, colors, color);
+            if ((rc = b2sr::check_launch("mis_join_kernel"))) return rc;
+            if ((rc = spmv_bin_bin(A, L.frontier, nullptr, 0, L.next, stream))) return rc;
+            flags(&fnow, &fnext);
+            mis_remove_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.F, L.frontier, L.next, L.act, fnow, fnext);
+            if ((rc = b2sr::check_launch("mis_remove_kernel"))) return rc;
+            if ((rc = read_flag(fnow, &any, stream))) return rc;
+            if (!any) break;
+        }
+        ++color;
+        if (!colors) break;
+    }
+    if (iters) *iters = rounds;
+    if (ncolors) *ncolors = colors ? color : 0;
+    return B2SR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int b2sr_mis(const b2sr_matrix *A, const uint64_t *key, uint32_t *mis_bits, void *ws, size_t ws_bytes,
+             uint32_t *iters, hipStream_t stream)
+{
+    return independent_sets(A, key, mis_bits, nullptr, ws, ws_bytes, iters, nullptr, stream);
+}
+
+int b2sr_color(const b2sr_matrix *A, const uint64_t *key, uint32_t *colors, void *ws, size_t ws_bytes,
+               uint32_t *ncolors, hipStream_t stream)
+{
+    return independent_sets(A, key, nullptr, colors, ws, ws_bytes, nullptr, ncolors, stream);
 }
 
 }  // extern "C"

@@ -199,7 +199,7 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
 {
     int rc = b2sr::validate_matrix(A);
     if (rc) return rc;
-    if (semiring < B2SR_PLUS_TIMES_F32 || semiring > B2SR_OR_U64) return B2SR_ENOTSUP;
+    if (semiring < B2SR_PLUS_TIMES_F32 || semiring > B2SR_MAX_TIMES_U64) return B2SR_ENOTSUP;
     if (flags & ~(B2SR_MASK_COMPLEMENT | B2SR_ACCUMULATE | B2SR_SELF)) return B2SR_EINVAL;
     if ((flags & B2SR_SELF) && semiring != B2SR_MIN_PLUS_F32 && semiring != B2SR_MIN_PLUS_U32) return B2SR_EINVAL;
     if (col_scale && semiring != B2SR_PLUS_TIMES_F32) return B2SR_EINVAL;
@@ -232,6 +232,7 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
     case B2SR_PLUS_TIMES_F32: return dispatch<kPlusF32>(A->tile, p, stream);
     case B2SR_MIN_PLUS_F32: return dispatch<kMinF32>(A->tile, p, stream);
     case B2SR_MIN_PLUS_U32: return dispatch<kMinU32>(A->tile, p, stream);
+    case B2SR_MAX_TIMES_U64: return dispatch<kMaxU64>(A->tile, p, stream);
     default: return dispatch<kOr64>(A->tile, p, stream);
     }
 }

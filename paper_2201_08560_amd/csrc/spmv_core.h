@@ -35,7 +35,7 @@ template <class P> __device__ __forceinline__ P load_stream(const P *p)
 #endif
 }
 
-enum Kind : int { kBits = 0, kCount = 1, kPlusF32 = 2, kMinF32 = 3, kMinU32 = 4, kOr64 = 5 };
+enum Kind : int { kBits = 0, kCount = 1, kPlusF32 = 2, kMinF32 = 3, kMinU32 = 4, kOr64 = 5, kMaxU64 = 6 };
 
 template <int K> struct KindTraits;
 template <> struct KindTraits<kBits> {
@@ -67,6 +67,11 @@ template <> struct KindTraits<kOr64> {
     using V = uint64_t;
     static __device__ __forceinline__ V id() { return 0ull; }
     static __device__ __forceinline__ V op(V a, V b) { return a | b; }
+};
+template <> struct KindTraits<kMaxU64> {
+    using V = uint64_t;
+    static __device__ __forceinline__ V id() { return 0ull; }
+    static __device__ __forceinline__ V op(V a, V b) { return b > a ? b : a; }
 };
 
 struct SpmvArgs {
@@ -270,6 +275,8 @@ __device__ __forceinline__ void store_values(const SpmvArgs &p, uint32_t I, uint
             if (v[k] != KT::id()) atomic_min_f32((float *)p.y + row, v[k] + p.alpha);
         } else if constexpr (K == kMinU32) {
             if (v[k] != KT::id()) atomicMin((uint32_t *)p.y + row, sat_add_u32(v[k], p.w_u32));
+        } else if constexpr (K == kMaxU64) {
+            if (v[k]) atomicMax((unsigned long long *)p.y + row, (unsigned long long)v[k]);
         } else {
             if (v[k]) atomicOr((unsigned long long *)p.y + row, (unsigned long long)v[k]);
         }

@@ -94,7 +94,7 @@ def test_algorithm_argument_errors():
     A = ctypes.byref(mat())
     need = L.b2sr_algo_workspace_bytes(A, b2.ALGO_BFS)
     assert need > 0
-    for algo in (b2.ALGO_BFS, b2.ALGO_SSSP, b2.ALGO_CC, b2.ALGO_PAGERANK, b2.ALGO_MSBFS):
+    for algo in (b2.ALGO_BFS, b2.ALGO_SSSP, b2.ALGO_CC, b2.ALGO_PAGERANK, b2.ALGO_MSBFS, b2.ALGO_MIS, b2.ALGO_COLOR):
         assert L.b2sr_algo_workspace_bytes(A, algo) > 0
     assert L.b2sr_algo_workspace_bytes(A, 99) == 0
     p = ctypes.c_void_p(FAKE)
@@ -197,3 +197,15 @@ def test_transpose_argument_errors():
     assert L.b2sr_csr_transpose(100, 1 << 32, p, p, p, p, p, need, None) == -2
     A = mat(n=64, tile=5)
     assert L.b2sr_pagerank_directed(ctypes.byref(A), 0.85, 1, p, p, 1 << 20, None) == -1
+
+
+def test_mis_color_argument_errors():
+    A = mat(n=64, tile=8)
+    need = L.b2sr_algo_workspace_bytes(ctypes.byref(A), 6)
+    assert need >= 64 * 16 and L.b2sr_algo_workspace_bytes(ctypes.byref(A), 7) == need
+    p = FAKE
+    assert L.b2sr_mis(ctypes.byref(A), None, p, p, need, None, None) == -1
+    assert L.b2sr_mis(ctypes.byref(A), p, None, p, need, None, None) == -1
+    assert L.b2sr_mis(ctypes.byref(A), p, p, None, need, None, None) == -3
+    assert L.b2sr_color(ctypes.byref(A), p, None, p, need, None, None) == -1
+    assert L.b2sr_color(ctypes.byref(A), p, p, p, need - 1, None, None) == -3

@@ -259,6 +259,41 @@ def test_spmv_or_u64(gi, T):
         assert np.array_equal(y, np.where(keep, orc.spmv_or64(g, x), np.uint64(0)))
 
 
+@pytest.mark.parametrize("T", TILES)
+@pytest.mark.parametrize("gi", range(len(GRAPHS)), ids=IDS)
+def test_spmv_max_times(gi, T):
+    g = GRAPHS[gi]
+    A = b2sr(g, T)
+    r = gg.rng(600 + gi)
+    x = r.integers(0, 1 << 63, size=g.n, dtype=np.uint64) * (r.random(g.n) < 0.4)
+    xd = torch.from_numpy(x.view(np.int64)).cuda()
+    ref = orc.spmv_max(g, x)
+    assert np.array_equal(b2.as_u64(b2.spmv_bin_full(A, b2.MAX_TIMES_U64, xd)), ref)
+    act = dev_u32(pack_bits(x != 0))  # only the non-zero entries: the same maximum
+    assert np.array_equal(b2.as_u64(b2.spmv_bin_full(A, b2.MAX_TIMES_U64, xd, x_active=act)), ref)
+    for mask, comp in masks_for(g.n, 9 + gi):
+        md = None if mask is None else dev_u32(pack_bits(mask))
+        keep = np.ones(g.n, bool) if mask is None else (~mask if comp else mask)
+        y = b2.as_u64(b2.spmv_bin_full(A, b2.MAX_TIMES_U64, xd, None, md, comp))
+        assert np.array_equal(y, np.where(keep, ref, np.uint64(0)))
+
+
+@pytest.mark.parametrize("T", TILES)
+@pytest.mark.parametrize("gi", range(len(GRAPHS)), ids=IDS)
+def test_mis_and_color(gi, T):
+    g = GRAPHS[gi]
+    A = b2sr(g, T)
+    key = b2.mis_keys(g.n, 40 + gi)
+    k = b2.as_u64(key)
+    m, rounds = b2.b2sr_mis(A, key)
+    exp, exp_rounds = orc.mis(g, k)
+    assert np.array_equal(unpack_bits(b2.as_u32(m), g.n), exp) and rounds == exp_rounds
+    assert padding_zero(b2.as_u32(m), g.n)
+    col, nc = b2.b2sr_color(A, key)
+    exp_col, exp_nc = orc.color(g, k)
+    assert nc == exp_nc and np.array_equal(b2.as_u32(col), exp_col)
+
+
 # ------------------------------------------------------------------ masked SpGEMM
 
 @pytest.mark.parametrize("T", TILES)

@@ -444,3 +444,74 @@ def test_directed_pagerank_pins():
         for _ in range(6):
             r = (1 - d) / g.n + d * A.T @ np.divide(r, o, out=np.zeros_like(r), where=o > 0)
         assert np.allclose(orc.pagerank_directed(g, d, 6), r, rtol=1e-12, atol=0)
+
+
+# ---- max-times: MIS and colouring (Table V) ------------------------------------
+
+def _keys(n, seed):
+    r = np.random.default_rng(seed).integers(0, 1 << 31, size=n, dtype=np.uint64)
+    return (r << np.uint64(32)) | (np.arange(n, dtype=np.uint64) + np.uint64(1))
+
+
+def test_spmv_max_brute_force():
+    for seed in range(3):
+        g = gg.random_graph_tiny(40, 0.15, 900 + seed)
+        x = np.random.default_rng(seed).integers(0, 1 << 62, size=g.n, dtype=np.uint64)
+        x[::3] = 0
+        A = g.dense().astype(bool)
+        exp = np.array([x[A[i]].max() if A[i].any() else 0 for i in range(g.n)], dtype=np.uint64)
+        assert np.array_equal(orc.spmv_max(g, x), exp)
+
+
+def _independent_and_maximal(g, inset, among=None):
+    A = g.dense().astype(bool)
+    among = np.ones(g.n, bool) if among is None else among
+    assert not (A & np.outer(inset, inset)).any()                       # independent
+    covered = inset | (A[:, inset].any(1) if inset.any() else np.zeros(g.n, bool))
+    assert np.all(covered[among])                                       # maximal among the candidates
+
+
+def test_mis_pins():
+    for seed in range(6):
+        g = gg.random_graph_tiny(60, 0.08, 950 + seed)
+        k = _keys(g.n, seed)
+        m, rounds = orc.mis(g, k)
+        assert np.array_equal(m, orc.mis_greedy(g, k))   # rounds of local maxima == sequential greedy
+        _independent_and_maximal(g, m)
+        assert rounds >= 1
+    n = 30
+    K = gg.complete(n)
+    k = _keys(n, 1)
+    assert np.flatnonzero(orc.mis(K, k)[0]).tolist() == [int(np.argmax(k))]
+    p = gg.path(n)
+    up = np.arange(1, n + 1, dtype=np.uint64)           # keys increase along the path
+    assert np.flatnonzero(orc.mis(p, up)[0]).tolist() == list(range(n - 1, -1, -2))[::-1]
+    s = gg.star(10)                                      # vertex 0 is the centre
+    hi = np.r_[100, np.arange(1, 10)].astype(np.uint64)
+    lo = np.r_[1, np.arange(2, 11)].astype(np.uint64)
+    assert np.flatnonzero(orc.mis(s, hi)[0]).tolist() == [0]
+    assert np.flatnonzero(orc.mis(s, lo)[0]).tolist() == list(range(1, 10))
+    e = gg.canonical_csr(5, [], [])
+    assert orc.mis(e, _keys(5, 2))[0].all()
+    z = _keys(5, 3)
+    z[2] = 0                                             # key 0: never a candidate
+    assert not orc.mis(e, z)[0][2]
+
+
+def test_color_pins():
+    for seed in range(5):
+        g = gg.random_graph_tiny(50, 0.1, 970 + seed)
+        k = _keys(g.n, seed)
+        col, nc = orc.color(g, k)
+        A = g.dense().astype(bool)
+        assert np.all(col < nc)
+        assert not (A & (col[:, None] == col[None, :])).any()          # proper
+        for c in range(nc):                                             # class c: MIS of what was left
+            _independent_and_maximal(g, col == c, among=col >= c)
+        assert nc <= int(g.degrees().max(initial=0)) + 1
+    K = gg.complete(12)
+    col, nc = orc.color(K, _keys(12, 4))
+    assert nc == 12 and sorted(col.tolist()) == list(range(12))
+    e = gg.canonical_csr(7, [], [])
+    col, nc = orc.color(e, _keys(7, 5))
+    assert nc == 1 and not col.any()
