@@ -257,6 +257,27 @@ def batched_section(graphs, reps: int = 3) -> dict:
             "speedup_best_batched_vs_per_graph": res["per_graph"]["ms"] / res[best]["ms"]}
 
 
+def stream_read_ceiling(w: "Workload", reps: int = 7) -> dict:
+    """The read-only bandwidth of a plain stream over the same number of bytes
+    as the headline product (its matrix's tile bits plus a tail of indices):
+    the practical ceiling the product is compared with."""
+    nbytes = spmv_bytes(w.A, True) & ~15
+    buf = w.A.bits if w.A.bits.numel() >= nbytes else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    if buf.numel() < nbytes:
+        nbytes = buf.numel() & ~15
+    out = b2.b2sr_stream_read(buf, nbytes)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b2.b2sr_stream_read(buf, nbytes, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    t = float(np.median(ts))
+    return {"bytes": nbytes, "ms": 1e3 * t, "GB_per_s": nbytes / t / 1e9, "frac_of_peak": nbytes / t / 1e9 / HBM_PEAK_GBS}
+
+
 def cold_warm(w: "Workload", reps: int = 5) -> dict:
     """The headline product timed warm (back to back) and cold (a 1 GiB write
     between launches evicts the 256 MB Infinity Cache and the L2s)."""
@@ -519,6 +540,9 @@ def main():
                      "kernel_source_digest": digest},
         "convert_ms": w.convert_s * 1e3,
     }
+    ceiling = stream_read_ceiling(w)
+    out["roofline"]["stream_read_ceiling"] = ceiling
+    out["roofline"]["frac_of_stream_read"] = (alg / kt / 1e9) / ceiling["GB_per_s"]
     if not args.no_extras:
         out["verify"] = verify(w)
         out["bfs_single_source"] = bfs_gteps(w)

@@ -423,6 +423,17 @@ int b2sr_bfs_session_extract(b2sr_bfs_session session, uint32_t slot, uint32_t *
 int b2sr_bfs_session_info(b2sr_bfs_session session, uint32_t *step, uint64_t *busy);
 int b2sr_bfs_session_destroy(b2sr_bfs_session session);
 
+/* ---- calibration -----------------------------------------------------------
+ * b2sr_stream_read: reads bytes / 16 consecutive 16-byte vectors at p (device,
+ *   16-byte aligned) with nontemporal loads over B2SR_STREAM_READ_BLOCKS
+ *   workgroups of 256 threads and writes to out (device,
+ *   B2SR_STREAM_READ_BLOCKS words) one word per workgroup whose XOR over all
+ *   workgroups is the XOR of every 32-bit word read.  Its time is the read-only
+ *   bandwidth a product kernel's stream is compared with.  Errors: EINVAL, EHIP.
+ */
+#define B2SR_STREAM_READ_BLOCKS 8192
+int b2sr_stream_read(const void *p, size_t bytes, uint32_t *out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

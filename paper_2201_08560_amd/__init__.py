@@ -89,6 +89,7 @@ _SIGS = {
     "b2sr_pagerank": (_I, [_MP, ctypes.c_float, _U32, _P, _P, _SZ, _P]),
     "b2sr_pagerank_directed": (_I, [_MP, ctypes.c_float, _U32, _P, _P, _SZ, _P]),
     "b2sr_mis": (_I, [_MP, _P, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
+    "b2sr_stream_read": (_I, [_P, _SZ, _P, _P]),
     "b2sr_color": (_I, [_MP, _P, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_csr_transpose_workspace_bytes": (_SZ, [_U32]),
     "b2sr_csr_transpose": (_I, [_U32, _U64, _P, _P, _P, _P, _P, _SZ, _P]),
@@ -366,6 +367,17 @@ def b2sr_pagerank_directed(At: B2SR, damping=0.85, iterations=20, out=None, ws=N
     ws, need = _ws(At, ALGO_PAGERANK, ws)
     _check(lib().b2sr_pagerank_directed(At.view, float(damping), int(iterations), _ptr(out), _ptr(ws), need,
                                         _stream()), "b2sr_pagerank_directed")
+    return out
+
+
+STREAM_READ_BLOCKS = 8192
+
+
+def b2sr_stream_read(t: torch.Tensor, nbytes: int | None = None, out=None):
+    """Streams the bytes of device tensor t once (roofline calibration)."""
+    nbytes = t.numel() * t.element_size() if nbytes is None else nbytes
+    out = torch.empty(STREAM_READ_BLOCKS, dtype=torch.int32, device="cuda") if out is None else out
+    _check(lib().b2sr_stream_read(_ptr(t), nbytes, _ptr(out), _stream()), "b2sr_stream_read")
     return out
 
 

@@ -209,3 +209,10 @@ def test_mis_color_argument_errors():
     assert L.b2sr_mis(ctypes.byref(A), p, p, None, need, None, None) == -3
     assert L.b2sr_color(ctypes.byref(A), p, None, p, need, None, None) == -1
     assert L.b2sr_color(ctypes.byref(A), p, p, p, need - 1, None, None) == -3
+
+
+def test_stream_read_argument_errors():
+    assert L.b2sr_stream_read(None, 64, FAKE, None) == -1
+    assert L.b2sr_stream_read(FAKE, 64, None, None) == -1
+    assert L.b2sr_stream_read(FAKE + 4, 64, FAKE, None) == -1   # not 16-byte aligned
+    assert L.b2sr_stream_read(FAKE, 8, FAKE, None) == 0         # under one vector: nothing to read

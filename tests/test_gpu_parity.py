@@ -401,3 +401,12 @@ def test_pagerank_deterministic_and_mass():
         b = b2.b2sr_pagerank(A, 0.85, 20).cpu().numpy()
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
         assert rel_l1(a, orc.pagerank(g, 0.85, 20)) <= 1e-5
+
+
+def test_stream_read_reads_every_word():
+    r = gg.rng(77)
+    for nbytes in (16, 16 * 1000, 16 * 8192 * 256 * 3 + 16 * 5):
+        h = r.integers(0, 2**32, size=nbytes // 4, dtype=np.uint64).astype(np.uint32)
+        t = torch.from_numpy(h.view(np.int32)).cuda()
+        out = b2.as_u32(b2.b2sr_stream_read(t, nbytes))
+        assert np.bitwise_xor.reduce(out) == np.bitwise_xor.reduce(h)
