@@ -35,14 +35,15 @@ using namespace b2sr_core;
 
 namespace {
 
-template <int T, int K, bool ACT> __global__ void __launch_bounds__(256) spmv_kernel(SpmvArgs p)
+template <int T, int K, bool ACT, bool SHORT = false> __global__ void __launch_bounds__(256) spmv_kernel(SpmvArgs p)
 {
     using V = typename KindTraits<K>::V;
     constexpr bool stage = Cfg<T, K>::kStage;
     __shared__ __align__(16) V s_x[stage ? 4 * kStageBytesPerWave / sizeof(V) : 1];
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     if (wave * p.chunk >= p.ntiles) return;
-    spmv_chunk<T, K, ACT>(p, (uint32_t)wave, s_x + (stage ? (threadIdx.x / B2SR_WAVE) * kStageBytesPerWave / sizeof(V) : 0));
+    spmv_chunk<T, K, ACT, SHORT>(p, (uint32_t)wave,
+                                 s_x + (stage ? (threadIdx.x / B2SR_WAVE) * kStageBytesPerWave / sizeof(V) : 0));
 }
 
 // Float sums of rows that straddle chunks.  One thread per (chunk, row of a
@@ -104,7 +105,12 @@ __global__ void zero_words_kernel(uint32_t *__restrict__ y, uint32_t nwords)
 
 template <int T, int K> int launch(SpmvArgs p, hipStream_t stream)
 {
-    p.chunk = chunk_tiles<T, K>(p.ntiles);
+    // bit and count products: short blocks when the mean tile-row is shorter
+    // than a long block, or under the sparse-frontier hint
+    bool short_blocks = false;
+    if constexpr (!Cfg<T, K>::kStage)
+        short_blocks = (p.flags & B2SR_SPARSE_X) || (uint64_t)p.ntiles < (uint64_t)p.ntr * Cfg<T, K>::BT;
+    p.chunk = short_blocks ? chunk_tiles<T, K, true>(p.ntiles) : chunk_tiles<T, K>(p.ntiles);
     const uint32_t nchunks = (uint32_t)((p.ntiles + (uint64_t)p.chunk - 1) / p.chunk);
     if (!(p.flags & B2SR_ACCUMULATE) || K >= kPlusF32) {
         if constexpr (K == kBits) {
@@ -119,6 +125,8 @@ template <int T, int K> int launch(SpmvArgs p, hipStream_t stream)
     if constexpr (Cfg<T, K>::kStage) {
         if (p.xact) spmv_kernel<T, K, true><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
         else spmv_kernel<T, K, false><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
+    } else if (short_blocks) {
+        spmv_kernel<T, K, false, true><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
     } else {
         spmv_kernel<T, K, false><<<b2sr::grid_for(nchunks, 4), 256, 0, stream>>>(p);
     }

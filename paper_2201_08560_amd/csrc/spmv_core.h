@@ -15,6 +15,9 @@
 #ifndef B2SR_BITS_STEPS_SMALL
 #define B2SR_BITS_STEPS_SMALL 8  // the same for T <= 16
 #endif
+#ifndef B2SR_BITS_STEPS_SHORT
+#define B2SR_BITS_STEPS_SHORT 4  // the same for short tile-rows and sparse frontiers
+#endif
 #ifndef B2SR_STAGE_BYTES
 #define B2SR_STAGE_BYTES 4096    // LDS bytes per wave for staged x segments
 #endif
@@ -94,12 +97,16 @@ struct SpmvArgs {
 // Block shape per tile width and kind.  Bit and count products read the x
 // segment as T bits; the others stage T values per tile in LDS (a fixed budget
 // per wave, so the block shrinks as the vector values widen).
-template <int T, int K> struct Cfg {
+// SHORT (bit and count products): fewer steps per block, for matrices whose
+// tile-rows are shorter than a block and for sparse frontiers; fewer
+// registers then buy occupancy where the long blocks' loads would be cut short.
+template <int T, int K, bool SHORT = false> struct Cfg {
     using S = TileShape<T>;
     static constexpr int LPT = S::LPT, RPL = S::RPL, TPW = S::TPW;
     static constexpr bool kStage = K >= kPlusF32;
     static constexpr int VB = sizeof(typename KindTraits<K>::V);
     static constexpr int U = kStage ? B2SR_STAGE_BYTES / (TPW * T * VB)
+                           : SHORT  ? B2SR_BITS_STEPS_SHORT
                                     : (T == 32 ? B2SR_BITS_STEPS : B2SR_BITS_STEPS_SMALL);
     static constexpr int BT = U * TPW;                 // tiles per block
     static constexpr int JK = BT >= 64 ? BT / 64 : 1;  // tile-column registers per lane
@@ -110,9 +117,9 @@ template <int T, int K> struct Cfg {
 // Tiles per wave chunk: whole blocks, aiming at about 32K waves per launch,
 // between 1 and 16 blocks.  A pure function of (T, kind, ntiles), so the
 // float-sum workspace query and the launch agree.
-template <int T, int K> inline uint32_t chunk_tiles(uint32_t ntiles)
+template <int T, int K, bool SHORT = false> inline uint32_t chunk_tiles(uint32_t ntiles)
 {
-    constexpr uint32_t bt = Cfg<T, K>::BT;
+    constexpr uint32_t bt = Cfg<T, K, SHORT>::BT;
     constexpr uint64_t waves = B2SR_TARGET_WAVES;
     uint64_t nb = ((uint64_t)ntiles + waves * bt - 1) / (waves * bt);
     nb = nb < 1 ? 1 : (nb > 16 ? 16 : nb);
@@ -292,10 +299,10 @@ constexpr uint32_t kStageBytesPerWave = B2SR_STAGE_BYTES;
 
 // Processes tile chunk chunk_id (wave-uniform) of the product described by p.
 // xs is this wave's LDS slice (unused by bit and count products).
-template <int T, int K, bool ACT = false>
+template <int T, int K, bool ACT = false, bool SHORT = false>
 __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id, typename KindTraits<K>::V *xs)
 {
-    using C = Cfg<T, K>;
+    using C = Cfg<T, K, SHORT>;
     using KT = KindTraits<K>;
     using V = typename KT::V;
     using Piece = typename PieceT<T>::type;
