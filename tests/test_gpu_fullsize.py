@@ -1,0 +1,105 @@
+"""Parity at the benchmark's full size and launch configuration: R-MAT scale
+20, edge factor 16, B2SR-32, the same inputs and flags as the timed step; every
+output is compared with the oracle (which runs these sizes in seconds), and
+triangle counting on R-MAT scale 18 at every tile width."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle as orc
+from helpers import EPS32, TILES, pack_bits, padding_zero, rel_l1, unpack_bits
+
+pytestmark = pytest.mark.gpu
+b2 = pytest.importorskip("paper_2201_08560_amd")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+@pytest.fixture(scope="module")
+def big():
+    print("generating R-MAT s20 ef16", flush=True)
+    g = gg.rmat(20, 16, seed=20)
+    A = b2.B2SR.from_graph(g, 32)
+    r = gg.rng(2020)
+    n = g.n
+    pred = r.random(n) < 0.5
+    mask = r.random(n) < 0.01
+    xf = r.random(n).astype(np.float32)
+    xd = np.where(r.random(n) < 0.5, r.integers(0, 20, n), np.inf).astype(np.float32)
+    return {"g": g, "A": A, "pred": pred, "mask": mask, "xf": xf, "xd": xd,
+            "sources": gg.sample_sources(g, 64, seed=64)}
+
+
+def dev_bits(b):
+    return torch.from_numpy(pack_bits(b).view(np.int32)).cuda()
+
+
+def test_headline_products(big):
+    g, A, n = big["g"], big["A"], big["g"].n
+    ones, mask = np.ones(n, bool), big["mask"]
+    # the headline product: full frontier, 1 % visited mask, complemented, accumulated into zeros
+    y = torch.zeros((n + 31) // 32, dtype=torch.int32, device="cuda")
+    b2.spmv_bin_bin(A, dev_bits(ones), dev_bits(mask), complement=True, accumulate=True, out=y)
+    yb = b2.as_u32(y)
+    assert padding_zero(yb, n)
+    assert np.array_equal(unpack_bits(yb, n), orc.spmv_or(g, ones, mask, True))
+    # the same with the random half frontier the step packs, and under the sparse-frontier hint
+    half = big["pred"]
+    assert np.array_equal(unpack_bits(b2.as_u32(b2.spmv_bin_bin(A, dev_bits(half))), n), orc.spmv_or(g, half))
+    sparse = gg.rng(5).random(n) < 0.001
+    assert np.array_equal(unpack_bits(b2.as_u32(b2.spmv_bin_bin(A, dev_bits(sparse), sparse_x=True)), n),
+                          orc.spmv_or(g, sparse))
+    assert np.array_equal(b2.as_u32(b2.spmv_bin_bin(A, dev_bits(ones), count=True)), orc.spmv_count(g, ones))
+
+
+def test_value_products(big):
+    g, A = big["g"], big["A"]
+    xf, xd = big["xf"], big["xd"]
+    y = b2.spmv_bin_full(A, b2.PLUS_TIMES_F32, torch.from_numpy(xf).cuda()).cpu().numpy()
+    ref = orc.spmv_plus(g, xf.astype(np.float64))
+    bound = (g.degrees() + 2) * EPS32 * ref + 1e-30  # x >= 0: sum |terms| = the sum
+    assert np.all(np.abs(y - ref) <= bound)
+    ym = b2.spmv_bin_full(A, b2.MIN_PLUS_F32, torch.from_numpy(xd).cuda(), self_loop=True, alpha=1.0).cpu().numpy()
+    assert np.array_equal(ym, orc.spmv_min_plus(g, xd.astype(np.float64), 1.0, True).astype(np.float32))
+
+
+def test_algorithms(big):
+    g, A, src = big["g"], big["A"], big["sources"]
+    print("bfs / msbfs", flush=True)
+    assert np.array_equal(b2.as_u32(b2.b2sr_bfs(A, int(src[0]))[0]), orc.bfs(g, int(src[0])))
+    lvm, _ = b2.b2sr_msbfs(A, src[:16])
+    assert np.array_equal(b2.as_u32(lvm), orc.bfs_multi(g, src[:16]))
+    print("sssp / cc", flush=True)
+    assert np.array_equal(b2.as_u32(b2.b2sr_sssp(A, int(src[0]))[0]), orc.sssp_unit(g, int(src[0])))
+    assert np.array_equal(b2.as_u32(b2.b2sr_cc(A)[0]), orc.cc(g))
+    print("pagerank x 50", flush=True)
+    pr = b2.b2sr_pagerank(A, 0.85, 50).cpu().numpy()
+    assert rel_l1(pr, orc.pagerank(g, 0.85, 50)) <= 1e-5
+
+
+@pytest.mark.parametrize("T", TILES)
+def test_triangle_count_rmat18(T):
+    g = gg.rmat(18, 16, seed=18)
+    print(f"tc rmat18 T={T}", flush=True)
+    assert b2.triangle_count(g.rowptr, g.colind, g.n, T) == orc.tc(g) == 82552366
+
+
+def test_batched_full_config():
+    """The 256-graph batch (autotuned tile widths, 64 sources per graph): sampled
+    graphs' levels against the oracle; padding vertices stay unreached."""
+    from paper_2201_08560_amd import autotune
+    from paper_2201_08560_amd.batch import GraphBatch
+    graphs = gg.chung_lu_batch(256, 2.1, seed=1000, workers=1)  # no fork of a process using the GPU
+    tiles = [autotune.choose_tile(g, nsample=256)[0] for g in graphs]
+    B = GraphBatch(graphs, tiles)
+    B.set_sources([gg.sample_sources(g, 64, seed=1000 + i) for i, g in enumerate(graphs)])
+    lv, _ = B.run(b2.BATCH_LEVELS)
+    sizes = np.array([g.n for g in graphs])
+    sample = sorted({int(np.argmax(sizes)), int(np.argmin(sizes))} | set(gg.rng(9).choice(256, 6, replace=False).tolist()))
+    for i in sample:
+        print(f"batch graph {i} n={graphs[i].n} T={tiles[i]}", flush=True)
+        assert np.array_equal(B.levels_of_host(lv, i), orc.bfs_multi(graphs[i], B.sources[i]))
+    host = b2.as_u32(lv)
+    for i, g in enumerate(graphs):
+        assert np.all(host[int(B.offsets[i]) + g.n:int(B.offsets[i + 1])] == b2.UNREACHED)
