@@ -280,6 +280,7 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
 #define B2SR_ALGO_MSBFS 5
 #define B2SR_ALGO_MIS 6
 #define B2SR_ALGO_COLOR 7
+#define B2SR_ALGO_ECC 8
 size_t b2sr_algo_workspace_bytes(const b2sr_matrix *A, int algo);
 
 /* BFS (Sec. V): Boolean semiring, masked bin_bin_bin product per level with
@@ -330,6 +331,22 @@ int b2sr_mis(const b2sr_matrix *A, const uint64_t *key, uint32_t *mis_bits, void
  * undirected.  Workspace: b2sr_algo_workspace_bytes(A, B2SR_ALGO_COLOR). */
 int b2sr_color(const b2sr_matrix *A, const uint64_t *key, uint32_t *colors, void *ws,
                size_t ws_bytes, uint32_t *ncolors, hipStream_t stream);
+
+/* Eccentricities (BFS on the Boolean semiring, 64 sources at a time as bits of
+ * one frontier word, as b2sr_msbfs, without storing levels): ecc[s] = the
+ * largest finite BFS level from srcs[s] (0 for a vertex that reaches nothing).
+ * srcs and ecc are HOST arrays of nsrc entries (any count; repeats allowed).
+ * Reads one word per level, so it synchronises `stream`.  Workspace:
+ * b2sr_algo_workspace_bytes(A, B2SR_ALGO_ECC). */
+int b2sr_eccentricity(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32_t *ecc,
+                      void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Diameter: the largest finite distance between two vertices, as the largest
+ * eccentricity over every vertex (n / 64 batches of b2sr_eccentricity: exact,
+ * and as costly as n/64 multi-source BFS runs).  *diameter is a HOST word.
+ * Same workspace as b2sr_eccentricity. */
+int b2sr_diameter(const b2sr_matrix *A, uint32_t *diameter, void *ws, size_t ws_bytes,
+                  hipStream_t stream);
 
 /* PageRank of a directed graph: At is the transpose of the arc matrix (the
  * pull matrix), r_0 = 1/n, then r_i(v) = (1 - d)/n + d * sum_{u -> v} r(u) / o(u)

@@ -74,6 +74,7 @@ def lib():
         L.orc_pagerank.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_double, ctypes.c_uint32, _f64p]
         L.orc_pagerank_directed.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_double, ctypes.c_uint32, _f64p]
         L.orc_spmv_max.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u64p, _u64p]
+        L.orc_eccentricity.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u32p, ctypes.c_uint32, _u32p]
         L.orc_mis.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u64p, _u8p]
         L.orc_mis.restype = ctypes.c_uint32
         L.orc_mis_greedy.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u64p, _u8p]
@@ -251,6 +252,18 @@ def color(g, key):
     out = np.zeros(g.n, dtype=np.uint32)
     c = lib().orc_color(g.n, g.rowptr, g.colind, np.ascontiguousarray(key, dtype=np.uint64), out)
     return out, int(c)
+
+
+def eccentricity(g, srcs):
+    srcs = np.ascontiguousarray(srcs, dtype=np.uint32)
+    out = np.zeros(srcs.size, dtype=np.uint32)
+    lib().orc_eccentricity(g.n, g.rowptr, g.colind, srcs, srcs.size, out)
+    return out
+
+
+def diameter(g) -> int:
+    """The largest finite distance: the largest eccentricity over every vertex."""
+    return int(eccentricity(g, np.arange(g.n)).max(initial=0))
 
 
 def tc(g) -> int:

@@ -542,6 +542,26 @@ uint32_t orc_color(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, c
     return c;
 }
 
+/* Eccentricity of each source: the largest finite BFS level (0 when nothing
+ * else is reachable), one textbook BFS per source. */
+void orc_eccentricity(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, const uint32_t *srcs,
+                      uint32_t nsrc, uint32_t *ecc)
+{
+#pragma omp parallel
+    {
+        uint32_t *lv = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < (int64_t)nsrc; ++s) {
+            orc_bfs(n, rowptr, colind, srcs[s], lv);
+            uint32_t m = 0;
+            for (uint32_t v = 0; v < n; ++v)
+                if (lv[v] != ORC_UNREACHED && lv[v] > m) m = lv[v];
+            ecc[s] = m;
+        }
+        free(lv);
+    }
+}
+
 /* Triangles of a simple undirected graph: for every edge (i, j) with j < i,
  * count the common neighbours k with k < j.  Each triangle k < j < i is
  * counted exactly once.  (Sec. V: the sum of (L L^T) masked by L.) */

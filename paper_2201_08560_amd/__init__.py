@@ -21,7 +21,7 @@ __all__ = [
     "B2SRError", "B2SR", "lib", "b2sr_count_tiles", "b2sr_from_csr", "b2sr_pack_bits", "spmv_bin_bin",
     "spmv_bin_full", "spmv_bin_full_workspace_bytes", "spgemm_masked", "spgemm_masked_workspace_bytes",
     "spgemm_masked_profile", "b2sr_pagerank_directed", "b2sr_csr_transpose", "b2sr_mis", "b2sr_color",
-    "mis_keys",
+    "mis_keys", "b2sr_eccentricity", "b2sr_diameter",
     "b2sr_algo_workspace_bytes", "b2sr_bfs", "b2sr_msbfs", "b2sr_sssp", "b2sr_cc", "b2sr_pagerank",
     "triangle_count", "b2sr_strerror", "as_u32", "as_u64", "header_functions", "FLAGS", "SEMIRINGS",
     "b2sr_msbfs_batch", "b2sr_msbfs_batch_workspace_bytes", "MsbfsPlan", "BfsSession",
@@ -40,7 +40,7 @@ ACCUMULATE = 0x4
 SELF = 0x8
 SPARSE_X = 0x10
 PLUS_TIMES_F32, MIN_PLUS_F32, MIN_PLUS_U32, OR_U64, MAX_TIMES_U64 = 1, 2, 3, 4, 5
-ALGO_BFS, ALGO_SSSP, ALGO_CC, ALGO_PAGERANK, ALGO_MSBFS, ALGO_MIS, ALGO_COLOR = 1, 2, 3, 4, 5, 6, 7
+ALGO_BFS, ALGO_SSSP, ALGO_CC, ALGO_PAGERANK, ALGO_MSBFS, ALGO_MIS, ALGO_COLOR, ALGO_ECC = 1, 2, 3, 4, 5, 6, 7, 8
 BATCH_LEVELS, BATCH_PERSISTENT = 0, 1
 FLAGS = {"BUILD_LOWER": BUILD_LOWER, "MASK_COMPLEMENT": MASK_COMPLEMENT, "OUT_COUNT": OUT_COUNT,
          "ACCUMULATE": ACCUMULATE, "SELF": SELF, "SPARSE_X": SPARSE_X}
@@ -90,6 +90,8 @@ _SIGS = {
     "b2sr_pagerank_directed": (_I, [_MP, ctypes.c_float, _U32, _P, _P, _SZ, _P]),
     "b2sr_mis": (_I, [_MP, _P, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_stream_read": (_I, [_P, _SZ, _P, _P]),
+    "b2sr_eccentricity": (_I, [_MP, _P, _U32, _P, _P, _SZ, _P]),
+    "b2sr_diameter": (_I, [_MP, ctypes.POINTER(_U32), _P, _SZ, _P]),
     "b2sr_color": (_I, [_MP, _P, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_csr_transpose_workspace_bytes": (_SZ, [_U32]),
     "b2sr_csr_transpose": (_I, [_U32, _U64, _P, _P, _P, _P, _P, _SZ, _P]),
@@ -379,6 +381,23 @@ def b2sr_stream_read(t: torch.Tensor, nbytes: int | None = None, out=None):
     out = torch.empty(STREAM_READ_BLOCKS, dtype=torch.int32, device="cuda") if out is None else out
     _check(lib().b2sr_stream_read(_ptr(t), nbytes, _ptr(out), _stream()), "b2sr_stream_read")
     return out
+
+
+def b2sr_eccentricity(A: B2SR, srcs, ws=None) -> np.ndarray:
+    """Eccentricities (largest finite BFS level) of the given sources, host uint32."""
+    srcs = np.ascontiguousarray(srcs, dtype=np.uint32)
+    ecc = np.zeros(srcs.size, dtype=np.uint32)
+    ws, need = _ws(A, ALGO_ECC, ws)
+    _check(lib().b2sr_eccentricity(A.view, srcs.ctypes.data_as(_P), srcs.size, ecc.ctypes.data_as(_P), _ptr(ws),
+                                   need, _stream()), "b2sr_eccentricity")
+    return ecc
+
+
+def b2sr_diameter(A: B2SR, ws=None) -> int:
+    d = _U32(0)
+    ws, need = _ws(A, ALGO_ECC, ws)
+    _check(lib().b2sr_diameter(A.view, ctypes.byref(d), _ptr(ws), need, _stream()), "b2sr_diameter")
+    return d.value
 
 
 def mis_keys(n: int, seed: int) -> torch.Tensor:

@@ -4,6 +4,7 @@
 // kernel per iteration; convergence is read back as one device word per
 // iteration (the flags alternate between two words so the update kernel can
 // clear the next one, which saves a launch).
+#include <algorithm>
 #include <utility>
 
 #include "common.h"
@@ -112,6 +113,59 @@ __device__ __forceinline__ void store_pred_bits(uint32_t *bits, uint64_t base, u
     const uint64_t m = __ballot(p);
     const uint64_t w = base / 32 + lane_id();
     if (lane_id() < 2 && w < (n + 31u) / 32u) bits[w] = (uint32_t)(m >> (32 * lane_id()));
+}
+
+// ---------------------------------------------------------------- eccentricity
+// 64 sources at a time as bits of one frontier word per vertex, as the
+// multi-source BFS does, but no levels are stored: each level ORs its new
+// frontier words into alive[level & 1], and the host reads which sources still
+// reached new vertices.  A source's eccentricity is its last live level.
+__global__ void ecc_init_kernel(uint32_t n, uint64_t *F, uint64_t *V, uint32_t *act, uint64_t *alive)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = tid; i < n; i += stride) {
+        F[i] = 0;
+        V[i] = 0;
+    }
+    for (uint64_t w = tid; w < (n + 31) / 32; w += stride) act[w] = 0;
+    if (tid < 2) alive[tid] = 0;
+}
+
+__global__ void ecc_seed_kernel(uint32_t nsrc, const uint32_t *srcs, uint64_t *F, uint64_t *V, uint32_t *act)
+{
+    // one thread seeds every source, so repeated vertices cannot race
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (uint32_t s = 0; s < nsrc; ++s) {
+            F[srcs[s]] |= 1ull << s;
+            V[srcs[s]] |= 1ull << s;
+            act[srcs[s] >> 5] |= 1u << (srcs[s] & 31);
+        }
+}
+
+__global__ void ecc_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, uint64_t *V, uint32_t *act,
+                                  uint64_t *alive, uint32_t level)
+{
+    uint64_t seen = 0;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
+         base += waves * 64) {
+        const uint64_t i = base + lane_id();
+        uint64_t y = 0;
+        if (i < n) {
+            y = Y[i] & ~V[i];
+            F[i] = y;
+            if (y) V[i] |= y;
+        }
+        seen |= y;
+        const uint64_t m = __ballot(y != 0);
+        const uint64_t w = base / 32 + lane_id();
+        if (lane_id() < 2 && w < (n + 31u) / 32u) act[w] = (uint32_t)(m >> (32 * lane_id()));
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) seen |= shfl_xor(seen, d);
+    if (lane_id() == 0 && seen) atomicOr((unsigned long long *)alive + (level & 1), (unsigned long long)seen);
+    if (blockIdx.x == 0 && threadIdx.x == 0) alive[(level + 1) & 1] = 0;
 }
 
 // New frontier words: Y & ~V.  Marks them visited, records levels, and writes
@@ -309,6 +363,7 @@ struct Layout {
     // SSSP / CC / PR
     float *f0 = nullptr, *f1 = nullptr, *f2 = nullptr;
     uint32_t *u0 = nullptr, *ones = nullptr, *act = nullptr;
+    uint64_t *alive = nullptr;
     void *spmv_ws = nullptr;
     size_t spmv_ws_bytes = 0;
     uint32_t *flags = nullptr;
@@ -341,6 +396,14 @@ Layout carve(const b2sr_matrix *A, int algo, void *ws)
     case B2SR_ALGO_CC:
         L.u0 = c.take<uint32_t>(n * 4);
         L.act = c.take<uint32_t>(nw * 4);
+        break;
+    case B2SR_ALGO_ECC:
+        L.F = c.take<uint64_t>(n * 8);
+        L.V = c.take<uint64_t>(n * 8);
+        L.Y = c.take<uint64_t>(n * 8);
+        L.srcs = c.take<uint32_t>(64 * 4);
+        L.act = c.take<uint32_t>(nw * 4);
+        L.alive = c.take<uint64_t>(2 * 8);
         break;
     case B2SR_ALGO_MIS:
     case B2SR_ALGO_COLOR:
@@ -382,7 +445,7 @@ extern "C" {
 
 size_t b2sr_algo_workspace_bytes(const b2sr_matrix *A, int algo)
 {
-    if (!A || !b2sr::valid_tile(A->tile) || algo < B2SR_ALGO_BFS || algo > B2SR_ALGO_COLOR) return 0;
+    if (!A || !b2sr::valid_tile(A->tile) || algo < B2SR_ALGO_BFS || algo > B2SR_ALGO_ECC) return 0;
     return carve(A, algo, nullptr).bytes;
 }
 
@@ -645,6 +708,60 @@ int b2sr_color(const b2sr_matrix *A, const uint64_t *key, uint32_t *colors, void
                uint32_t *ncolors, hipStream_t stream)
 {
     return independent_sets(A, key, nullptr, colors, ws, ws_bytes, nullptr, ncolors, stream);
+}
+
+int b2sr_eccentricity(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32_t *ecc, void *ws,
+                      size_t ws_bytes, hipStream_t stream)
+{
+    Layout L;
+    int rc = check_algo_args(A, B2SR_ALGO_ECC, ws, ws_bytes, &L);
+    if (rc) return rc;
+    if (nsrc && (!srcs || !ecc)) return B2SR_EINVAL;
+    const uint32_t n = A->n;
+    for (uint32_t s = 0; s < nsrc; ++s)
+        if (srcs[s] >= n) return B2SR_EINVAL;
+    for (uint32_t b = 0; b < nsrc; b += 64) {
+        const uint32_t k = std::min<uint32_t>(64, nsrc - b);
+        for (uint32_t s = 0; s < k; ++s) ecc[b + s] = 0;
+        if ((rc = b2sr::check(hipMemcpyAsync(L.srcs, srcs + b, k * 4, hipMemcpyHostToDevice, stream),
+                              "hipMemcpyAsync(srcs)")))
+            return rc;
+        ecc_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, L.F, L.V, L.act, L.alive);
+        if ((rc = b2sr::check_launch("ecc_init_kernel"))) return rc;
+        ecc_seed_kernel<<<1, 64, 0, stream>>>(k, L.srcs, L.F, L.V, L.act);
+        if ((rc = b2sr::check_launch("ecc_seed_kernel"))) return rc;
+        for (uint32_t level = 1;; ++level) {
+            if ((rc = spmv_bin_full(A, B2SR_OR_U64, L.F, nullptr, L.act, nullptr, 0, 0.0, 0.0, L.Y, nullptr, 0,
+                                    stream)))
+                return rc;
+            ecc_update_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, L.act, L.alive, level);
+            if ((rc = b2sr::check_launch("ecc_update_kernel"))) return rc;
+            uint64_t alive = 0;
+            if ((rc = b2sr::check(hipMemcpyAsync(&alive, L.alive + (level & 1), 8, hipMemcpyDeviceToHost, stream),
+                                  "hipMemcpyAsync(alive)")))
+                return rc;
+            if ((rc = b2sr::check(hipStreamSynchronize(stream), "hipStreamSynchronize"))) return rc;
+            if (!alive) break;
+            for (uint32_t s = 0; s < k; ++s)
+                if ((alive >> s) & 1u) ecc[b + s] = level;
+        }
+    }
+    return B2SR_OK;
+}
+
+int b2sr_diameter(const b2sr_matrix *A, uint32_t *diameter, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!diameter) return B2SR_EINVAL;
+    if (int rc = b2sr::validate_matrix(A)) return rc;
+    *diameter = 0;
+    uint32_t srcs[64], ecc[64];
+    for (uint32_t b = 0; b < A->n; b += 64) {
+        const uint32_t k = std::min<uint32_t>(64, A->n - b);
+        for (uint32_t s = 0; s < k; ++s) srcs[s] = b + s;
+        if (int rc = b2sr_eccentricity(A, srcs, k, ecc, ws, ws_bytes, stream)) return rc;
+        for (uint32_t s = 0; s < k; ++s) *diameter = std::max(*diameter, ecc[s]);
+    }
+    return B2SR_OK;
 }
 
 }  // extern "C"

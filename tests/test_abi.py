@@ -216,3 +216,15 @@ def test_stream_read_argument_errors():
     assert L.b2sr_stream_read(FAKE, 64, None, None) == -1
     assert L.b2sr_stream_read(FAKE + 4, 64, FAKE, None) == -1   # not 16-byte aligned
     assert L.b2sr_stream_read(FAKE, 8, FAKE, None) == 0         # under one vector: nothing to read
+
+
+def test_eccentricity_argument_errors():
+    A = mat(n=64, tile=8)
+    need = L.b2sr_algo_workspace_bytes(ctypes.byref(A), 8)
+    assert need >= 3 * 64 * 8
+    srcs = (ctypes.c_uint32 * 2)(0, 64)   # 64 is out of range
+    ecc = (ctypes.c_uint32 * 2)()
+    assert L.b2sr_eccentricity(ctypes.byref(A), srcs, 2, ecc, FAKE, need, None) == -1
+    assert L.b2sr_eccentricity(ctypes.byref(A), None, 2, ecc, FAKE, need, None) == -1
+    assert L.b2sr_eccentricity(ctypes.byref(A), srcs, 1, ecc, None, need, None) == -3
+    assert L.b2sr_diameter(ctypes.byref(A), None, FAKE, need, None) == -1

@@ -294,6 +294,18 @@ def test_mis_and_color(gi, T):
     assert nc == exp_nc and np.array_equal(b2.as_u32(col), exp_col)
 
 
+@pytest.mark.parametrize("T", TILES)
+@pytest.mark.parametrize("gi", range(len(GRAPHS)), ids=IDS)
+def test_eccentricity_and_diameter(gi, T):
+    g = GRAPHS[gi]
+    A = b2sr(g, T)
+    # more than one batch of 64, with a repeated source
+    srcs = np.r_[gg.rng(800 + gi).integers(0, g.n, 70), 0].astype(np.uint32)
+    assert np.array_equal(b2.b2sr_eccentricity(A, srcs), orc.eccentricity(g, srcs))
+    if g.n <= 5000:
+        assert b2.b2sr_diameter(A) == orc.diameter(g)
+
+
 # ------------------------------------------------------------------ masked SpGEMM
 
 @pytest.mark.parametrize("T", TILES)

@@ -515,3 +515,25 @@ def test_color_pins():
     e = gg.canonical_csr(7, [], [])
     col, nc = orc.color(e, _keys(7, 5))
     assert nc == 1 and not col.any()
+
+
+def test_eccentricity_closed_forms():
+    n = 41
+    p = gg.path(n)
+    assert np.array_equal(orc.eccentricity(p, np.arange(n)), np.maximum(np.arange(n), n - 1 - np.arange(n)))
+    c = gg.cycle(n)
+    assert np.all(orc.eccentricity(c, np.arange(n)) == n // 2)
+    s = gg.star(12)                                  # vertex 0 is the centre
+    assert orc.eccentricity(s, [0, 1, 5]).tolist() == [1, 2, 2]
+    assert np.all(orc.eccentricity(gg.complete(9), np.arange(9)) == 1)
+    k = gg.king_grid(7, 11)                          # Chebyshev distance from a corner
+    assert orc.eccentricity(k, [0])[0] == 10 and orc.diameter(k) == 10
+    u = gg.disjoint_union(gg.path(5), gg.path(1), gg.cycle(8))
+    assert orc.eccentricity(u, [0, 5, 6]).tolist() == [4, 0, 4]
+    assert orc.diameter(u) == 4
+    # brute force on small random graphs: all-pairs BFS distances
+    for seed in range(3):
+        g = gg.random_graph_tiny(40, 0.08, 990 + seed)
+        D = csg.shortest_path(g.to_scipy(), unweighted=True, directed=False)
+        D[np.isinf(D)] = -1
+        assert np.array_equal(orc.eccentricity(g, np.arange(g.n)), D.max(1).astype(np.uint32))
