@@ -533,7 +533,7 @@ def main():
                                "4 single products + 64-source BFS + SSSP + CC + 50 PageRank iterations",
                    "n": g.n, "nnz": g.nnz, "tile": 32, "ntiles": w.A.ntiles, "products_per_step": w.products,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "spmv_kernel<32, 0, false> (masked bin x bin SpMV, full frontier)",
+        "roofline": {"bound": "hbm", "kernel": "spmv_kernel<32, 0, false, false> (masked bin x bin SpMV, full frontier)",
                      "achieved": alg / kt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / kt / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg, "ms_per_launch": kt * 1e3, "gteps": g.nnz / kt / 1e9,
