@@ -29,6 +29,7 @@ _u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
 _u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
 _u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
 _vp = ctypes.c_void_p
 
 
@@ -80,6 +81,9 @@ def lib():
         L.orc_mis_greedy.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u64p, _u8p]
         L.orc_color.argtypes = [ctypes.c_uint32, _u32p, _u32p, _u64p, _u32p]
         L.orc_color.restype = ctypes.c_uint32
+        L.orc_ppr.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32,
+                              _f64p]
+        L.orc_sweep_cut.argtypes = [ctypes.c_uint32, _u32p, _u32p, _f32p, _u32p, _u64p]
         L.orc_tc.restype = ctypes.c_uint64
         L.orc_tc.argtypes = [ctypes.c_uint32, _u32p, _u32p]
         _lib = L
@@ -264,6 +268,41 @@ def eccentricity(g, srcs):
 def diameter(g) -> int:
     """The largest finite distance: the largest eccentricity over every vertex."""
     return int(eccentricity(g, np.arange(g.n)).max(initial=0))
+
+
+def ppr(g, seed: int, a: float = 0.85, iters: int = 20):
+    """Personalised PageRank from one seed (float64), see orc_ppr."""
+    p = np.zeros(g.n, dtype=np.float64)
+    lib().orc_ppr(g.n, g.rowptr, g.colind, int(seed), float(a), int(iters), p)
+    return p
+
+
+def sweep_cut(g, score):
+    """Sweep cut of a score vector (single-precision quotients), see
+    orc_sweep_cut.  Returns (order u32[n], stats dict)."""
+    score = np.ascontiguousarray(score, dtype=np.float32)
+    order = np.zeros(g.n, dtype=np.uint32)
+    st = np.zeros(5, dtype=np.uint64)
+    lib().orc_sweep_cut(g.n, g.rowptr, g.colind, score, order, st)
+    return order, sweep_stats(st)
+
+
+def sweep_stats(st) -> dict:
+    k, cut, vol, vol_all, taken = (int(v) for v in st)
+    den = min(vol, vol_all - vol)
+    return {"size": k, "cut": cut, "vol": vol, "vol_all": vol_all, "taken": taken,
+            "conductance": cut / den if den else None}
+
+
+def lgc(g, seed: int, a: float = 0.85, iters: int = 20):
+    """Local clustering around seed: personalised PageRank, then the sweep cut
+    of its single-precision rounding.  Returns (p float64, cluster bool[n],
+    stats)."""
+    p = ppr(g, seed, a, iters)
+    order, st = sweep_cut(g, p.astype(np.float32))
+    cluster = np.zeros(g.n, dtype=bool)
+    cluster[order[:st["size"]]] = True
+    return p, cluster, st
 
 
 def tc(g) -> int:

@@ -583,3 +583,116 @@ uint64_t orc_tc(uint32_t n, const uint32_t *rowptr, const uint32_t *colind)
     }
     return total;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Local graph clustering (Table V, arithmetic semiring)                      */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Personalised PageRank from one seed vertex by power iteration: p^0 = e_seed
+ * and, for iters steps,
+ *     p'_i = (1 - a) [i == seed] + a * sum_{j : A_ij = 1} p_j / deg_j,
+ * vertices of degree 0 contributing nothing (the reading taken for PageRank).
+ */
+void orc_ppr(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, uint32_t seed, double a,
+             uint32_t iters, double *p)
+{
+    double *z = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    for (uint32_t i = 0; i < n; ++i) p[i] = i == seed ? 1.0 : 0.0;
+    for (uint32_t it = 0; it < iters; ++it) {
+        for (uint32_t j = 0; j < n; ++j) {
+            uint32_t deg = rowptr[j + 1] - rowptr[j];
+            z[j] = deg ? p[j] / (double)deg : 0.0;
+        }
+#pragma omp parallel for schedule(dynamic, 1024)
+        for (int64_t i = 0; i < (int64_t)n; ++i) {
+            double v = 0.0;
+            for (uint32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) v += z[colind[e]];
+            p[i] = (i == (int64_t)seed ? 1.0 - a : 0.0) + a * v;
+        }
+    }
+    free(z);
+}
+
+typedef struct {
+    float q;
+    uint32_t v;
+} orc_sweep_item;
+
+/* Decreasing q, then increasing vertex id. */
+static int cmp_sweep(const void *pa, const void *pb)
+{
+    const orc_sweep_item *a = (const orc_sweep_item *)pa, *b = (const orc_sweep_item *)pb;
+    if (a->q != b->q) return a->q > b->q ? -1 : 1;
+    return a->v < b->v ? -1 : (a->v > b->v);
+}
+
+/*
+ * Sweep cut over a score vector (the last step of local clustering).  The
+ * vertices taken are those with deg_v > 0 whose quotient q_v = score_v / deg_v,
+ * evaluated in single precision, is > 0; they are ordered by decreasing q_v,
+ * ties by increasing id.  For each prefix S of k taken vertices (k >= 1),
+ *     cut(S) = number of edges with exactly one end in S,
+ *     vol(S) = sum of the degrees in S,
+ *     conductance(S) = cut(S) / min(vol(S), vol(V) - vol(S)),
+ * prefixes with a zero denominator not being candidates.  The prefix of least
+ * conductance is chosen, the shortest one among equal conductances (compared
+ * exactly, as cut_a * den_b against cut_b * den_a in 64-bit integers: both
+ * factors are below 2^32).  With no candidate the chosen prefix is empty.
+ *   order[n]: the taken vertices in sweep order, then every other vertex by
+ *             increasing id.
+ *   stats[5]: {k, cut, vol, vol(V), number taken}.
+ * The graph must be undirected (cut is counted from the edges at each end).
+ */
+void orc_sweep_cut(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, const float *score,
+                   uint32_t *order, uint64_t *stats)
+{
+    orc_sweep_item *it = (orc_sweep_item *)malloc((size_t)(n ? n : 1) * sizeof *it);
+    uint8_t *taken = (uint8_t *)calloc(n ? n : 1, 1), *in = (uint8_t *)calloc(n ? n : 1, 1);
+    uint32_t m = 0;
+    uint64_t vol_all = rowptr[n];
+    for (uint32_t v = 0; v < n; ++v) {
+        uint32_t deg = rowptr[v + 1] - rowptr[v];
+        if (deg == 0) continue;
+        float q = score[v] / (float)deg;
+        if (q > 0.0f) {
+            it[m].q = q;
+            it[m].v = v;
+            taken[v] = 1;
+            ++m;
+        }
+    }
+    qsort(it, m, sizeof *it, cmp_sweep);
+    uint32_t o = 0;
+    for (uint32_t r = 0; r < m; ++r) order[o++] = it[r].v;
+    for (uint32_t v = 0; v < n; ++v)
+        if (!taken[v]) order[o++] = v;
+
+    uint64_t cut = 0, vol = 0, best_k = 0, best_cut = 0, best_vol = 0, best_den = 0;
+    for (uint32_t k = 1; k <= m; ++k) {
+        uint32_t v = it[k - 1].v;
+        /* v joins S: its edges to S stop crossing, its other edges start */
+        for (uint32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+            if (in[colind[e]]) --cut;
+            else ++cut;
+        }
+        in[v] = 1;
+        vol += rowptr[v + 1] - rowptr[v];
+        uint64_t den = vol < vol_all - vol ? vol : vol_all - vol;
+        if (den == 0) continue;
+        if (best_k == 0 || cut * best_den < best_cut * den) {
+            best_k = k;
+            best_cut = cut;
+            best_vol = vol;
+            best_den = den;
+        }
+    }
+    stats[0] = best_k;
+    stats[1] = best_cut;
+    stats[2] = best_vol;
+    stats[3] = vol_all;
+    stats[4] = m;
+    free(it);
+    free(taken);
+    free(in);
+}

@@ -537,3 +537,132 @@ def test_eccentricity_closed_forms():
         D = csg.shortest_path(g.to_scipy(), unweighted=True, directed=False)
         D[np.isinf(D)] = -1
         assert np.array_equal(orc.eccentricity(g, np.arange(g.n)), D.max(1).astype(np.uint32))
+
+
+# ---- local graph clustering: personalised PageRank and the sweep cut ------------
+
+def barbell(m: int):
+    """Two copies of K_m (vertices 0..m-1 and m..2m-1) joined by the edge (m-1, m)."""
+    i, j = np.triu_indices(m, 1)
+    src = np.concatenate([i, i + m, [m - 1]])
+    dst = np.concatenate([j, j + m, [m]])
+    return gg.canonical_csr(2 * m, src, dst, name=f"barbell{m}")
+
+
+def walk_matrix(g):
+    """P = A D^-1 as a dense matrix (zero columns at degree-0 vertices)."""
+    A = g.dense().astype(np.float64)
+    deg = A.sum(0)
+    return A / np.where(deg > 0, deg, 1.0)
+
+
+def test_ppr_matches_the_matrix_power_series():
+    """K steps from e_s give (aP)^K e_s + (1-a) sum_{k<K} (aP)^k e_s."""
+    a = 0.85
+    for g in TINY[:30]:
+        if g.n == 0:
+            continue
+        s = g.n // 2
+        aP = a * walk_matrix(g)
+        e = np.zeros(g.n)
+        e[s] = 1.0
+        for K in (0, 1, 6):
+            want = np.linalg.matrix_power(aP, K) @ e
+            want += (1 - a) * sum(np.linalg.matrix_power(aP, k) @ e for k in range(K))
+            np.testing.assert_allclose(orc.ppr(g, s, a, K), want, rtol=1e-12, atol=1e-15)
+
+
+def test_ppr_fixed_point_and_mass():
+    a = 0.7
+    g = gg.random_graph_tiny(50, 0.15, 4242)
+    s = 3
+    # far enough out, the iteration sits on the solution of (I - aP) p = (1 - a) e_s
+    e = np.zeros(g.n)
+    e[s] = 1.0
+    want = np.linalg.solve(np.eye(g.n) - a * walk_matrix(g), (1 - a) * e)
+    np.testing.assert_allclose(orc.ppr(g, s, a, 300), want, rtol=1e-10, atol=1e-14)
+    # without degree-0 vertices the walk keeps all of the mass
+    k = gg.king_grid(9, 13)
+    for K in (1, 5, 40):
+        assert abs(orc.ppr(k, 17, 0.85, K).sum() - 1.0) < 1e-12
+    # an isolated seed keeps 1 - a after the first step and nothing else moves
+    u = gg.disjoint_union(gg.path(1), gg.cycle(6))
+    p = orc.ppr(u, 0, 0.85, 4)
+    assert p[0] == pytest.approx(0.15, abs=1e-15) and np.all(p[1:] == 0)
+
+
+def sweep_brute_force(g, score):
+    """Every prefix's conductance from the set itself, compared as exact fractions."""
+    from fractions import Fraction
+    A = g.dense().astype(np.int64)
+    deg = A.sum(1)
+    q = np.where(deg > 0, score.astype(np.float32) / np.maximum(deg, 1).astype(np.float32), np.float32(0))
+    taken = [v for v in range(g.n) if deg[v] > 0 and q[v] > 0]
+    taken.sort(key=lambda v: (-float(q[v]), v))
+    vol_all = int(deg.sum())
+    best = None
+    for k in range(1, len(taken) + 1):
+        S = np.zeros(g.n, bool)
+        S[taken[:k]] = True
+        cut = int(A[S][:, ~S].sum())
+        vol = int(deg[S].sum())
+        den = min(vol, vol_all - vol)
+        if den and (best is None or Fraction(cut, den) < best[0]):
+            best = (Fraction(cut, den), k, cut, vol)
+    return taken, best
+
+
+def test_sweep_cut_brute_force():
+    r = gg.rng(777)
+    for g in TINY[:40]:
+        for kind in ("continuous", "ties"):
+            if kind == "continuous":
+                score = r.random(g.n).astype(np.float32) - np.float32(0.2)   # some negative: not taken
+            else:
+                score = r.integers(-1, 3, g.n).astype(np.float32)          # many equal quotients
+            order, st = orc.sweep_cut(g, score)
+            taken, best = sweep_brute_force(g, score)
+            assert order[:len(taken)].tolist() == taken and st["taken"] == len(taken)
+            rest = sorted(set(range(g.n)) - set(taken))
+            assert order[len(taken):].tolist() == rest
+            assert st["vol_all"] == int(g.degrees().sum())
+            if best is None:
+                assert (st["size"], st["cut"], st["vol"]) == (0, 0, 0)
+            else:
+                assert (st["size"], st["cut"], st["vol"]) == best[1:]
+
+
+def test_lgc_closed_forms():
+    for m in (5, 12):
+        g = barbell(m)
+        for seed in (0, m - 1):                       # inside clique 1, and its bridge end
+            _, cluster, st = orc.lgc(g, seed, 0.85, 30)
+            assert cluster.tolist() == [True] * m + [False] * m
+            assert (st["cut"], st["vol"]) == (1, m * (m - 1) + 1)
+            assert st["conductance"] == 1 / (m * (m - 1) + 1)
+    # a seed's own component is a cluster of conductance 0
+    u = gg.disjoint_union(gg.complete(6), gg.complete(9))
+    _, cluster, st = orc.lgc(u, 8, 0.85, 10)
+    assert cluster.tolist() == [False] * 6 + [True] * 9 and st["cut"] == 0 and st["conductance"] == 0
+    # an isolated seed gives no candidate prefix
+    _, cluster, st = orc.lgc(gg.disjoint_union(gg.path(1), gg.cycle(5)), 0, 0.85, 10)
+    assert st["size"] == 0 and st["taken"] == 0 and not cluster.any()
+
+
+def test_sweep_pins_catch_planted_mistakes():
+    """A sweep that orders by the raw score, not score / degree, or that counts an
+    edge into S as crossing, disagrees with the brute force."""
+    g = barbell(6)
+    score = np.ones(g.n, np.float32)
+    score[[0, 1]] = 2.0
+    score[5] = 1.1                                  # the bridge end: degree 6, the others 5
+    taken, best = sweep_brute_force(g, score)
+    assert taken[:3] == [0, 1, 2]                   # 1.1 / 6 < 1 / 5: vertex 5 comes after the unit scores
+    assert orc.sweep_cut(g, score)[0][:len(taken)].tolist() == taken
+    raw = sorted((v for v in range(g.n)), key=lambda v: (-float(score[v]), v))
+    assert raw[:3] == [0, 1, 5]
+    # counting every edge of the joining vertex as crossing overstates the cut
+    A = g.dense().astype(np.int64)
+    S = np.zeros(g.n, bool)
+    S[:6] = True
+    assert int(A[S][:, ~S].sum()) == 1 != int(A[S].sum())
