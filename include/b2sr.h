@@ -281,6 +281,7 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
 #define B2SR_ALGO_MIS 6
 #define B2SR_ALGO_COLOR 7
 #define B2SR_ALGO_ECC 8
+#define B2SR_ALGO_LGC 9
 size_t b2sr_algo_workspace_bytes(const b2sr_matrix *A, int algo);
 
 /* BFS (Sec. V): Boolean semiring, masked bin_bin_bin product per level with
@@ -355,6 +356,36 @@ int b2sr_diameter(const b2sr_matrix *A, uint32_t *diameter, void *ws, size_t ws_
  * B2SR_ALGO_PAGERANK. */
 int b2sr_pagerank_directed(const b2sr_matrix *At, float damping, uint32_t iterations, float *rank,
                            void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Local graph clustering (Table V: arithmetic semiring).  Personalised
+ * PageRank from `seed`: p_0 = e_seed, then `iterations` steps of
+ *     p_i = (1 - alpha) [i == seed] + alpha * sum_{j : A_ij = 1} p_j / deg_j
+ * in float (plus-times products; degree-0 vertices contribute nothing), then
+ * b2sr_sweep_cut of p.  ppr: device float[n] (the final p).  cluster_bits and
+ * stats as for b2sr_sweep_cut (cluster_bits nullable).  seed >= n or alpha
+ * outside [0, 1]: EINVAL.  Workspace: b2sr_algo_workspace_bytes(A,
+ * B2SR_ALGO_LGC).  A must be undirected. */
+int b2sr_lgc(const b2sr_matrix *A, uint32_t seed, float alpha, uint32_t iterations, float *ppr,
+             uint32_t *cluster_bits, uint64_t *stats, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Sweep cut of a score vector (the last step of local clustering).  The
+ * vertices taken are those with deg_v > 0 (deg = set bits of row v) whose
+ * single-precision quotient q_v = score_v / deg_v is > 0, ordered by
+ * decreasing q_v, ties by increasing id.  Of the prefixes S of that order,
+ * the one of least conductance cut(S) / min(vol S, vol V - vol S) is chosen
+ * (cut = edges leaving S, vol = sum of degrees; the shortest prefix among
+ * equal conductances, compared exactly; prefixes with a zero denominator are
+ * not candidates).  Outputs (device):
+ *   stats: uint64_t[5] = {size of the chosen prefix (0: none), its cut, its
+ *          vol, vol V, number of vertices taken};
+ *   order (nullable): uint32_t[n], the taken vertices in sweep order, then
+ *          the others by increasing id;
+ *   cluster_bits (nullable): ceil(n/32) words, bit v set iff v is in the
+ *          chosen prefix (padding bits 0).
+ * score: device float[n] (NaN and values <= 0 are not taken).  Workspace:
+ * b2sr_algo_workspace_bytes(A, B2SR_ALGO_LGC).  A must be undirected. */
+int b2sr_sweep_cut(const b2sr_matrix *A, const float *score, uint32_t *order, uint32_t *cluster_bits,
+                   uint64_t *stats, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---- batched multi-source BFS over many graphs ---------------------------
  * Many graphs are placed in one vertex space of n vertices (each graph's ids

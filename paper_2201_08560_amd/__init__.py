@@ -41,6 +41,7 @@ SELF = 0x8
 SPARSE_X = 0x10
 PLUS_TIMES_F32, MIN_PLUS_F32, MIN_PLUS_U32, OR_U64, MAX_TIMES_U64 = 1, 2, 3, 4, 5
 ALGO_BFS, ALGO_SSSP, ALGO_CC, ALGO_PAGERANK, ALGO_MSBFS, ALGO_MIS, ALGO_COLOR, ALGO_ECC = 1, 2, 3, 4, 5, 6, 7, 8
+ALGO_LGC = 9
 BATCH_LEVELS, BATCH_PERSISTENT = 0, 1
 FLAGS = {"BUILD_LOWER": BUILD_LOWER, "MASK_COMPLEMENT": MASK_COMPLEMENT, "OUT_COUNT": OUT_COUNT,
          "ACCUMULATE": ACCUMULATE, "SELF": SELF, "SPARSE_X": SPARSE_X}
@@ -93,6 +94,8 @@ _SIGS = {
     "b2sr_eccentricity": (_I, [_MP, _P, _U32, _P, _P, _SZ, _P]),
     "b2sr_diameter": (_I, [_MP, ctypes.POINTER(_U32), _P, _SZ, _P]),
     "b2sr_color": (_I, [_MP, _P, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
+    "b2sr_lgc": (_I, [_MP, _U32, ctypes.c_float, _U32, _P, _P, _P, _P, _SZ, _P]),
+    "b2sr_sweep_cut": (_I, [_MP, _P, _P, _P, _P, _P, _SZ, _P]),
     "b2sr_csr_transpose_workspace_bytes": (_SZ, [_U32]),
     "b2sr_csr_transpose": (_I, [_U32, _U64, _P, _P, _P, _P, _P, _SZ, _P]),
     "b2sr_msbfs_batch_workspace_bytes": (_SZ, [_U32]),
@@ -398,6 +401,39 @@ def b2sr_diameter(A: B2SR, ws=None) -> int:
     ws, need = _ws(A, ALGO_ECC, ws)
     _check(lib().b2sr_diameter(A.view, ctypes.byref(d), _ptr(ws), need, _stream()), "b2sr_diameter")
     return d.value
+
+
+def sweep_stats(st) -> dict:
+    """The five stats words of a sweep cut as a dict (conductance as a float)."""
+    k, cut, vol, vol_all, taken = (int(v) for v in np.asarray(st, dtype=np.uint64))
+    den = min(vol, vol_all - vol)
+    return {"size": k, "cut": cut, "vol": vol, "vol_all": vol_all, "taken": taken,
+            "conductance": cut / den if den else None}
+
+
+def b2sr_sweep_cut(A: B2SR, score: torch.Tensor, order: bool = True, ws=None):
+    """Sweep cut of a float32 score vector: (order u32 tensor or None, cluster
+    bit words, stats dict)."""
+    n = A.n
+    o = torch.empty(n, dtype=torch.int32, device="cuda") if order else None
+    bits = torch.empty(max(1, (n + 31) // 32), dtype=torch.int32, device="cuda")
+    st = torch.empty(5, dtype=torch.int64, device="cuda")
+    ws, need = _ws(A, ALGO_LGC, ws)
+    _check(lib().b2sr_sweep_cut(A.view, _ptr(score), _ptr(o), _ptr(bits), _ptr(st), _ptr(ws), need, _stream()),
+           "b2sr_sweep_cut")
+    return o, bits, sweep_stats(st.cpu().numpy().view(np.uint64))
+
+
+def b2sr_lgc(A: B2SR, seed: int, alpha: float = 0.85, iterations: int = 20, ws=None):
+    """Local clustering around `seed`: (personalised PageRank float32 tensor,
+    cluster bit words, stats dict)."""
+    p = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    bits = torch.empty(max(1, (A.n + 31) // 32), dtype=torch.int32, device="cuda")
+    st = torch.empty(5, dtype=torch.int64, device="cuda")
+    ws, need = _ws(A, ALGO_LGC, ws)
+    _check(lib().b2sr_lgc(A.view, int(seed), float(alpha), int(iterations), _ptr(p), _ptr(bits), _ptr(st), _ptr(ws),
+                          need, _stream()), "b2sr_lgc")
+    return p, bits, sweep_stats(st.cpu().numpy().view(np.uint64))
 
 
 def mis_keys(n: int, seed: int) -> torch.Tensor:

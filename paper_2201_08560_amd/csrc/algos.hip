@@ -14,6 +14,7 @@ using namespace b2sr_dev;
 namespace b2sr {
 int fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
 int column_counts(const b2sr_matrix *A, uint32_t *colsum, hipStream_t s);
+size_t lgc_workspace_bytes(const b2sr_matrix *A);
 }
 
 namespace {
@@ -445,7 +446,9 @@ extern "C" {
 
 size_t b2sr_algo_workspace_bytes(const b2sr_matrix *A, int algo)
 {
-    if (!A || !b2sr::valid_tile(A->tile) || algo < B2SR_ALGO_BFS || algo > B2SR_ALGO_ECC) return 0;
+    if (!A || !b2sr::valid_tile(A->tile)) return 0;
+    if (algo == B2SR_ALGO_LGC) return b2sr::lgc_workspace_bytes(A);
+    if (algo < B2SR_ALGO_BFS || algo > B2SR_ALGO_ECC) return 0;
     return carve(A, algo, nullptr).bytes;
 }
 

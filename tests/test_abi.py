@@ -228,3 +228,19 @@ def test_eccentricity_argument_errors():
     assert L.b2sr_eccentricity(ctypes.byref(A), None, 2, ecc, FAKE, need, None) == -1
     assert L.b2sr_eccentricity(ctypes.byref(A), srcs, 1, ecc, None, need, None) == -3
     assert L.b2sr_diameter(ctypes.byref(A), None, FAKE, need, None) == -1
+
+
+def test_lgc_argument_errors():
+    A = mat(n=64, tile=8)
+    need = L.b2sr_algo_workspace_bytes(ctypes.byref(A), b2.ALGO_LGC)
+    assert need >= 64 * (6 * 4 + 2 * 8)          # keys, ids (twice), rank, degrees; volumes and cuts
+    p = FAKE
+    f = ctypes.c_float
+    assert L.b2sr_lgc(ctypes.byref(A), 64, f(0.85), 5, p, p, p, p, need, None) == -1     # seed >= n
+    assert L.b2sr_lgc(ctypes.byref(A), 0, f(1.5), 5, p, p, p, p, need, None) == -1       # alpha > 1
+    assert L.b2sr_lgc(ctypes.byref(A), 0, f(0.85), 5, None, p, p, p, need, None) == -1   # no ppr output
+    assert L.b2sr_lgc(ctypes.byref(A), 0, f(0.85), 5, p, p, None, p, need, None) == -1   # no stats
+    assert L.b2sr_lgc(ctypes.byref(A), 0, f(0.85), 5, p, p, p, p, need - 1, None) == -3
+    assert L.b2sr_sweep_cut(ctypes.byref(A), None, p, p, p, p, need, None) == -1         # no score
+    assert L.b2sr_sweep_cut(ctypes.byref(A), p, p, p, None, p, need, None) == -1         # no stats
+    assert L.b2sr_sweep_cut(ctypes.byref(A), p, p, p, p, None, need, None) == -3

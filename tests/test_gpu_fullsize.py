@@ -103,3 +103,28 @@ def test_batched_full_config():
     host = b2.as_u32(lv)
     for i, g in enumerate(graphs):
         assert np.all(host[int(B.offsets[i]) + g.n:int(B.offsets[i + 1])] == b2.UNREACHED)
+
+
+def test_local_clustering_full_size(big):
+    """Sweep cut of a seeded score vector over all 2^20 vertices, bit-exact, and
+    local clustering from the first benchmark source: personalised PageRank
+    within 1e-5 relative L1 and a consistent cluster."""
+    g, A = big["g"], big["A"]
+    s = (gg.rng(4040).random(g.n) ** 4 * (gg.rng(4041).random(g.n) < 0.6)).astype(np.float32)
+    print("sweep cut s20", flush=True)
+    order, st = orc.sweep_cut(g, s)
+    go, gbits, gst = b2.b2sr_sweep_cut(A, torch.from_numpy(s).cuda())
+    assert gst == st and np.array_equal(b2.as_u32(go), order)
+    c = np.zeros(g.n, bool)
+    c[order[:st["size"]]] = True
+    assert np.array_equal(unpack_bits(b2.as_u32(gbits), g.n), c)
+    seed = int(big["sources"][0])
+    print("lgc s20", flush=True)
+    p, bits, st = b2.b2sr_lgc(A, seed, 0.85, 20)
+    assert rel_l1(p.cpu().numpy(), orc.ppr(g, seed, 0.85, 20)) <= 1e-5
+    cluster = unpack_bits(b2.as_u32(bits), g.n)
+    deg = g.degrees().astype(np.int64)
+    M = g.to_scipy().tocsr()
+    cut = int((M[cluster] @ (~cluster).astype(np.int64)).sum())
+    assert (st["size"], st["cut"], st["vol"], st["vol_all"]) == (int(cluster.sum()), cut, int(deg[cluster].sum()),
+                                                                  int(deg.sum()))
