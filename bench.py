@@ -172,6 +172,26 @@ def bfs_gteps(w: Workload, nsrc: int = 8) -> dict:
             "sources": nsrc}
 
 
+def lgc_section(w: Workload, nsrc: int = 4, iters: int = 20) -> dict:
+    """Local clustering from benchmark sources: personalised PageRank
+    (`iters` plus-times products) then the sweep cut; and the sweep alone."""
+    ws = torch.empty(b2.b2sr_algo_workspace_bytes(w.A, b2.ALGO_LGC), dtype=torch.uint8, device="cuda")
+    total, sweep, clusters = [], [], []
+    for s in w.sources[:nsrc]:
+        b2.b2sr_lgc(w.A, int(s), 0.85, iters, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p, _, st = b2.b2sr_lgc(w.A, int(s), 0.85, iters, ws=ws)   # stats are read back: synchronises
+        total.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        _, _, st2 = b2.b2sr_sweep_cut(w.A, p, order=False, ws=ws)
+        sweep.append(time.perf_counter() - t0)
+        assert st2 == st
+        clusters.append({"seed": int(s), "size": st["size"], "conductance": st["conductance"], "taken": st["taken"]})
+    return {"iterations": iters, "ms_median": 1e3 * float(np.median(total)),
+            "sweep_ms_median": 1e3 * float(np.median(sweep)), "clusters": clusters}
+
+
 def tc_section(reps: int = 3) -> dict:
     out = {}
     for name, g in (("rmat18_ef16", gg.rmat(18, 16, seed=18)), ("king2048", gg.king_grid(2048, 2048))):
@@ -546,6 +566,7 @@ def main():
     if not args.no_extras:
         out["verify"] = verify(w)
         out["bfs_single_source"] = bfs_gteps(w)
+        out["lgc"] = lgc_section(w)
         out["tc"] = tc_section()
         out["batched"] = batched_section(batch_graphs)
         out["serving"] = serving_section(pool_graphs, args.serve_qps, args.serve_seconds,
