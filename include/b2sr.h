@@ -219,9 +219,11 @@ int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, 
  *   Floating-point sums are deterministic: a fixed reduction order that does
  *   not depend on scheduling (rows split across work chunks are combined in
  *   chunk order by a second kernel).
- *   ws/ws_bytes: workspace of at least spmv_bin_full_workspace_bytes(A,
- *   semiring) bytes (may be NULL when that is 0).  y must not alias x,
- *   x_active or mask.
+ *   ws/ws_bytes: workspace of spmv_bin_full_workspace_bytes(A, semiring)
+ *   bytes (may be NULL when that is 0).  For plus-times it holds the partial
+ *   sums of tile-rows split across work chunks and, last, n floats for x * s;
+ *   without col_scale those last 4n bytes may be left out.  With col_scale, ws
+ *   must be 16-byte aligned.  y must not alias x, x_active or mask.
  *   x and col_scale must be 16-byte aligned (segments are read as vectors).
  *   Errors: EINVAL, ENOSPC, ENOTSUP (unknown semiring), EHIP.
  */

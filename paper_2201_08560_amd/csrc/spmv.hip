@@ -35,7 +35,47 @@ using namespace b2sr_core;
 
 namespace {
 
-template <int T, int K, bool ACT, bool SHORT = false> __global__ void __launch_bounds__(256) spmv_kernel(SpmvArgs p)
+// Minimum waves per SIMD asked of the compiler (the second __launch_bounds__
+// argument) per tile width and kind: set where the product measured faster and
+// nothing spills; 1 is no request.
+#ifndef B2SR_W32_PLUS
+#define B2SR_W32_PLUS 5
+#endif
+#ifndef B2SR_W32_MIN
+#define B2SR_W32_MIN 6
+#endif
+#ifndef B2SR_W32_U64
+#define B2SR_W32_U64 6
+#endif
+#ifndef B2SR_W32_BITS
+#define B2SR_W32_BITS 5
+#endif
+#ifndef B2SR_W16_PLUS
+#define B2SR_W16_PLUS 5
+#endif
+#ifndef B2SR_W16_MIN
+#define B2SR_W16_MIN 5
+#endif
+#ifndef B2SR_W16_U64
+#define B2SR_W16_U64 1
+#endif
+#ifndef B2SR_W8_PLUS
+#define B2SR_W8_PLUS 1
+#endif
+#ifndef B2SR_W8_U64
+#define B2SR_W8_U64 1
+#endif
+constexpr int waves_hint(int T, int K)
+{
+    const bool plus = K == kPlusF32, mins = K == kMinF32 || K == kMinU32, u64 = K == kOr64 || K == kMaxU64;
+    if (T == 32) return plus ? B2SR_W32_PLUS : mins ? B2SR_W32_MIN : u64 ? B2SR_W32_U64 : B2SR_W32_BITS;
+    if (T == 16) return plus ? B2SR_W16_PLUS : mins ? B2SR_W16_MIN : u64 ? B2SR_W16_U64 : 1;
+    if (T == 8) return plus ? B2SR_W8_PLUS : u64 ? B2SR_W8_U64 : 1;
+    return 1;
+}
+
+template <int T, int K, bool ACT, bool SHORT = false>
+__global__ void __launch_bounds__(256, waves_hint(T, K)) spmv_kernel(SpmvArgs p)
 {
     using V = typename KindTraits<K>::V;
     constexpr bool stage = Cfg<T, K>::kStage;
@@ -96,6 +136,12 @@ template <int K> __global__ void init_values_kernel(SpmvArgs p)
             if (!accumulate) *y = KT::id();
         }
     }
+}
+
+__global__ void scale_x_kernel(uint32_t n, const float *__restrict__ x, const float *__restrict__ s, float *z)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        z[i] = x[i] * s[i];
 }
 
 __global__ void zero_words_kernel(uint32_t *__restrict__ y, uint32_t nwords)
@@ -170,6 +216,16 @@ uint32_t plus_chunk(uint32_t T, uint32_t ntiles)
     }
 }
 
+// Plus-times workspace: the first and last row of every chunk, then the
+// straddling rows' partials (256-byte aligned pieces); x * col_scale follows.
+size_t plus_partials_bytes(const b2sr_matrix *A)
+{
+    const uint32_t chunk = plus_chunk(A->tile, A->ntiles);
+    const uint64_t nchunks = ((uint64_t)A->ntiles + chunk - 1) / chunk;
+    const uint64_t rows_bytes = (nchunks * 2 * 4 + 255) & ~255ull;
+    return (size_t)((rows_bytes + nchunks * 2 * A->tile * 4 + 255) & ~255ull);
+}
+
 }  // namespace
 
 extern "C" {
@@ -195,10 +251,7 @@ int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, 
 size_t spmv_bin_full_workspace_bytes(const b2sr_matrix *A, int semiring)
 {
     if (!A || !b2sr::valid_tile(A->tile) || semiring != B2SR_PLUS_TIMES_F32) return 0;
-    const uint32_t chunk = plus_chunk(A->tile, A->ntiles);
-    const uint64_t nchunks = ((uint64_t)A->ntiles + chunk - 1) / chunk;
-    const uint64_t rows_bytes = (nchunks * 2 * 4 + 255) & ~255ull;
-    return (size_t)(rows_bytes + nchunks * 2 * A->tile * 4);
+    return plus_partials_bytes(A) + (size_t)A->n * 4;
 }
 
 int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float *col_scale,
@@ -218,11 +271,19 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
     if (x == y || (const void *)x_active == y || (const void *)mask == y) return B2SR_EINVAL;
     // x segments are read as 16-byte vectors
     if (((uintptr_t)x & 15) || ((uintptr_t)col_scale & 15)) return B2SR_EINVAL;
-    const size_t need = spmv_bin_full_workspace_bytes(A, semiring);
+    // the scaled copy of x is needed only with col_scale
+    const size_t need = semiring != B2SR_PLUS_TIMES_F32 ? 0
+                      : col_scale ? spmv_bin_full_workspace_bytes(A, semiring) : plus_partials_bytes(A);
     if (ws_bytes < need || (need && !ws)) return B2SR_ENOSPC;
+    if (col_scale && ((uintptr_t)ws & 15)) return B2SR_EINVAL;
     SpmvArgs p = make_args(A);
     p.x = x;
-    p.s = col_scale;
+    if (col_scale) {
+        float *z = (float *)((char *)ws + plus_partials_bytes(A));
+        scale_x_kernel<<<b2sr::grid_for(A->n, 256, 8192), 256, 0, stream>>>(A->n, (const float *)x, col_scale, z);
+        if ((rc = b2sr::check_launch("scale_x_kernel"))) return rc;
+        p.x = z;
+    }
     p.xact = x_active;
     p.mask = mask;
     p.flags = flags;
@@ -230,7 +291,7 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
     p.beta = (float)beta;
     p.w_u32 = semiring == B2SR_MIN_PLUS_U32 ? (uint32_t)alpha : 0u;
     p.y = y;
-    if (need) {
+    if (semiring == B2SR_PLUS_TIMES_F32) {
         const uint64_t nchunks = ((uint64_t)A->ntiles + plus_chunk(A->tile, A->ntiles) - 1) /
                                  plus_chunk(A->tile, A->ntiles);
         p.ws_rows = (uint32_t *)ws;

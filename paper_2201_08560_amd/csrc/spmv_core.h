@@ -21,6 +21,9 @@
 #ifndef B2SR_STAGE_BYTES
 #define B2SR_STAGE_BYTES 4096    // LDS bytes per wave for staged x segments
 #endif
+#ifndef B2SR_X_DMA
+#define B2SR_X_DMA 1             // stage 4-byte x segments at T = 32 with global-to-LDS loads
+#endif
 #ifndef B2SR_NT_TILES
 #define B2SR_NT_TILES 1          // stream tile bits with nontemporal loads
 #endif
@@ -83,7 +86,6 @@ struct SpmvArgs {
     const void *bits;
     uint32_t n, ntr, ntiles, chunk;
     const void *x;
-    const float *s;
     const uint32_t *xact;  // value products: columns whose x entries take part (nullable: all)
     const uint32_t *mask;
     unsigned flags;
@@ -442,39 +444,37 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 off[i] = use && full ? c0 : 0u;
                 partial |= (uint32_t)(use && !full) << i;
             }
-            if (quads) {
+            // At T = 32 with 4-byte values a step's segments are one 16-byte quad per
+            // lane at slot i * 1024 + 16 * lane: exactly where a global-to-LDS load
+            // puts lane l's quad, so those bytes need no registers.
+            constexpr bool kDma = B2SR_X_DMA && T == 32 && NQ == 1;
+            if (kDma && quads) {
+#pragma unroll
+                for (int i = 0; i < U; ++i)
+                    __builtin_amdgcn_global_load_lds(
+                        (const __attribute__((address_space(1))) void *)((const V *)p.x + off[i]),
+                        (__attribute__((address_space(3))) void *)(xs + i * TPW * T), 16, 0, 0);
+            } else if (quads) {
 #pragma unroll
                 for (int i = 0; i < U; ++i)
 #pragma unroll
                     for (int q = 0; q < NQ; ++q) xq[i][q] = ((const u32x4 *)((const V *)p.x + off[i]))[q];
-                if constexpr (K == kPlusF32) {
-                    if (p.s) {
-#pragma unroll
-                        for (int i = 0; i < U; ++i)
-#pragma unroll
-                            for (int q = 0; q < NQ; ++q) {
-                                const u32x4 sv = ((const u32x4 *)(p.s + off[i]))[q];
-                                u32x4 &v = xq[i][q];
-                                v.x = __float_as_uint(__uint_as_float(v.x) * __uint_as_float(sv.x));
-                                v.y = __float_as_uint(__uint_as_float(v.y) * __uint_as_float(sv.y));
-                                v.z = __float_as_uint(__uint_as_float(v.z) * __uint_as_float(sv.z));
-                                v.w = __float_as_uint(__uint_as_float(v.w) * __uint_as_float(sv.w));
-                            }
-                    }
-                }
             } else {
 #pragma unroll
                 for (int i = 0; i < U; ++i)
 #pragma unroll
                     for (int q = 0; q < NQ; ++q) xq[i][q] = u32x4{0u, 0u, 0u, 0u};
             }
+            if (!(kDma && quads)) {
 #pragma unroll
-            for (int i = 0; i < U; ++i) {
-                V *dst = xs + (i * TPW + grp) * T + sub * XW;
+                for (int i = 0; i < U; ++i) {
+                    V *dst = xs + (i * TPW + grp) * T + sub * XW;
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) ((u32x4 *)dst)[q] = xq[i][q];
+                    for (int q = 0; q < NQ; ++q) ((u32x4 *)dst)[q] = xq[i][q];
+                }
             }
             if (partial) {
+                if constexpr (kDma) __builtin_amdgcn_s_waitcnt(0);  // the quads have landed before they are overwritten
                 // only the last tile column can be cut by n; values past n are never selected
                 const uint32_t c0 = (p.n - 1) / T * T + sub * XW;
 #pragma unroll
@@ -483,12 +483,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                     V *dst = xs + (i * TPW + grp) * T + sub * XW;
                     for (int q = 0; q < XW; ++q) {
                         V v = KT::id();
-                        if (c0 + q < p.n) {
-                            v = ((const V *)p.x)[c0 + q];
-                            if constexpr (K == kPlusF32) {
-                                if (p.s) v *= p.s[c0 + q];
-                            }
-                        }
+                        if (c0 + q < p.n) v = ((const V *)p.x)[c0 + q];
                         dst[q] = v;
                     }
                 }

@@ -62,7 +62,12 @@ def test_spmv_argument_errors():
     need = L.spmv_bin_full_workspace_bytes(A, 1)
     assert need > 0
     assert L.spmv_bin_full(A, 1, x, None, None, None, 0, 1.0, 0.0, y, None, 0, None) == -3   # no workspace
-    assert L.spmv_bin_full(A, 1, x, None, None, None, 0, 1.0, 0.0, y, x, need - 1, None) == -3
+    base = need - 4 * 64                     # without col_scale the scaled copy of x is not needed
+    assert base > 0
+    assert L.spmv_bin_full(A, 1, x, None, None, None, 0, 1.0, 0.0, y, x, base - 1, None) == -3
+    s = ctypes.c_void_p(FAKE + 8192)
+    assert L.spmv_bin_full(A, 1, x, s, None, None, 0, 1.0, 0.0, y, x, need - 1, None) == -3
+    assert L.spmv_bin_full(A, 1, x, s, None, None, 0, 1.0, 0.0, y, ctypes.c_void_p(FAKE + 8), need, None) == -1  # ws misaligned
     assert L.spmv_bin_full_workspace_bytes(A, 2) == 0
     assert L.spmv_bin_full(A, 2, x, None, y, None, 0, 1.0, 0.0, y, None, 0, None) == -1   # x_active aliases y
 
