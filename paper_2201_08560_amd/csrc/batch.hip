@@ -32,6 +32,9 @@ using namespace b2sr_core;
 namespace {
 
 constexpr uint32_t kMaxGroups = 8;
+// Flag words: [0..7] as listed in BatchArgs; the barrier's arrival count and
+// generation 256 bytes apart, each on a line of its own.
+constexpr uint32_t kBarrierCount = 64, kBarrierGen = 128, kFlagWords = 192;
 constexpr uint32_t kUnreached = 0xFFFFFFFFu;
 
 struct Group {
@@ -48,10 +51,11 @@ struct BatchArgs {
     uint32_t *act;     // bit vector: vertices whose frontier word is non-zero
     uint32_t *levels;  // n x 64, vertex-major
     uint32_t *flags;   // [0], [1]: per-level parity flags; [2]: levels run;
-                       // [3]: barrier arrivals; [4]: barrier generation; [5]: barrier timed out;
+                       // [5]: barrier timed out (the barrier's own words are further on);
                        // [6]: BFS finished (per-level kernels return at once)
     const uint32_t *seed_vertex, *seed_bit;
     uint32_t nseeds;
+    unsigned tmask;  // tile widths present: bit 0 for 4, 1 for 8, 2 for 16, 3 for 32
 };
 
 __global__ void batch_init_kernel(BatchArgs b)
@@ -66,6 +70,7 @@ __global__ void batch_init_kernel(BatchArgs b)
     }
     for (uint64_t w = tid; w < (b.n + 31) / 32; w += stride) b.act[w] = 0;
     if (tid < 8) b.flags[tid] = 0;
+    if (tid == 8) b.flags[kBarrierCount] = 0;
 }
 
 // Seeds are distinct (vertex, bit) pairs, so the level writes never collide and
@@ -156,16 +161,30 @@ template <int T> __device__ __forceinline__ void run_chunk(const Group &g, uint3
     spmv_chunk<T, kOr64, true>(g.p, c, xs);
 }
 
+#ifndef B2SR_BARRIER_FAST_POLLS
+#define B2SR_BARRIER_FAST_POLLS 0
+#endif
+#ifndef B2SR_BARRIER_MAX_POLLS
+#define B2SR_BARRIER_MAX_POLLS (1u << 19)  // about 2 s of long sleeps
+#endif
+#ifndef B2SR_BARRIER_SLEEP
+#define B2SR_BARRIER_SLEEP 127
+#endif
+
 // Grid-wide barrier for the persistent kernel: block leaders count arrivals;
 // the last one resets the count and advances the generation the others wait
-// on.  Fences around it publish each block's writes device-wide.  A wait is
-// bounded (2^22 polls, a few seconds of wall time): when it runs
-// out, the flag flags[5] is raised and the caller leaves its loop.
-__device__ __forceinline__ void grid_barrier(uint32_t *flags)
+// on.  The count and the generation sit on cache lines of their own, away
+// from the flags every block reads.  Fences around it publish each block's
+// writes device-wide.  A wait is bounded (B2SR_BARRIER_MAX_POLLS polls, each
+// after a sleep: about two seconds): when it runs out, flags[5] is raised and
+// the caller leaves its loop.  Returns, as read once per block after the barrier,
+// bit 0 = flags[5] (timed out) and bit 1 = (*extra != 0) when extra is given.
+__device__ __forceinline__ uint32_t grid_barrier(uint32_t *flags, const uint32_t *extra)
 {
+    __shared__ uint32_t s_state;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t *count = flags + 3, *gen = flags + 4, *timed_out = flags + 5;
+        uint32_t *count = flags + kBarrierCount, *gen = flags + kBarrierGen, *timed_out = flags + 5;
         const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         if (atomicAdd(count, 1u) + 1 == gridDim.x) {
@@ -175,16 +194,23 @@ __device__ __forceinline__ void grid_barrier(uint32_t *flags)
         } else {
             uint32_t spins = 0;
             while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins == (1u << 22)) {
+                // a long sleep between polls: a thousand waiting blocks polling
+                // often crowd the arrivals on the counter's memory channel
+                if (spins < B2SR_BARRIER_FAST_POLLS) __builtin_amdgcn_s_sleep(1);
+                else __builtin_amdgcn_s_sleep(B2SR_BARRIER_SLEEP);
+                if (++spins == B2SR_BARRIER_MAX_POLLS) {
                     atomicOr(timed_out, 1u);
                     break;
                 }
             }
         }
         __threadfence();
+        uint32_t st = __hip_atomic_load(timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+        if (extra && __hip_atomic_load(extra, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) st |= 2u;
+        s_state = st;
     }
     __syncthreads();
+    return s_state;
 }
 
 // Every level of every graph in one launch.  Waves take work items (chunks of
@@ -192,9 +218,26 @@ __device__ __forceinline__ void grid_barrier(uint32_t *flags)
 // the update, and the update from the convergence test.  All threads read the
 // same flags after the barrier, so they leave the level loop together; the loop
 // is also bounded by max_levels and left at once if a barrier timed out.
-__global__ void __launch_bounds__(256) batch_persistent_kernel(BatchArgs b)
+// TMASK holds the tile widths present (bit 0: 4, 1: 8, 2: 16, 3: 32): only their
+// product paths are compiled in, so the registers, and with them the waves per
+// SIMD, are those of the widest path present rather than of all four.
+#ifndef B2SR_PW_SMALL
+#define B2SR_PW_SMALL 1  // waves per SIMD asked for masks without T = 8 and 16
+#endif
+#ifndef B2SR_PW_WIDE
+#define B2SR_PW_WIDE 1   // the same for masks holding T = 8 or 16
+#endif
+constexpr int persistent_waves(unsigned tmask) { return (tmask & 6u) ? B2SR_PW_WIDE : B2SR_PW_SMALL; }
+
+#ifndef B2SR_PERSIST_THREADS
+#define B2SR_PERSIST_THREADS 512  // threads per block of the persistent kernel
+#endif
+constexpr unsigned kPersistThreads = B2SR_PERSIST_THREADS;
+
+template <unsigned TMASK>
+__global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batch_persistent_kernel(BatchArgs b)
 {
-    __shared__ __align__(16) uint64_t s_x[4 * kStageBytesPerWave / sizeof(uint64_t)];
+    __shared__ __align__(16) uint64_t s_x[kPersistThreads / B2SR_WAVE * kStageBytesPerWave / sizeof(uint64_t)];
     uint64_t *xs = s_x + (threadIdx.x / B2SR_WAVE) * (kStageBytesPerWave / sizeof(uint64_t));
     const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     const uint32_t nwaves = gridDim.x * (blockDim.x / B2SR_WAVE);
@@ -205,15 +248,20 @@ __global__ void __launch_bounds__(256) batch_persistent_kernel(BatchArgs b)
             while (gi + 1 < b.ngroups && item >= b.g[gi + 1].item0) ++gi;
             const Group &g = b.g[gi];
             const uint32_t c = item - g.item0;
-            switch (g.tile) {
-            case 4: run_chunk<4>(g, c, xs); break;
-            case 8: run_chunk<8>(g, c, xs); break;
-            case 16: run_chunk<16>(g, c, xs); break;
-            default: run_chunk<32>(g, c, xs); break;
+            if constexpr ((TMASK & 1u) != 0) {
+                if (g.tile == 4) { run_chunk<4>(g, c, xs); continue; }
+            }
+            if constexpr ((TMASK & 2u) != 0) {
+                if (g.tile == 8) { run_chunk<8>(g, c, xs); continue; }
+            }
+            if constexpr ((TMASK & 4u) != 0) {
+                if (g.tile == 16) { run_chunk<16>(g, c, xs); continue; }
+            }
+            if constexpr ((TMASK & 8u) != 0) {
+                if (g.tile == 32) run_chunk<32>(g, c, xs);
             }
         }
-        grid_barrier(b.flags);
-        if (__hip_atomic_load(b.flags + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (grid_barrier(b.flags, nullptr) & 1u) break;
         bool any = false;
         for (uint64_t base = (uint64_t)wave * 64; base < b.n; base += (uint64_t)nwaves * 64)
             any |= update_group(b, base, level);
@@ -222,9 +270,8 @@ __global__ void __launch_bounds__(256) batch_persistent_kernel(BatchArgs b)
             b.flags[(level + 1) & 1] = 0;
             b.flags[2] = level;
         }
-        grid_barrier(b.flags);
-        if (__hip_atomic_load(b.flags + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        if (__hip_atomic_load(b.flags + (level & 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+        const uint32_t st = grid_barrier(b.flags, b.flags + (level & 1));
+        if ((st & 1u) || !(st & 2u)) break;
     }
 }
 
@@ -248,7 +295,7 @@ Layout carve(uint32_t n, void *ws)
     L.V = (uint64_t *)take((size_t)n * 8);
     L.Y = (uint64_t *)take((size_t)n * 8);
     L.act = (uint32_t *)take(((size_t)n + 31) / 32 * 4);
-    L.flags = (uint32_t *)take(32);
+    L.flags = (uint32_t *)take(kFlagWords * 4);
     L.bytes = off;
     return L;
 }
@@ -296,6 +343,7 @@ int make_args(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t 
         g.p.y = L.Y;
         g.p.flags = B2SR_ACCUMULATE;
         g.tile = A->tile;
+        b.tmask |= A->tile == 4 ? 1u : A->tile == 8 ? 2u : A->tile == 16 ? 4u : 8u;
         g.item0 = (uint32_t)items;
         g.nchunks = (uint32_t)(((uint64_t)A->ntiles + g.p.chunk - 1) / g.p.chunk);
         items += g.nchunks;
@@ -319,16 +367,40 @@ int launch_init(const BatchArgs &b, hipStream_t stream)
     return B2SR_OK;
 }
 
-int persistent_grid(unsigned *grid)
+// The persistent kernel compiled for exactly the tile widths present.
+const void *persistent_kernel(unsigned tmask)
+{
+    static const void *const table[16] = {
+        nullptr,
+        (const void *)batch_persistent_kernel<1>,  (const void *)batch_persistent_kernel<2>,
+        (const void *)batch_persistent_kernel<3>,  (const void *)batch_persistent_kernel<4>,
+        (const void *)batch_persistent_kernel<5>,  (const void *)batch_persistent_kernel<6>,
+        (const void *)batch_persistent_kernel<7>,  (const void *)batch_persistent_kernel<8>,
+        (const void *)batch_persistent_kernel<9>,  (const void *)batch_persistent_kernel<10>,
+        (const void *)batch_persistent_kernel<11>, (const void *)batch_persistent_kernel<12>,
+        (const void *)batch_persistent_kernel<13>, (const void *)batch_persistent_kernel<14>,
+        (const void *)batch_persistent_kernel<15>,
+    };
+#ifdef B2SR_PERSIST_FORCE_MASK
+    tmask = B2SR_PERSIST_FORCE_MASK;
+#endif
+    return table[tmask & 15u];
+}
+
+int persistent_grid(const void *kernel, unsigned *grid)
 {
     int dev = 0, per_cu = 0;
     hipDeviceProp_t prop;
+    if (!kernel) return B2SR_EINVAL;
     if (int rc = b2sr::check(hipGetDevice(&dev), "hipGetDevice")) return rc;
     if (int rc = b2sr::check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties")) return rc;
-    if (int rc = b2sr::check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_persistent_kernel, 256, 0),
+    if (int rc = b2sr::check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kPersistThreads, 0),
                              "hipOccupancyMaxActiveBlocksPerMultiprocessor"))
         return rc;
     if (per_cu < 1 || !prop.cooperativeLaunch) return B2SR_ENOTSUP;
+#ifdef B2SR_PERSIST_MAX_PER_CU
+    if (per_cu > B2SR_PERSIST_MAX_PER_CU) per_cu = B2SR_PERSIST_MAX_PER_CU;
+#endif
     *grid = (unsigned)per_cu * (unsigned)prop.multiProcessorCount;
     return B2SR_OK;
 }
@@ -336,10 +408,10 @@ int persistent_grid(unsigned *grid)
 int launch_persistent(BatchArgs &b, hipStream_t stream)
 {
     unsigned grid = 0;
-    if (int rc = persistent_grid(&grid)) return rc;
+    const void *kernel = persistent_kernel(b.tmask);
+    if (int rc = persistent_grid(kernel, &grid)) return rc;
     void *args[] = {&b};
-    return b2sr::check(hipLaunchCooperativeKernel((const void *)batch_persistent_kernel, dim3(grid), dim3(256), args, 0,
-                                                  stream),
+    return b2sr::check(hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(kPersistThreads), args, 0, stream),
                        "hipLaunchCooperativeKernel(batch_persistent_kernel)");
 }
 
@@ -489,8 +561,8 @@ int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix
     if (!rc && mode == B2SR_BATCH_PERSISTENT) {
         unsigned grid = 0;
         hipGraphNode_t run = nullptr;
-        rc = persistent_grid(&grid);
-        if (!rc) rc = add_node(P->first, &last, (const void *)batch_persistent_kernel, grid, 256, args_b, &run);
+        rc = persistent_grid(persistent_kernel(b.tmask), &grid);
+        if (!rc) rc = add_node(P->first, &last, persistent_kernel(b.tmask), grid, kPersistThreads, args_b, &run);
         if (!rc) {
             // ask for co-residency checks where the runtime offers them; the barrier
             // itself needs no runtime support and the grid is sized to be resident
