@@ -20,6 +20,8 @@
 // is read once per workgroup and Bt's rows are re-read from L2/MALL.
 #include <type_traits>
 
+#include <algorithm>
+
 #include "common.h"
 
 using namespace b2sr_dev;
@@ -29,7 +31,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / B2SR_WAVE;
 constexpr uint32_t kMapWords = 4096;  // bitmap of up to 131072 tile columns
-constexpr uint32_t kMaxPairs = 1024;  // set bits of a 32 x 32 mask tile
 
 template <int T> __device__ __forceinline__ uint32_t load_word(const void *bits, size_t idx)
 {
@@ -51,6 +52,7 @@ struct GemmArgs {
     const uint32_t *m_rp, *m_ci;
     const void *m_bits;
     uint32_t ntr;
+    uint32_t map_words;  // LDS bitmap words: enough for every tile column, at most kMapWords
     unsigned long long *sum;
 };
 
@@ -84,10 +86,12 @@ __device__ __forceinline__ uint32_t pair_sum(const GemmArgs &g, size_t ia, uint3
 // operations (matched pairs times the mask tile's set bits).
 template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThreads) spgemm_masked_kernel(GemmArgs g)
 {
-    __shared__ uint32_t s_map[kMapWords];
-    __shared__ uint32_t s_pre[kMapWords];
+    // the bitmap and its prefix are sized at launch to the matrix's tile columns,
+    // so that small matrices leave room for more workgroups per CU
+    extern __shared__ uint32_t s_dyn[];
+    uint32_t *const s_map = s_dyn, *const s_pre = s_dyn + g.map_words;
     __shared__ uint32_t s_thr[kThreads];
-    __shared__ uint16_t s_pairs[kWaves][kMaxPairs];
+    __shared__ uint16_t s_pairs[kWaves][T * T];
     __shared__ uint32_t s_cnt[kWaves][B2SR_WAVE];
     const uint32_t lane = lane_id(), wv = threadIdx.x / B2SR_WAVE;
     unsigned long long acc = 0;
@@ -99,7 +103,7 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
         if (m0 == m1 || a0 == a1) continue;  // workgroup-uniform
         const uint32_t jlo = g.a_ci[a0], jhi = g.a_ci[a1 - 1];
         const uint32_t span = jhi - jlo + 1;
-        const bool use_map = span <= kMapWords * 32;
+        const bool use_map = span <= g.map_words * 32;
         __syncthreads();
         if (use_map) {
             const uint32_t nw = (span + 31) / 32;
@@ -248,9 +252,14 @@ __global__ void __launch_bounds__(256) dot_counts_kernel(const uint32_t *__restr
 
 __global__ void zero_u64_kernel(unsigned long long *p) { *p = 0; }
 
-template <int T, bool PROFILE = false> int launch_masked(const GemmArgs &g, hipStream_t s)
+template <int T, bool PROFILE = false> int launch_masked(GemmArgs g, hipStream_t s)
 {
-    spgemm_masked_kernel<T, PROFILE><<<b2sr::grid_for(g.ntr, 1, 1u << 16), kThreads, 0, s>>>(g);
+    g.map_words = std::max<uint32_t>(1, std::min<uint32_t>(kMapWords, (g.ntr + 31) / 32));
+    // At T = 32 every match reads tile rows from global memory, and more resident
+    // workgroups measured slower: its blocks keep the full-size bitmap's LDS,
+    // which holds them to 3 per CU.
+    const uint32_t lds_words = T == 32 ? kMapWords : g.map_words;
+    spgemm_masked_kernel<T, PROFILE><<<b2sr::grid_for(g.ntr, 1, 1u << 16), kThreads, 2 * lds_words * 4, s>>>(g);
     return b2sr::check_launch("spgemm_masked_kernel");
 }
 
@@ -320,7 +329,7 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
     if ((rc = b2sr::check_launch("zero_u64x4_kernel"))) return rc;
     if (A->n == 0 || A->ntiles == 0 || Bt->ntiles == 0 || M->ntiles == 0) return B2SR_OK;
     GemmArgs g{A->tile_rowptr, A->tile_colind, A->bits, Bt->tile_rowptr, Bt->tile_colind, Bt->bits,
-               M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), c};
+               M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), 0, c};
     switch (A->tile) {
     case 4: return launch_masked<4, true>(g, stream);
     case 8: return launch_masked<8, true>(g, stream);
@@ -359,7 +368,7 @@ int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix
         }
     }
     GemmArgs g{A->tile_rowptr, A->tile_colind, A->bits, Bt->tile_rowptr, Bt->tile_colind, Bt->bits,
-               M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), sum};
+               M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), 0, sum};
     switch (A->tile) {
     case 4: return launch_masked<4>(g, stream);
     case 8: return launch_masked<8>(g, stream);
