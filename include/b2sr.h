@@ -249,6 +249,18 @@ size_t spgemm_masked_workspace_bytes(const b2sr_matrix *A, const b2sr_matrix *M)
 int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix *M,
                   unsigned flags, uint64_t *d_sum, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* spgemm_masked_rows: spgemm_masked restricted to the mask's tile-rows
+ *   [row_begin, row_end): *d_sum receives (or, with B2SR_ACCUMULATE, gains)
+ *   the sum over the mask's ones in rows row_begin*T .. row_end*T - 1 only.
+ *   Sums over consecutive ranges add up to spgemm_masked's.  M is required;
+ *   no workspace.  It lets a caller cut one long product into shorter
+ *   launches (a serving loop interleaving other work between them), and is
+ *   the per-device call when mask tile-rows are split across devices.
+ *   row_begin > row_end or row_end > ceil(n/T): EINVAL.  Errors: EINVAL, EHIP. */
+int spgemm_masked_rows(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix *M,
+                       uint32_t row_begin, uint32_t row_end, unsigned flags, uint64_t *d_sum,
+                       hipStream_t stream);
+
 /* spgemm_masked_profile: the work spgemm_masked does for the same operands
  *   (M required), counted instead of the sum.  d_counts (device, 4 x uint64_t)
  *   receives: [0] mask tiles visited (those whose tile-row of A is non-empty),

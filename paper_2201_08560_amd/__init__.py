@@ -20,12 +20,12 @@ import torch
 __all__ = [
     "B2SRError", "B2SR", "lib", "b2sr_count_tiles", "b2sr_from_csr", "b2sr_pack_bits", "spmv_bin_bin",
     "spmv_bin_full", "spmv_bin_full_workspace_bytes", "spgemm_masked", "spgemm_masked_workspace_bytes",
-    "spgemm_masked_profile", "b2sr_pagerank_directed", "b2sr_csr_transpose", "b2sr_mis", "b2sr_color",
+    "spgemm_masked_profile", "spgemm_masked_rows", "b2sr_pagerank_directed", "b2sr_csr_transpose", "b2sr_mis", "b2sr_color",
     "mis_keys", "b2sr_eccentricity", "b2sr_diameter",
     "b2sr_algo_workspace_bytes", "b2sr_bfs", "b2sr_msbfs", "b2sr_sssp", "b2sr_cc", "b2sr_pagerank",
     "triangle_count", "b2sr_strerror", "as_u32", "as_u64", "header_functions", "FLAGS", "SEMIRINGS",
     "b2sr_msbfs_batch", "b2sr_msbfs_batch_workspace_bytes", "MsbfsPlan", "BfsSession",
-    "b2sr_bfs_session_bytes",
+    "b2sr_bfs_session_bytes", "b2sr_lgc", "b2sr_sweep_cut",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -82,6 +82,7 @@ _SIGS = {
     "spgemm_masked_workspace_bytes": (_SZ, [_MP, _MP]),
     "spgemm_masked": (_I, [_MP, _MP, _MP, ctypes.c_uint, _P, _P, _SZ, _P]),
     "spgemm_masked_profile": (_I, [_MP, _MP, _MP, _P, _P]),
+    "spgemm_masked_rows": (_I, [_MP, _MP, _MP, _U32, _U32, ctypes.c_uint, _P, _P]),
     "b2sr_algo_workspace_bytes": (_SZ, [_MP, _I]),
     "b2sr_bfs": (_I, [_MP, _U32, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
     "b2sr_msbfs": (_I, [_MP, ctypes.POINTER(_U32), _U32, _P, _P, _SZ, ctypes.POINTER(_U32), _P]),
@@ -301,6 +302,14 @@ def spgemm_masked(A: B2SR, Bt: B2SR, M: B2SR | None = None, accumulate=False, ou
 
 
 # ---- algorithms -------------------------------------------------------------
+
+def spgemm_masked_rows(A: B2SR, Bt: B2SR, M: B2SR, row_begin: int, row_end: int, accumulate=False, out=None):
+    """spgemm_masked over the mask tile-rows [row_begin, row_end) only."""
+    out = torch.zeros(1, dtype=torch.int64, device="cuda") if out is None else out
+    _check(lib().spgemm_masked_rows(A.view, Bt.view, M.view, int(row_begin), int(row_end),
+                                    ACCUMULATE if accumulate else 0, _ptr(out), _stream()), "spgemm_masked_rows")
+    return out
+
 
 def spgemm_masked_profile(A: B2SR, Bt: B2SR, M: B2SR, out=None) -> dict:
     """Work counts of spgemm_masked(A, Bt, M) (b2sr.h): mask tiles, lookups,

@@ -54,6 +54,7 @@ struct GemmArgs {
     uint32_t ntr;
     uint32_t map_words;  // LDS bitmap words: enough for every tile column, at most kMapWords
     unsigned long long *sum;
+    uint32_t row0, row1;  // the mask tile-rows taken: [row0, row1)
 };
 
 // sum over the listed mask bits (r, c) of popcount(A_tile[r] & Bt_tile[c]) for
@@ -97,7 +98,7 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
     unsigned long long acc = 0;
     [[maybe_unused]] unsigned long long n_tiles = 0, n_lookups = 0, n_matches = 0;
 
-    for (uint32_t I = blockIdx.x; I < g.ntr; I += gridDim.x) {
+    for (uint32_t I = g.row0 + blockIdx.x; I < g.row1; I += gridDim.x) {
         const uint32_t m0 = g.m_rp[I], m1 = g.m_rp[I + 1];
         const uint32_t a0 = g.a_rp[I], a1 = g.a_rp[I + 1];
         if (m0 == m1 || a0 == a1) continue;  // workgroup-uniform
@@ -259,7 +260,8 @@ template <int T, bool PROFILE = false> int launch_masked(GemmArgs g, hipStream_t
     // workgroups measured slower: its blocks keep the full-size bitmap's LDS,
     // which holds them to 3 per CU.
     const uint32_t lds_words = T == 32 ? kMapWords : g.map_words;
-    spgemm_masked_kernel<T, PROFILE><<<b2sr::grid_for(g.ntr, 1, 1u << 16), kThreads, 2 * lds_words * 4, s>>>(g);
+    if (g.row1 <= g.row0) return B2SR_OK;
+    spgemm_masked_kernel<T, PROFILE><<<b2sr::grid_for(g.row1 - g.row0, 1, 1u << 16), kThreads, 2 * lds_words * 4, s>>>(g);
     return b2sr::check_launch("spgemm_masked_kernel");
 }
 
@@ -329,7 +331,8 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
     if ((rc = b2sr::check_launch("zero_u64x4_kernel"))) return rc;
     if (A->n == 0 || A->ntiles == 0 || Bt->ntiles == 0 || M->ntiles == 0) return B2SR_OK;
     GemmArgs g{A->tile_rowptr, A->tile_colind, A->bits, Bt->tile_rowptr, Bt->tile_colind, Bt->bits,
-               M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), 0, c};
+               M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), 0, c,
+               0, b2sr::n_tile_rows(A->n, A->tile)};
     switch (A->tile) {
     case 4: return launch_masked<4, true>(g, stream);
     case 8: return launch_masked<8, true>(g, stream);
@@ -368,7 +371,37 @@ int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix
         }
     }
     GemmArgs g{A->tile_rowptr, A->tile_colind, A->bits, Bt->tile_rowptr, Bt->tile_colind, Bt->bits,
-               M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), 0, sum};
+               M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), 0, sum,
+               0, b2sr::n_tile_rows(A->n, A->tile)};
+    switch (A->tile) {
+    case 4: return launch_masked<4>(g, stream);
+    case 8: return launch_masked<8>(g, stream);
+    case 16: return launch_masked<16>(g, stream);
+    default: return launch_masked<32>(g, stream);
+    }
+}
+
+int spgemm_masked_rows(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix *M, uint32_t row_begin,
+                       uint32_t row_end, unsigned flags, uint64_t *d_sum, hipStream_t stream)
+{
+    int rc = b2sr::validate_matrix(A);
+    if (rc) return rc;
+    if ((rc = b2sr::validate_matrix(Bt))) return rc;
+    if (!M) return B2SR_EINVAL;
+    if ((rc = b2sr::validate_matrix(M))) return rc;
+    if (flags & ~B2SR_ACCUMULATE) return B2SR_EINVAL;
+    if (!d_sum) return B2SR_EINVAL;
+    if (Bt->n != A->n || Bt->tile != A->tile || M->n != A->n || M->tile != A->tile) return B2SR_EINVAL;
+    const uint32_t ntr = b2sr::n_tile_rows(A->n, A->tile);
+    if (row_begin > row_end || row_end > ntr) return B2SR_EINVAL;
+    unsigned long long *sum = (unsigned long long *)d_sum;
+    if (!(flags & B2SR_ACCUMULATE)) {
+        zero_u64_kernel<<<1, 1, 0, stream>>>(sum);
+        if ((rc = b2sr::check_launch("zero_u64_kernel"))) return rc;
+    }
+    if (A->n == 0 || A->ntiles == 0 || Bt->ntiles == 0 || M->ntiles == 0) return B2SR_OK;
+    GemmArgs g{A->tile_rowptr, A->tile_colind, A->bits, Bt->tile_rowptr, Bt->tile_colind, Bt->bits,
+               M->tile_rowptr, M->tile_colind, M->bits, ntr, 0, sum, row_begin, row_end};
     switch (A->tile) {
     case 4: return launch_masked<4>(g, stream);
     case 8: return launch_masked<8>(g, stream);

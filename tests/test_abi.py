@@ -84,6 +84,11 @@ def test_spgemm_and_build_argument_errors():
     assert L.spgemm_masked_workspace_bytes(A, A) == 0
     assert L.spgemm_masked_workspace_bytes(A, None) == 2 * 8 * 8 * 4
     assert L.spgemm_masked(A, A, None, 0, s, None, 0, None) == -3       # unmasked needs workspace
+    assert L.spgemm_masked_rows(A, A, None, 0, 8, 0, s, None) == -1      # mask required
+    assert L.spgemm_masked_rows(A, A, A, 3, 2, 0, s, None) == -1         # begin > end
+    assert L.spgemm_masked_rows(A, A, A, 0, 9, 0, s, None) == -1         # end past the 8 tile-rows
+    assert L.spgemm_masked_rows(A, B16, A, 0, 8, 0, s, None) == -1       # tile mismatch
+    assert L.spgemm_masked_rows(A, A, A, 0, 8, 0, None, None) == -1      # no output
     nt = ctypes.c_uint64(0)
     p = ctypes.c_void_p(FAKE)
     assert L.b2sr_count_tiles(10, 5, p, p, 5, 0, p, ctypes.byref(nt), None) == -1       # tile 5

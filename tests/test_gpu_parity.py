@@ -330,6 +330,35 @@ def test_spgemm_masked(gi, T):
     assert int(b2.as_u64(acc)[0]) == 2 * orc.masked_sum(g, g, g)
 
 
+def _rows_only(c, r0, r1):
+    """CSR c with every row outside [r0, r1) emptied (a mask restricted to rows)."""
+    rows = np.repeat(np.arange(c.n, dtype=np.int64), np.diff(c.rowptr.astype(np.int64)))
+    keep = (rows >= r0) & (rows < r1)
+    return gg.directed_csr(c.n, rows[keep], c.colind.astype(np.int64)[keep])
+
+
+@pytest.mark.parametrize("T", TILES)
+@pytest.mark.parametrize("gi", range(len(GRAPHS)), ids=IDS)
+def test_spgemm_masked_rows(gi, T):
+    """The product over consecutive ranges of mask tile-rows: each range equals
+    the oracle's sum with the mask restricted to those rows, and the ranges add
+    up to the whole product (triangle counting and the A.A mask)."""
+    g = GRAPHS[gi]
+    ntr = (g.n + T - 1) // T
+    cuts = sorted({0, ntr, *gg.rng(900 + gi).integers(0, ntr + 1, 3).tolist()})
+    L = orc.tril(g)
+    Ld, A = b2sr(g, T, lower=True), b2sr(g, T)
+    for X, Xd in ((L, Ld), (g, A)):
+        total = b2.spgemm_masked_rows(Xd, Xd, Xd, 0, 0)          # an empty range gives 0
+        assert int(b2.as_u64(total)[0]) == 0
+        for r0, r1 in zip(cuts[:-1], cuts[1:]):
+            print(f"spgemm rows {g.name} T={T} [{r0}, {r1})", flush=True)
+            part = b2.spgemm_masked_rows(Xd, Xd, Xd, r0, r1)
+            assert int(b2.as_u64(part)[0]) == orc.masked_sum(X, X, _rows_only(X, r0 * T, r1 * T))
+            b2.spgemm_masked_rows(Xd, Xd, Xd, r0, r1, accumulate=True, out=total)
+        assert int(b2.as_u64(total)[0]) == int(b2.as_u64(b2.spgemm_masked(Xd, Xd, Xd))[0])
+
+
 def _tiles(c, T):
     """(tile-row, tile-column, set bits) of every non-empty T x T tile of CSR c."""
     rows = np.repeat(np.arange(c.n, dtype=np.int64), np.diff(c.rowptr.astype(np.int64)))
