@@ -242,7 +242,12 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
  *   n and T and may alias.  Triangle counting (Sec. V) is A = Bt = M = L, the
  *   strictly lower triangle.
  *   B2SR_ACCUMULATE adds to *d_sum instead of overwriting it.
- *   ws: spgemm_masked_workspace_bytes(A, M) bytes (0 when M != NULL).
+ *   ws: spgemm_masked_workspace_bytes(A, M) bytes.  Unmasked: required.
+ *   Masked: optional.  When A and Bt are the same matrix (the same three
+ *   arrays), a workspace of that size holds lists that let each mask tile (I, J)
+ *   scan the shorter of A's tile-row I and Bt's tile-row J: about half the
+ *   lookups on power-law graphs.  The result is the same with or without it:
+ *   with ws NULL or smaller, every mask tile scans Bt's row J.
  *   Errors: EINVAL, ENOSPC, EHIP.
  */
 size_t spgemm_masked_workspace_bytes(const b2sr_matrix *A, const b2sr_matrix *M);
@@ -253,7 +258,7 @@ int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix
  *   [row_begin, row_end): *d_sum receives (or, with B2SR_ACCUMULATE, gains)
  *   the sum over the mask's ones in rows row_begin*T .. row_end*T - 1 only.
  *   Sums over consecutive ranges add up to spgemm_masked's.  M is required;
- *   no workspace.  It lets a caller cut one long product into shorter
+ *   no workspace (every mask tile scans Bt's row J).  It lets a caller cut one long product into shorter
  *   launches (a serving loop interleaving other work between them), and is
  *   the per-device call when mask tile-rows are split across devices.
  *   row_begin > row_end or row_end > ceil(n/T): EINVAL.  Errors: EINVAL, EHIP. */
@@ -262,6 +267,7 @@ int spgemm_masked_rows(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_m
                        hipStream_t stream);
 
 /* spgemm_masked_profile: the work spgemm_masked does for the same operands
+ *   when every mask tile scans Bt's row J (no workspace)
  *   (M required), counted instead of the sum.  d_counts (device, 4 x uint64_t)
  *   receives: [0] mask tiles visited (those whose tile-row of A is non-empty),
  *   [1] tile columns of Bt looked up in A's tile-row, [2] matched tile pairs

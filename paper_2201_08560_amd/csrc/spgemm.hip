@@ -23,8 +23,13 @@
 #include <algorithm>
 
 #include "common.h"
+#include "scan.h"
 
 using namespace b2sr_dev;
+
+namespace b2sr {
+int fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
+}
 
 namespace {
 
@@ -43,6 +48,10 @@ template <int T> __device__ __forceinline__ uint32_t load_word(const void *bits,
 #define B2SR_TC_UB 4
 #endif
 constexpr int kUB = B2SR_TC_UB;  // Bt tile columns per lane per round
+#ifndef B2SR_TC_SWAP_CHUNK
+#define B2SR_TC_SWAP_CHUNK 128
+#endif
+constexpr uint32_t kSwapChunk = B2SR_TC_SWAP_CHUNK;  // swapped mask tiles per work item
 
 struct GemmArgs {
     const uint32_t *a_rp, *a_ci;
@@ -55,7 +64,26 @@ struct GemmArgs {
     uint32_t map_words;  // LDS bitmap words: enough for every tile column, at most kMapWords
     unsigned long long *sum;
     uint32_t row0, row1;  // the mask tile-rows taken: [row0, row1)
+    // Orientation (A and Bt the same matrix): the mask tiles (I, J) with
+    // 0 < |A_I| < |Bt_J| tiles are listed under J as (I, mask tile) pairs,
+    // sw_list[2 e], sw_list[2 e + 1] for e in [sw_off[J], sw_off[J + 1]); the
+    // workgroup of tile-row J then scans A's shorter row I against its bitmap.
+    // Null: every mask tile scans Bt's row J.
+    const uint32_t *sw_off, *sw_list;
+    // Work items when sw_off is set: (row | 2^31 for a swapped chunk, e0, e1)
+    // triples; item_off[ntr] of them.  A row's own mask tiles are one item,
+    // its list of swapped tiles is cut into chunks of kSwapChunk entries, so
+    // that a long row's list is spread over many workgroups.
+    const uint32_t *item_off, *items;
+    uint32_t items_bound;  // an upper bound of item_off[ntr] (the launch's grid)
 };
+
+// Whether mask tile (I, J) is taken from J's side: A and Bt alias, and A's row
+// I is the shorter non-empty one.
+__device__ __forceinline__ bool swapped(uint32_t len_ai, uint32_t len_btj)
+{
+    return len_ai > 0 && len_ai < len_btj;
+}
 
 // sum over the listed mask bits (r, c) of popcount(A_tile[r] & Bt_tile[c]) for
 // the tiles at positions ia (A) and kb (Bt).  Tiles of T <= 8 are loaded whole
@@ -98,10 +126,20 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
     unsigned long long acc = 0;
     [[maybe_unused]] unsigned long long n_tiles = 0, n_lookups = 0, n_matches = 0;
 
-    for (uint32_t I = g.row0 + blockIdx.x; I < g.row1; I += gridDim.x) {
-        const uint32_t m0 = g.m_rp[I], m1 = g.m_rp[I + 1];
+    const uint32_t nwork = g.sw_off ? g.item_off[g.ntr] : g.row1 - g.row0;
+    for (uint32_t wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
+        uint32_t I = g.row0 + wk, s0 = 0, s1 = 0;
+        bool own = true;  // this row's own mask tiles (else a chunk of its swapped list)
+        if (g.sw_off) {
+            const uint32_t x = g.items[3 * (size_t)wk];
+            I = x & 0x7FFFFFFFu;
+            own = !(x >> 31);
+            s0 = g.items[3 * (size_t)wk + 1];
+            s1 = g.items[3 * (size_t)wk + 2];
+        }
+        const uint32_t m0 = own ? g.m_rp[I] : 0u, m1 = own ? g.m_rp[I + 1] : 0u;
         const uint32_t a0 = g.a_rp[I], a1 = g.a_rp[I + 1];
-        if (m0 == m1 || a0 == a1) continue;  // workgroup-uniform
+        if ((m0 == m1 && s0 == s1) || a0 == a1) continue;  // workgroup-uniform
         const uint32_t jlo = g.a_ci[a0], jhi = g.a_ci[a1 - 1];
         const uint32_t span = jhi - jlo + 1;
         const bool use_map = span <= g.map_words * 32;
@@ -154,8 +192,12 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
             return (lo < a1 && g.a_ci[lo] == K) ? (int64_t)lo : -1;
         };
 
-        for (uint32_t m = m0 + wv; m < m1; m += kWaves) {
-            const uint32_t J = g.m_ci[m];
+        // One mask tile m: its set bits (r, c) are listed, then the tile columns
+        // ci[p0 .. p1) of the streamed row are looked up in this row's bitmap.
+        // Normal orientation: the stream is Bt's row J and the bitmap gives A_IK;
+        // swapped: the stream is A's row (the mask tile's row) and the bitmap,
+        // this row of Bt = A, gives Bt_JK.
+        auto do_tile = [&](uint32_t m, uint32_t p0, uint32_t p1, const uint32_t *ci, bool swap) {
             // list the set bits (r, c) of mask tile m
             const uint32_t mw = lane < (uint32_t)T ? load_word<T>(g.m_bits, (size_t)m * T + lane) : 0u;
             const uint32_t cnt = __popc(mw);
@@ -174,36 +216,47 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const uint32_t b0 = g.b_rp[J], b1 = g.b_rp[J + 1];
-            // Bt's tile-row J, kUB tile columns per lane per round: the column
+            // the streamed row, kUB tile columns per lane per round: the column
             // loads and lookups of a round are independent, so they overlap
             unsigned long long part = 0;
-            for (uint32_t base = b0; base < b1; base += 64 * kUB) {
-                uint32_t kb[kUB], K[kUB];
+            for (uint32_t base = p0; base < p1; base += 64 * kUB) {
+                uint32_t ps[kUB], K[kUB];
 #pragma unroll
                 for (int u = 0; u < kUB; ++u) {
-                    kb[u] = base + 64 * u + lane;
-                    K[u] = g.b_ci[min(kb[u], b1 - 1)];
+                    ps[u] = base + 64 * u + lane;
+                    K[u] = ci[min(ps[u], p1 - 1)];
                 }
-                int64_t ia[kUB];
+                int64_t hit[kUB];
 #pragma unroll
-                for (int u = 0; u < kUB; ++u) ia[u] = kb[u] < b1 ? lookup(K[u]) : -1;
+                for (int u = 0; u < kUB; ++u) hit[u] = ps[u] < p1 ? lookup(K[u]) : -1;
 #pragma unroll
                 for (int u = 0; u < kUB; ++u) {
                     if constexpr (PROFILE) {
-                        n_lookups += kb[u] < b1;
-                        if (ia[u] >= 0) {
+                        n_lookups += ps[u] < p1;
+                        if (hit[u] >= 0) {
                             ++n_matches;
                             part += npairs;
                         }
-                    } else if (ia[u] >= 0) {
-                        part += pair_sum<T>(g, (size_t)ia[u], kb[u], s_pairs[wv], npairs);
+                    } else if (hit[u] >= 0) {
+                        part += swap ? pair_sum<T>(g, (size_t)ps[u], (uint32_t)hit[u], s_pairs[wv], npairs)
+                                     : pair_sum<T>(g, (size_t)hit[u], ps[u], s_pairs[wv], npairs);
                     }
                 }
             }
             acc += part;
             if constexpr (PROFILE) n_tiles += lane == 0;
             __builtin_amdgcn_wave_barrier();
+        };
+
+        for (uint32_t m = m0 + wv; m < m1; m += kWaves) {
+            const uint32_t J = g.m_ci[m];
+            const uint32_t b0 = g.b_rp[J], b1 = g.b_rp[J + 1];
+            if (g.sw_off && swapped(a1 - a0, b1 - b0)) continue;  // taken from J's side
+            do_tile(m, b0, b1, g.b_ci, false);
+        }
+        for (uint32_t e = s0 + wv; e < s1; e += kWaves) {
+            const uint32_t Ir = g.sw_list[2 * (size_t)e], m = g.sw_list[2 * (size_t)e + 1];
+            do_tile(m, g.a_rp[Ir], g.a_rp[Ir + 1], g.a_ci, true);
         }
     }
     (void)s_cnt;
@@ -260,8 +313,9 @@ template <int T, bool PROFILE = false> int launch_masked(GemmArgs g, hipStream_t
     // workgroups measured slower: its blocks keep the full-size bitmap's LDS,
     // which holds them to 3 per CU.
     const uint32_t lds_words = T == 32 ? kMapWords : g.map_words;
-    if (g.row1 <= g.row0) return B2SR_OK;
-    spgemm_masked_kernel<T, PROFILE><<<b2sr::grid_for(g.row1 - g.row0, 1, 1u << 16), kThreads, 2 * lds_words * 4, s>>>(g);
+    if (!g.sw_off && g.row1 <= g.row0) return B2SR_OK;
+    const uint32_t work = g.sw_off ? g.items_bound : g.row1 - g.row0;
+    spgemm_masked_kernel<T, PROFILE><<<b2sr::grid_for(work, 1, 1u << 16), kThreads, 2 * lds_words * 4, s>>>(g);
     return b2sr::check_launch("spgemm_masked_kernel");
 }
 
@@ -284,11 +338,137 @@ int launch_unmasked(const b2sr_matrix *A, const b2sr_matrix *Bt, uint32_t *ws, u
     return b2sr::check_launch("dot_counts_kernel");
 }
 
-}  // namespace
-
-namespace b2sr {
-int fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
+// ---- orientation lists (A and Bt the same matrix) ------------------------------
+// One wave per mask tile-row I, its lanes over the row's tiles.
+__global__ void swap_count_kernel(GemmArgs g, uint32_t *counts)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t I = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B2SR_WAVE; I < g.ntr; I += nwaves) {
+        const uint32_t lai = g.a_rp[I + 1] - g.a_rp[I];
+        for (uint32_t m = g.m_rp[I] + lane; m < g.m_rp[I + 1]; m += B2SR_WAVE) {
+            const uint32_t J = g.m_ci[m];
+            if (swapped(lai, g.b_rp[J + 1] - g.b_rp[J])) atomicAdd(&counts[J], 1u);
+        }
+    }
 }
+
+__global__ void swap_fill_kernel(GemmArgs g, uint32_t *cursor, uint32_t *list)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t I = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B2SR_WAVE; I < g.ntr; I += nwaves) {
+        const uint32_t lai = g.a_rp[I + 1] - g.a_rp[I];
+        for (uint32_t m = g.m_rp[I] + lane; m < g.m_rp[I + 1]; m += B2SR_WAVE) {
+            const uint32_t J = g.m_ci[m];
+            if (!swapped(lai, g.b_rp[J + 1] - g.b_rp[J])) continue;
+            const uint32_t e = atomicAdd(&cursor[J], 1u);
+            list[2 * (size_t)e] = (uint32_t)I;
+            list[2 * (size_t)e + 1] = m;
+        }
+    }
+}
+
+// Work items per row: one for its own mask tiles (when it has any and A's row
+// is not empty), one per kSwapChunk entries of its swapped list.
+__global__ void item_count_kernel(GemmArgs g, const uint32_t *off, uint32_t *counts)
+{
+    for (uint32_t X = blockIdx.x * blockDim.x + threadIdx.x; X < g.ntr; X += gridDim.x * blockDim.x) {
+        const bool own = g.m_rp[X + 1] > g.m_rp[X] && g.a_rp[X + 1] > g.a_rp[X];
+        counts[X] = (own ? 1u : 0u) + (off[X + 1] - off[X] + kSwapChunk - 1) / kSwapChunk;
+    }
+}
+
+__global__ void item_fill_kernel(GemmArgs g, const uint32_t *off, const uint32_t *item_off, uint32_t *items)
+{
+    for (uint32_t X = blockIdx.x * blockDim.x + threadIdx.x; X < g.ntr; X += gridDim.x * blockDim.x) {
+        size_t w = item_off[X];
+        if (g.m_rp[X + 1] > g.m_rp[X] && g.a_rp[X + 1] > g.a_rp[X]) {
+            items[3 * w] = X;
+            items[3 * w + 1] = 0;
+            items[3 * w + 2] = 0;
+            ++w;
+        }
+        for (uint32_t e = off[X]; e < off[X + 1]; e += kSwapChunk, ++w) {
+            items[3 * w] = X | 0x80000000u;
+            items[3 * w + 1] = e;
+            items[3 * w + 2] = min(off[X + 1], e + kSwapChunk);
+        }
+    }
+}
+
+__global__ void copy_u32_kernel(uint32_t n, const uint32_t *__restrict__ a, uint32_t *__restrict__ b)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+struct SwapLayout {
+    uint32_t *off, *cursor, *list, *item_off, *items, *sums;
+    size_t bytes;
+};
+
+SwapLayout swap_layout(const b2sr_matrix *A, const b2sr_matrix *M, void *ws)
+{
+    const size_t ntr = b2sr::n_tile_rows(A->n, A->tile);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        o = (o + 255) & ~(size_t)255;
+        char *p = ws ? (char *)ws + o : nullptr;
+        o += bytes;
+        return (uint32_t *)p;
+    };
+    SwapLayout L;
+    L.off = take((ntr + 1) * 4);
+    L.cursor = take(ntr * 4);
+    L.list = take((size_t)M->ntiles * 8);
+    L.item_off = take((ntr + 1) * 4);
+    // at most one item per row for its own tiles plus one per started chunk
+    L.items = take((2 * ntr + (size_t)M->ntiles / kSwapChunk + 1) * 12);
+    L.sums = take(b2sr_scan::scan_blocks(ntr) * 4);
+    L.bytes = o;
+    return L;
+}
+
+size_t swap_bytes(const b2sr_matrix *A, const b2sr_matrix *M) { return swap_layout(A, M, nullptr).bytes; }
+
+// Lists, under each tile-row J, the mask tiles (I, J) whose row I of A is the
+// shorter: counts, their prefix (the list offsets), then a scatter through a
+// copy of the offsets.  The order inside a list follows the atomics, which
+// does not change the integer sum.
+int build_swap_lists(GemmArgs &g, const b2sr_matrix *A, const b2sr_matrix *M, void *ws, hipStream_t s)
+{
+    using b2sr_scan::device_scan;
+    using b2sr_scan::LoadArray;
+    const SwapLayout L = swap_layout(A, M, ws);
+    const uint32_t ntr = g.ntr;
+    int rc;
+    // list offsets: off[0] = 0, off[J + 1] = swapped tiles of rows 0 .. J
+    if ((rc = b2sr::fill_u32(L.off, (uint64_t)ntr + 1, 0, s))) return rc;
+    const unsigned wgrid = b2sr::grid_for(ntr, 256 / B2SR_WAVE, 1u << 16);
+    swap_count_kernel<<<wgrid, 256, 0, s>>>(g, L.off + 1);
+    if ((rc = b2sr::check_launch("swap_count_kernel"))) return rc;
+    if ((rc = device_scan<uint32_t>(ntr, LoadArray<uint32_t>{L.off + 1}, L.off + 1, true, L.sums, s))) return rc;
+    copy_u32_kernel<<<b2sr::grid_for(ntr, 256, 4096), 256, 0, s>>>(ntr, L.off, L.cursor);
+    if ((rc = b2sr::check_launch("copy_u32_kernel"))) return rc;
+    swap_fill_kernel<<<wgrid, 256, 0, s>>>(g, L.cursor, L.list);
+    if ((rc = b2sr::check_launch("swap_fill_kernel"))) return rc;
+    // work items: item_off[0] = 0, item_off[X + 1] = items of rows 0 .. X
+    if ((rc = b2sr::fill_u32(L.item_off, 1, 0, s))) return rc;
+    item_count_kernel<<<b2sr::grid_for(ntr, 256, 4096), 256, 0, s>>>(g, L.off, L.item_off + 1);
+    if ((rc = b2sr::check_launch("item_count_kernel"))) return rc;
+    if ((rc = device_scan<uint32_t>(ntr, LoadArray<uint32_t>{L.item_off + 1}, L.item_off + 1, true, L.sums, s)))
+        return rc;
+    item_fill_kernel<<<b2sr::grid_for(ntr, 256, 4096), 256, 0, s>>>(g, L.off, L.item_off, L.items);
+    if ((rc = b2sr::check_launch("item_fill_kernel"))) return rc;
+    g.sw_off = L.off;
+    g.sw_list = L.list;
+    g.item_off = L.item_off;
+    g.items = L.items;
+    g.items_bound = (uint32_t)std::min<uint64_t>(0xFFFFFFFFu, 2ull * ntr + M->ntiles / kSwapChunk + 1);
+    return B2SR_OK;
+}
+
+}  // namespace
 
 namespace b2sr {
 // colsum[c] = number of set bits in column c, for c < nTR * T (the columns of
@@ -313,7 +493,8 @@ extern "C" {
 
 size_t spgemm_masked_workspace_bytes(const b2sr_matrix *A, const b2sr_matrix *M)
 {
-    if (!A || !b2sr::valid_tile(A->tile) || M) return 0;
+    if (!A || !b2sr::valid_tile(A->tile)) return 0;
+    if (M) return swap_bytes(A, M);
     return (size_t)2 * b2sr::n_tile_rows(A->n, A->tile) * A->tile * sizeof(uint32_t);
 }
 
@@ -332,7 +513,7 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
     if (A->n == 0 || A->ntiles == 0 || Bt->ntiles == 0 || M->ntiles == 0) return B2SR_OK;
     GemmArgs g{A->tile_rowptr, A->tile_colind, A->bits, Bt->tile_rowptr, Bt->tile_colind, Bt->bits,
                M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), 0, c,
-               0, b2sr::n_tile_rows(A->n, A->tile)};
+               0, b2sr::n_tile_rows(A->n, A->tile), nullptr, nullptr, nullptr, nullptr, 0};
     switch (A->tile) {
     case 4: return launch_masked<4, true>(g, stream);
     case 8: return launch_masked<8, true>(g, stream);
@@ -352,7 +533,8 @@ int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix
     if (!d_sum) return B2SR_EINVAL;
     if (Bt->n != A->n || Bt->tile != A->tile) return B2SR_EINVAL;
     if (M && (M->n != A->n || M->tile != A->tile)) return B2SR_EINVAL;
-    const size_t need = spgemm_masked_workspace_bytes(A, M);
+    // the unmasked sum needs its workspace; the masked one uses it when given
+    const size_t need = M ? 0 : spgemm_masked_workspace_bytes(A, M);
     if (ws_bytes < need || (need && !ws)) return B2SR_ENOSPC;
     unsigned long long *sum = (unsigned long long *)d_sum;
     if (!(flags & B2SR_ACCUMULATE)) {
@@ -372,7 +554,14 @@ int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix
     }
     GemmArgs g{A->tile_rowptr, A->tile_colind, A->bits, Bt->tile_rowptr, Bt->tile_colind, Bt->bits,
                M->tile_rowptr, M->tile_colind, M->bits, b2sr::n_tile_rows(A->n, A->tile), 0, sum,
-               0, b2sr::n_tile_rows(A->n, A->tile)};
+               0, b2sr::n_tile_rows(A->n, A->tile), nullptr, nullptr, nullptr, nullptr, 0};
+    // A and Bt the same matrix, and room for the lists: each mask tile scans the
+    // shorter of its two tile-rows
+    const bool alias = Bt->tile_rowptr == A->tile_rowptr && Bt->tile_colind == A->tile_colind &&
+                       Bt->bits == A->bits && Bt->ntiles == A->ntiles;
+    if (alias && ws && ws_bytes >= swap_bytes(A, M)) {
+        if ((rc = build_swap_lists(g, A, M, ws, stream))) return rc;
+    }
     switch (A->tile) {
     case 4: return launch_masked<4>(g, stream);
     case 8: return launch_masked<8>(g, stream);
@@ -401,7 +590,8 @@ int spgemm_masked_rows(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_m
     }
     if (A->n == 0 || A->ntiles == 0 || Bt->ntiles == 0 || M->ntiles == 0) return B2SR_OK;
     GemmArgs g{A->tile_rowptr, A->tile_colind, A->bits, Bt->tile_rowptr, Bt->tile_colind, Bt->bits,
-               M->tile_rowptr, M->tile_colind, M->bits, ntr, 0, sum, row_begin, row_end};
+               M->tile_rowptr, M->tile_colind, M->bits, ntr, 0, sum, row_begin, row_end, nullptr, nullptr, nullptr,
+               nullptr, 0};
     switch (A->tile) {
     case 4: return launch_masked<4>(g, stream);
     case 8: return launch_masked<8>(g, stream);

@@ -328,6 +328,12 @@ def test_spgemm_masked(gi, T):
     acc = b2.spgemm_masked(A, A, A)
     b2.spgemm_masked(A, A, A, accumulate=True, out=acc)
     assert int(b2.as_u64(acc)[0]) == 2 * orc.masked_sum(g, g, g)
+    # with A = Bt the binding passes the orientation workspace; without it every
+    # mask tile scans Bt's row: the same sums
+    for X in (Ld, A):
+        plain = torch.zeros(1, dtype=torch.int64, device="cuda")
+        assert b2.lib().spgemm_masked(X.view, X.view, X.view, 0, b2._ptr(plain), None, 0, b2._stream()) == 0
+        assert int(b2.as_u64(plain)[0]) == int(b2.as_u64(b2.spgemm_masked(X, X, X))[0])
 
 
 def _rows_only(c, r0, r1):
