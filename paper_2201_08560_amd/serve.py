@@ -47,6 +47,7 @@ class Query:
     finished: float | None = None
     result: object = None
     joined_step: int | None = None
+    waited_for_memory: bool = False   # admission found the budget full at least once
 
     @property
     def latency(self) -> float | None:
@@ -233,11 +234,15 @@ class Server:
             s = self.sessions.get(q.graph)
             if s is not None:
                 free = [k for k in range(64) if k not in s.slots]
-                if not free or not self._take(res):
+                if not free:
+                    return False
+                if not self._take(res):
+                    q.waited_for_memory = True
                     return False
             else:
                 nb = self.ex.session_bytes(q.graph)
                 if not self._take(nb + res):
+                    q.waited_for_memory = True
                     return False
                 s = _Session(q.graph, self.ex.open_session(q.graph), nb)
                 self.sessions[q.graph] = s
@@ -256,11 +261,13 @@ class Server:
             job = self.jobs.get(key)
             if job is not None:
                 if not self._take(res):
+                    q.waited_for_memory = True
                     return False
                 job.queries.append(q)
             else:
                 nb = self.ex.job_bytes(q.kind, q.graph)
                 if not self._take(nb + res):
+                    q.waited_for_memory = True
                     return False
                 job = _Job(key, self.ex.submit(q.kind, q.graph, q.source), nb, [q])
                 self.jobs[key] = job
@@ -298,7 +305,8 @@ class Server:
                "rejected": sum(q.status == "rejected" for q in self.done),
                "cancelled": sum(q.status == "cancelled" for q in self.done),
                "bfs_steps": self.steps_run, "ticks": self.ticks, "tick_seconds": self.tick_seconds,
-               "peak_bytes_in_use": self.peak_in_use, "budget_bytes": self.budget}
+               "peak_bytes_in_use": self.peak_in_use, "budget_bytes": self.budget,
+               "waited_for_memory": sum(q.waited_for_memory for q in self.done)}
         if lat.size:
             out["p50_ms"] = float(np.percentile(lat, 50) * 1e3)
             out["p99_ms"] = float(np.percentile(lat, 99) * 1e3)

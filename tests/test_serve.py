@@ -96,6 +96,8 @@ def test_budget_rejects_what_can_never_fit_and_delays_the_rest():
         check(q)
     assert srv.peak_in_use <= budget and srv.in_use == 0
     assert b.admitted >= a.finished and c.admitted < a.finished  # c joined a's session; b waited
+    assert b.waited_for_memory and not a.waited_for_memory and not c.waited_for_memory
+    assert srv.stats()["waited_for_memory"] == 1
     # graph 0's session (512 vertices) is larger than the whole budget: rejected
     srv2 = Server(FakeExecutor(GRAPHS), 1000, clock=FakeClock())
     q = Query(9, "bfs", 0, 0, 0.0)
