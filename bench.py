@@ -192,6 +192,9 @@ def lgc_section(w: Workload, nsrc: int = 4, iters: int = 20) -> dict:
             "sweep_ms_median": 1e3 * float(np.median(sweep)), "clusters": clusters}
 
 
+VALU_OPS_PER_S = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU operations per second, one per lane-cycle
+
+
 def tc_section(reps: int = 3) -> dict:
     out = {}
     for name, g in (("rmat18_ef16", gg.rmat(18, 16, seed=18)), ("king2048", gg.king_grid(2048, 2048))):
@@ -215,7 +218,11 @@ def tc_section(reps: int = 3) -> dict:
             # product the timing ran, its lookups are fewer
             work = b2.spgemm_masked_profile(L, L, L)
             res[f"T{T}"] = {"triangles": int(b2.as_u64(s)[0]), "ms": 1e3 * t, "edges_per_s": g.edges / t,
-                            "plain_work": work, "row_pairs_per_s": work["row_pairs"] / t}
+                            "plain_work": work, "row_pairs_per_s": work["row_pairs"] / t,
+                            # one AND + popcount per bit-row pair against the integer VALU
+                            # rate (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz): far below it, the
+                            # product is bound by the latency of its lookups and gathers
+                            "row_pairs_frac_of_valu_peak": work["row_pairs"] / t / VALU_OPS_PER_S}
             del L
         out[name] = res
     return out
