@@ -519,8 +519,8 @@ def main():
         log(f"serving pool: {len(pool_graphs)} R-MAT graphs in {time.perf_counter() - t0:.1f} s, "
             f"nnz={sum(g.nnz for g in pool_graphs)}")
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE={world}) is not supported: this build "
-              "runs the B2SR path on a single MI355X.", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE={world}) is not supported: the B2SR "
+              "path runs on a single MI355X (the design notes describe how it would shard).", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
