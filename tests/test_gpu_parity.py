@@ -328,6 +328,15 @@ def test_spgemm_masked(gi, T):
     acc = b2.spgemm_masked(A, A, A)
     b2.spgemm_masked(A, A, A, accumulate=True, out=acc)
     assert int(b2.as_u64(acc)[0]) == 2 * orc.masked_sum(g, g, g)
+    # A = Bt (oriented) under masks unrelated to A: a symmetric one and a directed one
+    if g.n <= 5000:
+        assert int(b2.as_u64(b2.spgemm_masked(A, A, Md))[0]) == orc.masked_sum(g, g, M)
+        r = gg.rng(990 + gi)
+        k = 4 * g.n
+        D = gg.directed_csr(g.n, r.integers(0, g.n, k), r.integers(0, g.n, k))
+        Dd = b2.B2SR.from_csr(D.rowptr, D.colind, D.n, T)
+        assert int(b2.as_u64(b2.spgemm_masked(A, A, Dd))[0]) == orc.masked_sum(g, g, D)
+        assert int(b2.as_u64(b2.spgemm_masked(Ld, Ld, Dd))[0]) == orc.masked_sum(L, L, D)
     # with A = Bt the binding passes the orientation workspace; without it every
     # mask tile scans Bt's row: the same sums
     for X in (Ld, A):
