@@ -237,10 +237,11 @@ def batched_section(graphs, reps: int = 3) -> dict:
     from paper_2201_08560_amd.batch import GraphBatch
     count = len(graphs)
     t0 = time.perf_counter()
-    tiles = [autotune.choose_tile(g, nsample=256)[0] for g in graphs]
+    tiles = [autotune.choose_tile(g, nsample=256)[0] for g in graphs]   # per-graph launches
+    batch_tile = autotune.choose_batch_tile(graphs)[0]                  # the batched forms
     tune_s = time.perf_counter() - t0
     sources = [gg.sample_sources(g, 64, seed=1000 + i) for i, g in enumerate(graphs)]
-    B = GraphBatch(graphs, tiles)
+    B = GraphBatch(graphs, [batch_tile] * count)
     B.set_sources(sources)
     singles = [b2.B2SR.from_graph(g, t) for g, t in zip(graphs, tiles)]
     ws_single = torch.empty(max(b2.b2sr_algo_workspace_bytes(A, b2.ALGO_MSBFS) for A in singles),
@@ -281,7 +282,8 @@ def batched_section(graphs, reps: int = 3) -> dict:
     hist = {str(T): tiles.count(T) for T in (4, 8, 16, 32)}
     best = min((k for k in res if k != "per_graph"), key=lambda k: res[k]["ms"])
     return {"graphs": count, "n_total": B.n, "nnz_total": int(sum(g.nnz for g in graphs)),
-            "sources_per_graph": 64, "tile_histogram": hist, "autotune_s": tune_s, "modes": res,
+            "sources_per_graph": 64, "tile_histogram": hist, "batch_tile": batch_tile, "autotune_s": tune_s,
+            "modes": res,
             "identical_results": bool(same),
             "speedup_best_batched_vs_per_graph": res["per_graph"]["ms"] / res[best]["ms"]}
 

@@ -69,6 +69,21 @@ def choose_tile(g, value_bytes: int = 8, beta: float = 0.25, nsample: int = 1024
     return best, {"sampling_estimate": prof, "ntiles": tiles, "cost": cost}
 
 
+def choose_batch_tile(graphs, value_bytes: int = 8, beta: float = 0.25) -> tuple[int, dict]:
+    """One tile width for a whole batch: the T with the least modelled product
+    cost summed over the graphs.  A batch holds one block-diagonal matrix per
+    tile width present, each a product launch per level, and on the benchmark
+    batch a separate group for a few small graphs whose own best width differs
+    by a few percent costs more than it saves."""
+    total = {T: 0.0 for T in TILES}
+    for g in graphs:
+        cost = product_cost(exact_tiles(g.rowptr, g.colind, g.n), value_bytes, beta)
+        for T in TILES:
+            total[T] += cost[T]
+    best = min(total, key=lambda k: (total[k], k))
+    return best, {"cost": total}
+
+
 def _load_graph(spec: str):
     """A graph from a generator spec (rmat:SCALE:EF[:SEED], rmat_dir:SCALE:EF[:SEED],
     er:N:M[:SEED], king:R:C) or an .npz file holding n, rowptr and colind."""

@@ -229,6 +229,9 @@ __device__ __forceinline__ uint32_t grid_barrier(uint32_t *flags, const uint32_t
 #endif
 constexpr int persistent_waves(unsigned tmask) { return (tmask & 6u) ? B2SR_PW_WIDE : B2SR_PW_SMALL; }
 
+#ifndef B2SR_PERSIST_MAX_PER_CU
+#define B2SR_PERSIST_MAX_PER_CU 2
+#endif
 #ifndef B2SR_PERSIST_THREADS
 #define B2SR_PERSIST_THREADS 512  // threads per block of the persistent kernel
 #endif
@@ -381,9 +384,6 @@ const void *persistent_kernel(unsigned tmask)
         (const void *)batch_persistent_kernel<13>, (const void *)batch_persistent_kernel<14>,
         (const void *)batch_persistent_kernel<15>,
     };
-#ifdef B2SR_PERSIST_FORCE_MASK
-    tmask = B2SR_PERSIST_FORCE_MASK;
-#endif
     return table[tmask & 15u];
 }
 
@@ -398,9 +398,9 @@ int persistent_grid(const void *kernel, unsigned *grid)
                              "hipOccupancyMaxActiveBlocksPerMultiprocessor"))
         return rc;
     if (per_cu < 1 || !prop.cooperativeLaunch) return B2SR_ENOTSUP;
-#ifdef B2SR_PERSIST_MAX_PER_CU
+    // at most 2 blocks of 512 threads per CU: more blocks meeting at every
+    // barrier measured slower than the extra waves gain
     if (per_cu > B2SR_PERSIST_MAX_PER_CU) per_cu = B2SR_PERSIST_MAX_PER_CU;
-#endif
     *grid = (unsigned)per_cu * (unsigned)prop.multiProcessorCount;
     return B2SR_OK;
 }

@@ -86,23 +86,34 @@ def test_triangle_count_rmat18(T):
 
 
 def test_batched_full_config():
-    """The 256-graph batch (autotuned tile widths, 64 sources per graph): sampled
-    graphs' levels against the oracle; padding vertices stay unreached."""
+    """The 256-graph batch, 64 sources per graph, as the benchmark times it (one
+    tile width for the batch, per-level and persistent launches) and with each
+    graph's own autotuned width (several groups): sampled graphs' levels against
+    the oracle; padding vertices stay unreached; both layouts give the same levels."""
     from paper_2201_08560_amd import autotune
     from paper_2201_08560_amd.batch import GraphBatch
     graphs = gg.chung_lu_batch(256, 2.1, seed=1000, workers=1)  # no fork of a process using the GPU
-    tiles = [autotune.choose_tile(g, nsample=256)[0] for g in graphs]
-    B = GraphBatch(graphs, tiles)
-    B.set_sources([gg.sample_sources(g, 64, seed=1000 + i) for i, g in enumerate(graphs)])
-    lv, _ = B.run(b2.BATCH_LEVELS)
+    sources = [gg.sample_sources(g, 64, seed=1000 + i) for i, g in enumerate(graphs)]
     sizes = np.array([g.n for g in graphs])
     sample = sorted({int(np.argmax(sizes)), int(np.argmin(sizes))} | set(gg.rng(9).choice(256, 6, replace=False).tolist()))
-    for i in sample:
-        print(f"batch graph {i} n={graphs[i].n} T={tiles[i]}", flush=True)
-        assert np.array_equal(B.levels_of_host(lv, i), orc.bfs_multi(graphs[i], B.sources[i]))
-    host = b2.as_u32(lv)
-    for i, g in enumerate(graphs):
-        assert np.all(host[int(B.offsets[i]) + g.n:int(B.offsets[i + 1])] == b2.UNREACHED)
+    per_graph = [autotune.choose_tile(g, nsample=256)[0] for g in graphs]
+    batch_tile = autotune.choose_batch_tile(graphs)[0]
+    ref = None  # (batch, levels) of the first run: every later run must agree graph by graph
+    for tiles in ([batch_tile] * len(graphs), per_graph):
+        B = GraphBatch(graphs, tiles)
+        B.set_sources(sources)
+        for mode in (b2.BATCH_LEVELS, b2.BATCH_PERSISTENT):
+            lv, _ = B.run(mode)
+            for i in sample:
+                print(f"batch graph {i} n={graphs[i].n} T={tiles[i]} mode={mode}", flush=True)
+                assert np.array_equal(B.levels_of_host(lv, i), orc.bfs_multi(graphs[i], B.sources[i]))
+            pad = torch.cat([lv[int(B.offsets[i]) + g.n:int(B.offsets[i + 1])].reshape(-1)
+                             for i, g in enumerate(graphs)])
+            assert bool((pad == -1).all())  # 0xFFFFFFFF: unreached
+            if ref is None:
+                ref = (B, lv)
+            else:
+                assert all(torch.equal(B.levels_of(lv, i), ref[0].levels_of(ref[1], i)) for i in range(len(graphs)))
 
 
 def test_local_clustering_full_size(big):
