@@ -115,3 +115,17 @@ def test_autotune_exact_counts_match_oracle():
         assert T in (4, 8, 16, 32)
         for k in (4, 8, 16, 32):
             assert rep["ntiles"][k] == orc.b2sr_count_tiles(g, k)
+
+
+def test_batch_tile_is_the_least_summed_cost():
+    """One width for a batch: the argmin over T of the per-graph modelled costs
+    summed (each graph's cost table from choose_tile), ties to the smaller T."""
+    graphs = [gg.rmat(10, 8, seed=3), gg.king_grid(40, 50), gg.complete(40), gg.er_gnm(3000, 9000, seed=5)]
+    total = {T: 0.0 for T in autotune.TILES}
+    for g in graphs:
+        cost = autotune.choose_tile(g, nsample=128)[1]["cost"]
+        for T in total:
+            total[T] += cost[T]
+    T, rep = autotune.choose_batch_tile(graphs)
+    assert rep["cost"] == pytest.approx(total)
+    assert T == min(total, key=lambda k: (total[k], k))
