@@ -193,7 +193,9 @@ __device__ __forceinline__ uint32_t grid_barrier(uint32_t *flags, const uint32_t
             atomicAdd(gen, 1u);
         } else {
             uint32_t spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            // relaxed polls: the fence after the wait is the acquire that pairs with
+            // the last arriver's fence before it advanced the generation
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 // a long sleep between polls: a thousand waiting blocks polling
                 // often crowd the arrivals on the counter's memory channel
                 if (spins < B2SR_BARRIER_FAST_POLLS) __builtin_amdgcn_s_sleep(1);
