@@ -109,8 +109,9 @@ def set_num_threads(t: int) -> None:
 # ---- B2SR from its definition -------------------------------------------------
 
 def row_bytes(T: int) -> int:
-    """Bytes per bit-row (Table II; T=4 uses half of an unsigned char)."""
-    return {4: 1, 8: 1, 16: 2, 32: 4}[T]
+    """Bytes per bit-row (Table II; T=4 uses half of an unsigned char; T=64
+    the unsigned long long packing type of Sec. III-A)."""
+    return {4: 1, 8: 1, 16: 2, 32: 4, 64: 8}[T]
 
 
 def b2sr_count_tiles(g, T: int, lower_only: bool = False) -> int:
@@ -119,12 +120,12 @@ def b2sr_count_tiles(g, T: int, lower_only: bool = False) -> int:
 
 def b2sr_build(g, T: int, lower_only: bool = False):
     """Returns (tile_rowptr u32[nTR+1], tile_colind u32[nT], bits) with bits as
-    u8/u8/u16/u32 words for T = 4/8/16/32, T words per tile."""
+    u8/u8/u16/u32/u64 words for T = 4/8/16/32/64, T words per tile."""
     ntr = (g.n + T - 1) // T
     nt = b2sr_count_tiles(g, T, lower_only)
     trp = np.zeros(ntr + 1, dtype=np.uint32)
     tci = np.zeros(max(nt, 1), dtype=np.uint32)
-    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[row_bytes(T)]
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}[row_bytes(T)]
     bits = np.zeros(max(nt * T, 1), dtype=dt)
     rc = lib().orc_b2sr_build(g.n, g.rowptr, g.colind, T, int(lower_only), trp, tci, _ptr(bits))
     if rc != 0:

@@ -55,10 +55,11 @@ static int cmp_u32(const void *a, const void *b)
 }
 
 /* Bytes of one bit-row for tile dimension T (Table II; T=4 uses the low nibble
- * of an unsigned char). */
+ * of an unsigned char; T=64 uses the unsigned long long bit-packing type that
+ * Sec. III-A lists for BitTiles). */
 static size_t row_bytes(uint32_t T)
 {
-    return T == 32 ? 4 : (T == 16 ? 2 : 1);
+    return T == 64 ? 8 : T == 32 ? 4 : (T == 16 ? 2 : 1);
 }
 
 /*
@@ -116,13 +117,14 @@ uint64_t orc_b2sr_count_tiles(uint32_t n, const uint32_t *rowptr, const uint32_t
  * the same order.  Bit-row r of a tile is the word at index tile*T + r; bit c
  * of it (least significant first: "bits are indexed from right to left",
  * Sec. IV) is A[I*T + r][J*T + c].  Word width per Table II: 1 byte for T=4
- * (low nibble) and T=8, 2 bytes for T=16, 4 bytes for T=32.
+ * (low nibble) and T=8, 2 bytes for T=16, 4 bytes for T=32; 8 bytes for T=64
+ * (the 64-bit packing type of Sec. III-A, a tile size Sec. VI-B also names).
  * bits must be zero-filled by the caller.
  */
 int orc_b2sr_build(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, uint32_t T,
                    int lower_only, uint32_t *tile_rowptr, uint32_t *tile_colind, void *bits)
 {
-    if (T != 4 && T != 8 && T != 16 && T != 32) return -1;
+    if (T != 4 && T != 8 && T != 16 && T != 32 && T != 64) return -1;
     uint32_t ntr = (n + T - 1) / T;
     size_t rb = row_bytes(T);
     uint32_t maxseg = 0;
@@ -155,7 +157,8 @@ int orc_b2sr_build(uint32_t n, const uint32_t *rowptr, const uint32_t *colind, u
             size_t word = (size_t)lo * T + r;
             if (rb == 1) b[word] |= (uint8_t)(1u << c);
             else if (rb == 2) ((uint16_t *)b)[word] |= (uint16_t)(1u << c);
-            else ((uint32_t *)b)[word] |= (1u << c);
+            else if (rb == 4) ((uint32_t *)b)[word] |= (1u << c);
+            else ((uint64_t *)b)[word] |= ((uint64_t)1 << c);
         }
     }
     return 0;

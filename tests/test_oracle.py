@@ -14,6 +14,7 @@ import oracle as orc
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 TILES = (4, 8, 16, 32)
+TILES64 = TILES + (64,)  # B2SR-64: the 64-bit packing type of Sec. III-A
 UNR = orc.UNREACHED
 
 
@@ -47,9 +48,14 @@ def decode_b2sr(n, T, trp, tci, bits):
     return a[:n, :n]
 
 
-@pytest.mark.parametrize("T", TILES)
+# graphs spanning several 64-row tile-rows, with a ragged last one
+SMALL = [gg.random_graph_tiny(int(gg.rng(20_000 + s).integers(65, 300)), p, 300 + s)
+         for s, p in enumerate([0.01, 0.03, 0.1, 0.3, 0.6, 0.02, 0.05, 0.2])]
+
+
+@pytest.mark.parametrize("T", TILES64)
 def test_b2sr_build_brute_force(T):
-    for g in TINY[:40]:
+    for g in TINY[:40] + SMALL:
         for lower in (False, True):
             trp, tci, bits = orc.b2sr_build(g, T, lower_only=lower)
             dense = g.dense()
@@ -87,6 +93,35 @@ def test_mycielskian12_storage_matches_paper():
         assert round(kib, 2) == pytest.approx(gold["b2sr_KB"][str(T)], abs=1e-9), T
 
 
+def test_b2sr64_closed_forms():
+    """B2SR-64 (no printed number pins T = 64): tile words written out by hand
+    for graphs whose bit patterns are known, and the byte formula of the three
+    arrays (4-byte indices, 8-byte bit-rows)."""
+    full = (1 << 64) - 1
+    # K_64: one tile, bit-row r is every column but the diagonal
+    trp, tci, bits = orc.b2sr_build(gg.complete(64), 64)
+    assert trp.tolist() == [0, 1] and tci.tolist() == [0]
+    assert bits.dtype == np.uint64 and [int(w) for w in bits] == [full ^ (1 << r) for r in range(64)]
+    # K_130: 3 x 3 tiles; the last tile-row and column hold 2 vertices
+    g = gg.complete(130)
+    trp, tci, bits = orc.b2sr_build(g, 64)
+    assert trp.tolist() == [0, 3, 6, 9] and tci.tolist() == [0, 1, 2] * 3
+    w = [int(v) for v in bits]
+    assert w[2 * 64 + 5] == 0b11 and w[8 * 64 + 1] == 0b01 and w[8 * 64 + 2] == 0  # padding rows are zero
+    assert w[4 * 64 + 7] == full ^ (1 << 7) and w[1 * 64 + 0] == full
+    assert orc.b2sr_bytes(9, 130, 64) == 4 * 4 + 4 * 9 + 9 * 64 * 8
+    # path on 200 vertices: 4 diagonal tiles and 3 pairs of corner tiles
+    trp, tci, bits = orc.b2sr_build(gg.path(200), 64)
+    assert trp.tolist() == [0, 2, 5, 8, 10] and tci.tolist() == [0, 1, 0, 1, 2, 1, 2, 3, 2, 3]
+    w = [int(v) for v in bits]
+    assert w[0 * 64 + 0] == 0b10 and w[0 * 64 + 5] == (1 << 4) | (1 << 6) and w[0 * 64 + 63] == 1 << 62
+    assert w[1 * 64 + 63] == 1 and sum(w[64:128]) == 1  # (63, 64) in tile (0, 1)
+    assert w[2 * 64 + 0] == 1 << 63  # (64, 63) in tile (1, 0)
+    # the lower triangle of K_64 keeps bits below the diagonal only
+    _, _, bits = orc.b2sr_build(gg.complete(64), 64, lower_only=True)
+    assert [int(v) for v in bits] == [(1 << r) - 1 for r in range(64)]
+
+
 def test_mycielski_edge_recurrence_and_triangle_free():
     e, n = 1, 2
     for k in range(2, 11):
@@ -103,7 +138,7 @@ def test_mycielski_edge_recurrence_and_triangle_free():
 def test_tile_count_against_numpy_pairs_medium():
     g = gg.er_gnm(3000, 9000, seed=5)
     rows = np.repeat(np.arange(g.n), g.degrees())
-    for T in TILES:
+    for T in TILES64:
         key = (rows // T) * ((g.n + T - 1) // T) + g.colind // T
         assert orc.b2sr_count_tiles(g, T) == np.unique(key).size
 
