@@ -288,6 +288,15 @@ def star(n: int) -> Csr:
     return canonical_csr(n, np.zeros_like(i), i, name=f"star{n}")
 
 
+def wheel(n: int) -> Csr:
+    """A cycle on 0..n-2 (the rim) and vertex n-1 (the hub) joined to all of
+    them; n - 1 triangles when the rim has at least 4 vertices."""
+    i = np.arange(n - 1, dtype=np.int64)
+    src = np.concatenate([i, i])
+    dst = np.concatenate([(i + 1) % (n - 1), np.full(n - 1, n - 1, dtype=np.int64)])
+    return canonical_csr(n, src, dst, name=f"wheel{n}")
+
+
 def complete(n: int) -> Csr:
     i, j = np.triu_indices(n, 1)
     return canonical_csr(n, i, j, name=f"K{n}")

@@ -34,7 +34,7 @@
  *
  * Matrix layout (the B2SR format)
  * -------------------------------
- * An n x n binary matrix A is cut into T x T tiles, T in {4, 8, 16, 32};
+ * An n x n binary matrix A is cut into T x T tiles, T in {4, 8, 16, 32, 64};
  * nTR = ceil(n / T) tile-rows.  Only non-empty tiles are stored:
  *   tile_rowptr[nTR + 1]  exclusive prefix count of non-empty tiles per
  *                         tile-row (tile_rowptr[0] = 0; tiles of tile-row I
@@ -46,7 +46,10 @@
  *                         significant bit first) is A[I*T + r][J*T + c].
  *                         Word type (Table II): uint8_t for T = 4 (low nibble
  *                         used) and T = 8, uint16_t for T = 16, uint32_t for
- *                         T = 32.  Bits for rows or columns >= n are zero.
+ *                         T = 32; uint64_t for T = 64 (the 64-bit packing
+ *                         type Sec. III-A lists).  Bits for rows or columns
+ *                         >= n are zero.  bits must be 16-byte aligned for
+ *                         T >= 16, 8-byte for T = 8, 4-byte for T = 4.
  * Indices are 32-bit: n, nnz and ntiles must be < 2^32.
  *
  * Vector layout
@@ -106,7 +109,7 @@ extern "C" {
 /* A non-owning view of a B2SR matrix in device memory (layout above). */
 typedef struct b2sr_matrix {
     uint32_t n;      /* rows = columns                         */
-    uint32_t tile;   /* T: 4, 8, 16 or 32                      */
+    uint32_t tile;   /* T: 4, 8, 16, 32 or 64                  */
     uint32_t ntiles; /* number of non-empty tiles              */
     uint32_t reserved; /* must be 0                            */
     const uint32_t *tile_rowptr; /* device, nTR + 1 entries    */
@@ -132,7 +135,7 @@ int b2sr_version(void);
  *   Columns inside a row may be unsorted and may repeat.  Every column index
  *   must be < n (not checked on the device).
  *   flags: 0 or B2SR_BUILD_LOWER.
- *   Errors: EINVAL (tile not in {4,8,16,32}, NULL pointer with n > 0, unknown
+ *   Errors: EINVAL (tile not in {4,8,16,32,64}, NULL pointer with n > 0, unknown
  *   flag), ERANGE (nnz >= 2^32), EHIP.
  */
 int b2sr_count_tiles(uint32_t n, uint64_t nnz, const uint32_t *rowptr, const uint32_t *colind,
@@ -317,9 +320,10 @@ int b2sr_bfs(const b2sr_matrix *A, uint32_t src, uint32_t *levels, void *ws, siz
 int b2sr_msbfs(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32_t *levels,
                void *ws, size_t ws_bytes, uint32_t *iters, hipStream_t stream);
 
-/* SSSP with unit edge weights (Sec. V): tropical min-plus over float with the
- * diagonal as zero, iterated to a fixpoint.  dist (uint32_t[n]) holds hop
- * distances, unreachable = 0xFFFFFFFF. */
+/* SSSP with unit edge weights (Sec. V): tropical min-plus over uint32 with
+ * saturating addition (B2SR_MIN_PLUS_U32, edge weight 1) and the diagonal as
+ * zero, iterated to a fixpoint; exact for every n.  dist (uint32_t[n]) holds
+ * hop distances, unreachable = 0xFFFFFFFF. */
 int b2sr_sssp(const b2sr_matrix *A, uint32_t src, uint32_t *dist, void *ws, size_t ws_bytes,
               uint32_t *iters, hipStream_t stream);
 
@@ -443,15 +447,26 @@ int b2sr_msbfs_batch(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, ui
  * after the BFS has finished return at once, and plan_launch replays the second
  * graph until the device reports the BFS finished (it synchronises `stream`).
  * mode B2SR_BATCH_PERSISTENT: one graph of initialisation, seeding and the
- * persistent kernel; plan_launch synchronises only when iters is not NULL.
+ * persistent kernel, whose kernel node is cooperative (the runtime checks at
+ * each replay that the grid can be co-resident; plan_create returns
+ * B2SR_ENOTSUP when the runtime refuses that attribute).  plan_launch
+ * synchronises only when iters is not NULL, and then reports a grid barrier
+ * that timed out (B2SR_EHIP).  Without iters the time-out flag stays set in the
+ * plan's workspace, where it makes every later replay stop at once, until
+ * b2sr_msbfs_batch_plan_status reads it: that call synchronises `stream`,
+ * writes the levels run of the last replay to *iters (nullable) and returns
+ * B2SR_EHIP, clearing the flag, when a barrier timed out since the last
+ * status read.  The plan's workspace keeps that state between launches.
  * The plan keeps the pointers it was created with: rewrite the seed arrays in
- * device memory between launches to run other sources. */
+ * device memory between launches to run other sources.  plan_create clears
+ * the time-out flag with a synchronous hipMemset. */
 typedef struct b2sr_msbfs_plan_s *b2sr_msbfs_plan;
 int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups,
                                  uint32_t nseeds, const uint32_t *seed_vertex,
                                  const uint32_t *seed_bit, uint32_t *levels, unsigned mode,
                                  void *ws, size_t ws_bytes, b2sr_msbfs_plan *plan);
 int b2sr_msbfs_batch_plan_launch(b2sr_msbfs_plan plan, uint32_t *iters, hipStream_t stream);
+int b2sr_msbfs_batch_plan_status(b2sr_msbfs_plan plan, uint32_t *iters, hipStream_t stream);
 int b2sr_msbfs_batch_plan_destroy(b2sr_msbfs_plan plan);
 
 /* ---- serving: continuous multi-source BFS sessions ------------------------

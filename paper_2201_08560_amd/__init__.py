@@ -104,6 +104,7 @@ _SIGS = {
     "b2sr_msbfs_batch_plan_create": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, ctypes.c_uint, _P, _SZ,
                                           ctypes.POINTER(_P)]),
     "b2sr_msbfs_batch_plan_launch": (_I, [_P, ctypes.POINTER(_U32), _P]),
+    "b2sr_msbfs_batch_plan_status": (_I, [_P, ctypes.POINTER(_U32), _P]),
     "b2sr_msbfs_batch_plan_destroy": (_I, [_P]),
     "b2sr_bfs_session_bytes": (_SZ, [_U32]),
     "b2sr_bfs_session_create": (_I, [_MP, _P, _SZ, _P, ctypes.POINTER(_P)]),
@@ -174,7 +175,7 @@ def _words(n: int) -> int:
     return (n + 31) // 32
 
 
-_ROW_BYTES = {4: 1, 8: 1, 16: 2, 32: 4}
+_ROW_BYTES = {4: 1, 8: 1, 16: 2, 32: 4, 64: 8}
 
 
 class B2SR:
@@ -221,11 +222,11 @@ class B2SR:
         return cls.from_csr(g.rowptr, g.colind, g.n, tile, lower, transpose)
 
     def to_host(self):
-        """(tile_rowptr u32, tile_colind u32, bits as u8/u8/u16/u32 words)."""
+        """(tile_rowptr u32, tile_colind u32, bits as u8/u8/u16/u32/u64 words)."""
         trp = as_u32(self.tile_rowptr)
         tci = as_u32(self.tile_colind)[: self.ntiles]
         raw = self.bits.cpu().numpy()[: self.ntiles * self.tile * _ROW_BYTES[self.tile]]
-        dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[_ROW_BYTES[self.tile]]
+        dt = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}[_ROW_BYTES[self.tile]]
         return trp, tci, raw.view(dt)
 
 
@@ -540,11 +541,23 @@ class MsbfsPlan:
                                                   _ptr(self.ws), need, ctypes.byref(h)), "b2sr_msbfs_batch_plan_create")
         self._h = h
 
-    def launch(self, want_iters: bool = False):
+    def launch(self, want_iters: bool = False, check: bool = True):
+        """Replays the plan.  With ``check`` (the default) the call waits for the
+        replay and raises if a grid barrier timed out; ``check=False`` only
+        enqueues it (call ``status`` later)."""
         it = _U32(0)
-        _check(lib().b2sr_msbfs_batch_plan_launch(self._h, ctypes.byref(it) if want_iters else None, _stream()),
+        sync = want_iters or check
+        _check(lib().b2sr_msbfs_batch_plan_launch(self._h, ctypes.byref(it) if sync else None, _stream()),
                "b2sr_msbfs_batch_plan_launch")
         return it.value if want_iters else None
+
+    def status(self) -> int:
+        """Waits for the enqueued replays; raises if a barrier timed out since the
+        last status read; returns the levels run by the last replay."""
+        it = _U32(0)
+        _check(lib().b2sr_msbfs_batch_plan_status(self._h, ctypes.byref(it), _stream()),
+               "b2sr_msbfs_batch_plan_status")
+        return it.value
 
     def close(self):
         if self._h is not None and _lib is not None:

@@ -1,7 +1,7 @@
 """Tile-width choice per graph.
 
 Step 1, a sampling profile (Sec. III-C, Algorithm 1): for N sampled rows and
-each k in {4, 8, 16, 32}, count the distinct k-wide column chunks the row
+each k in {4, 8, 16, 32, 64}, count the distinct k-wide column chunks the row
 touches (its bit-rows in B2SR-k).  Algorithm 1 as printed is garbled (it
 indexes the counter with a nonzero's position and divides a count by itself);
 the reading used here: for a sampled row with e nonzeros and c_k distinct
@@ -24,8 +24,8 @@ import torch
 
 from . import BUILD_LOWER, _i32, b2sr_count_tiles  # noqa: F401
 
-TILES = (4, 8, 16, 32)
-ROW_BYTES = {4: 1, 8: 1, 16: 2, 32: 4}
+TILES = (4, 8, 16, 32, 64)
+ROW_BYTES = {4: 1, 8: 1, 16: 2, 32: 4, 64: 8}
 
 
 def sampling_profile(rowptr: np.ndarray, colind: np.ndarray, n: int, nsample: int = 1024, seed: int = 0) -> dict:

@@ -202,11 +202,11 @@ __global__ void msbfs_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, 
 }
 
 // ---------------------------------------------------------------- SSSP / CC
-__global__ void sssp_init_kernel(uint32_t n, uint32_t src, float *d, uint32_t *act, uint32_t *flags)
+__global__ void sssp_init_kernel(uint32_t n, uint32_t src, uint32_t *d, uint32_t *act, uint32_t *flags)
 {
     const uint32_t nw = (n + 31) / 32;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        d[i] = i == src ? 0.0f : __builtin_huge_valf();
+        d[i] = i == src ? 0u : kUnreached;
         if (i < nw) act[i] = i == src / 32 ? 1u << (src % 32) : 0u;
     }
     if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
@@ -229,14 +229,6 @@ __global__ void changed_kernel(uint32_t n, const V *a, const V *b, uint32_t *act
     }
     if (__syncthreads_or(diff) && threadIdx.x == 0) atomicOr(flag_now, 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
-}
-
-__global__ void dist_to_u32_kernel(uint32_t n, const float *d, uint32_t *out)
-{
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const float v = d[i];
-        out[i] = v == __builtin_huge_valf() ? kUnreached : (uint32_t)v;
-    }
 }
 
 __global__ void iota_kernel(uint32_t n, uint32_t *x, uint32_t *flags)
@@ -363,7 +355,7 @@ struct Layout {
     uint32_t *srcs = nullptr;
     // SSSP / CC / PR
     float *f0 = nullptr, *f1 = nullptr, *f2 = nullptr;
-    uint32_t *u0 = nullptr, *ones = nullptr, *act = nullptr;
+    uint32_t *u0 = nullptr, *u1 = nullptr, *ones = nullptr, *act = nullptr;
     uint64_t *alive = nullptr;
     void *spmv_ws = nullptr;
     size_t spmv_ws_bytes = 0;
@@ -390,8 +382,8 @@ Layout carve(const b2sr_matrix *A, int algo, void *ws)
         L.act = c.take<uint32_t>(nw * 4);
         break;
     case B2SR_ALGO_SSSP:
-        L.f0 = c.take<float>(n * 4);
-        L.f1 = c.take<float>(n * 4);
+        L.u0 = c.take<uint32_t>(n * 4);
+        L.u1 = c.take<uint32_t>(n * 4);
         L.act = c.take<uint32_t>(nw * 4);
         break;
     case B2SR_ALGO_CC:
@@ -526,27 +518,28 @@ int b2sr_sssp(const b2sr_matrix *A, uint32_t src, uint32_t *dist, void *ws, size
     if (rc) return rc;
     if (!dist || src >= A->n) return B2SR_EINVAL;
     const uint32_t n = A->n;
-    sssp_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, L.f0, L.act, L.flags);
+    sssp_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, L.u0, L.act, L.flags);
     if ((rc = b2sr::check_launch("sssp_init_kernel"))) return rc;
-    float *cur = L.f0, *nxt = L.f1;
+    // hop counts in uint32 with saturating addition: exact for every n
+    uint32_t *cur = L.u0, *nxt = L.u1;
     uint32_t it = 0;
     for (;;) {
         ++it;
         // only distances that changed last iteration can improve a neighbour; the
         // others were folded in when they changed (the SELF term keeps x_i)
-        if ((rc = spmv_bin_full(A, B2SR_MIN_PLUS_F32, cur, nullptr, L.act, nullptr, B2SR_SELF, 1.0, 0.0, nxt, nullptr,
+        if ((rc = spmv_bin_full(A, B2SR_MIN_PLUS_U32, cur, nullptr, L.act, nullptr, B2SR_SELF, 1.0, 0.0, nxt, nullptr,
                                 0, stream)))
             return rc;
         uint32_t *fnow = L.flags + (it & 1), *fnext = L.flags + ((it + 1) & 1);
-        changed_kernel<float><<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, L.act, fnow, fnext);
+        changed_kernel<uint32_t><<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, L.act, fnow, fnext);
         if ((rc = b2sr::check_launch("changed_kernel"))) return rc;
         uint32_t any = 0;
         if ((rc = read_flag(fnow, &any, stream))) return rc;
         std::swap(cur, nxt);
         if (!any) break;
     }
-    dist_to_u32_kernel<<<vgrid(n), 256, 0, stream>>>(n, cur, dist);
-    if ((rc = b2sr::check_launch("dist_to_u32_kernel"))) return rc;
+    copy_u32_kernel<<<vgrid(n), 256, 0, stream>>>(n, cur, dist);
+    if ((rc = b2sr::check_launch("copy_u32_kernel"))) return rc;
     if (iters) *iters = it;
     return B2SR_OK;
 }

@@ -23,6 +23,7 @@
 //   * a plan: the persistent launch (with its initialisation) instantiated as a
 //     hipGraph once and replayed.
 #include <new>
+#include <utility>
 
 #include "spmv_core.h"
 
@@ -55,7 +56,8 @@ struct BatchArgs {
                        // [6]: BFS finished (per-level kernels return at once)
     const uint32_t *seed_vertex, *seed_bit;
     uint32_t nseeds;
-    unsigned tmask;  // tile widths present: bit 0 for 4, 1 for 8, 2 for 16, 3 for 32
+    uint32_t sticky_timeout;  // plans: initialisation leaves flags[5] for the status call to read
+    unsigned tmask;  // tile widths present: bit 0 for 4, 1 for 8, 2 for 16, 3 for 32, 4 for 64
 };
 
 __global__ void batch_init_kernel(BatchArgs b)
@@ -69,7 +71,7 @@ __global__ void batch_init_kernel(BatchArgs b)
         b.Y[i] = 0;
     }
     for (uint64_t w = tid; w < (b.n + 31) / 32; w += stride) b.act[w] = 0;
-    if (tid < 8) b.flags[tid] = 0;
+    if (tid < 8 && !(tid == 5 && b.sticky_timeout)) b.flags[tid] = 0;
     if (tid == 8) b.flags[kBarrierCount] = 0;
 }
 
@@ -220,9 +222,9 @@ __device__ __forceinline__ uint32_t grid_barrier(uint32_t *flags, const uint32_t
 // the update, and the update from the convergence test.  All threads read the
 // same flags after the barrier, so they leave the level loop together; the loop
 // is also bounded by max_levels and left at once if a barrier timed out.
-// TMASK holds the tile widths present (bit 0: 4, 1: 8, 2: 16, 3: 32): only their
-// product paths are compiled in, so the registers, and with them the waves per
-// SIMD, are those of the widest path present rather than of all four.
+// TMASK holds the tile widths present (bit 0: 4, 1: 8, 2: 16, 3: 32, 4: 64):
+// only their product paths are compiled in, so the registers, and with them the
+// waves per SIMD, are those of the widest path present rather than of all five.
 #ifndef B2SR_PW_SMALL
 #define B2SR_PW_SMALL 1  // waves per SIMD asked for masks without T = 8 and 16
 #endif
@@ -263,7 +265,10 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
                 if (g.tile == 16) { run_chunk<16>(g, c, xs); continue; }
             }
             if constexpr ((TMASK & 8u) != 0) {
-                if (g.tile == 32) run_chunk<32>(g, c, xs);
+                if (g.tile == 32) { run_chunk<32>(g, c, xs); continue; }
+            }
+            if constexpr ((TMASK & 16u) != 0) {
+                if (g.tile == 64) run_chunk<64>(g, c, xs);
             }
         }
         if (grid_barrier(b.flags, nullptr) & 1u) break;
@@ -342,13 +347,14 @@ int make_args(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t 
         g.p.ntr = b2sr::n_tile_rows(n, A->tile);
         g.p.ntiles = A->ntiles;
         g.p.chunk = A->tile == 4 ? or64_chunk<4>(A->ntiles) : A->tile == 8 ? or64_chunk<8>(A->ntiles)
-                  : A->tile == 16 ? or64_chunk<16>(A->ntiles) : or64_chunk<32>(A->ntiles);
+                  : A->tile == 16 ? or64_chunk<16>(A->ntiles) : A->tile == 32 ? or64_chunk<32>(A->ntiles)
+                  : or64_chunk<64>(A->ntiles);
         g.p.x = L.F;
         g.p.xact = L.act;  // only non-zero frontier words take part
         g.p.y = L.Y;
         g.p.flags = B2SR_ACCUMULATE;
         g.tile = A->tile;
-        b.tmask |= A->tile == 4 ? 1u : A->tile == 8 ? 2u : A->tile == 16 ? 4u : 8u;
+        b.tmask |= A->tile == 4 ? 1u : A->tile == 8 ? 2u : A->tile == 16 ? 4u : A->tile == 32 ? 8u : 16u;
         g.item0 = (uint32_t)items;
         g.nchunks = (uint32_t)(((uint64_t)A->ntiles + g.p.chunk - 1) / g.p.chunk);
         items += g.nchunks;
@@ -373,21 +379,13 @@ int launch_init(const BatchArgs &b, hipStream_t stream)
 }
 
 // The persistent kernel compiled for exactly the tile widths present.
-const void *persistent_kernel(unsigned tmask)
+template <unsigned... M> const void *persistent_pick(unsigned tmask, std::integer_sequence<unsigned, M...>)
 {
-    static const void *const table[16] = {
-        nullptr,
-        (const void *)batch_persistent_kernel<1>,  (const void *)batch_persistent_kernel<2>,
-        (const void *)batch_persistent_kernel<3>,  (const void *)batch_persistent_kernel<4>,
-        (const void *)batch_persistent_kernel<5>,  (const void *)batch_persistent_kernel<6>,
-        (const void *)batch_persistent_kernel<7>,  (const void *)batch_persistent_kernel<8>,
-        (const void *)batch_persistent_kernel<9>,  (const void *)batch_persistent_kernel<10>,
-        (const void *)batch_persistent_kernel<11>, (const void *)batch_persistent_kernel<12>,
-        (const void *)batch_persistent_kernel<13>, (const void *)batch_persistent_kernel<14>,
-        (const void *)batch_persistent_kernel<15>,
-    };
-    return table[tmask & 15u];
+    static const void *const table[] = {(const void *)batch_persistent_kernel<M + 1>...};
+    return tmask >= 1 && tmask <= sizeof...(M) ? table[tmask - 1] : nullptr;
 }
+
+const void *persistent_kernel(unsigned tmask) { return persistent_pick(tmask, std::make_integer_sequence<unsigned, 31>{}); }
 
 int persistent_grid(const void *kernel, unsigned *grid)
 {
@@ -430,6 +428,9 @@ int finish_persistent(const BatchArgs &b, uint32_t *iters, hipStream_t s)
     if (int rc = b2sr::check(hipMemcpyAsync(h, b.flags, sizeof h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync")) return rc;
     if (int rc = b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize")) return rc;
     if (h[5]) {
+        // clear the flag so that the next launch runs again, then report the time-out
+        if (int rc = b2sr::fill_u32(b.flags + 5, 1, 0, s)) return rc;
+        if (int rc = b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize")) return rc;
         b2sr::set_hip_error(hipErrorLaunchTimeOut, "batch_persistent_kernel grid barrier timed out");
         return B2SR_EHIP;
     }
@@ -448,6 +449,7 @@ int launch_level(const BatchArgs &b, hipStream_t stream)
         case 4: batch_product_kernel<4><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
         case 8: batch_product_kernel<8><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
         case 16: batch_product_kernel<16><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
+        case 64: batch_product_kernel<64><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
         default: batch_product_kernel<32><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
         }
         if (int rc = b2sr::check_launch("batch_product_kernel")) return rc;
@@ -503,7 +505,8 @@ int add_levels(hipGraph_t g, hipGraphNode_t *last, BatchArgs &b, uint32_t levels
             const void *f = gr.tile == 4    ? (const void *)batch_product_kernel<4>
                             : gr.tile == 8  ? (const void *)batch_product_kernel<8>
                             : gr.tile == 16 ? (const void *)batch_product_kernel<16>
-                                            : (const void *)batch_product_kernel<32>;
+                            : gr.tile == 32 ? (const void *)batch_product_kernel<32>
+                                            : (const void *)batch_product_kernel<64>;
             if (int rc = add_node(g, last, f, b2sr::grid_for(gr.nchunks, 4), 256, args_p)) return rc;
         }
         if (int rc = add_node(g, last, (const void *)batch_update_kernel, b2sr::grid_for(b.n, 256, 1024), 256, args_b))
@@ -557,6 +560,10 @@ int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix
     BatchArgs &b = P->args;
     void *args_b[] = {&b};
     hipGraphNode_t last = nullptr;
+    // the time-out flag outlives a replay: cleared here once, then only by the
+    // status read that reports it
+    b.sticky_timeout = 1;
+    if (!rc) rc = b2sr::check(hipMemset(b.flags + 5, 0, sizeof(uint32_t)), "hipMemset(time-out flag)");
     if (!rc) rc = b2sr::check(hipGraphCreate(&P->first, 0), "hipGraphCreate");
     if (!rc) rc = add_node(P->first, &last, (const void *)batch_init_kernel, vgrid((uint64_t)n * 64), 256, args_b);
     if (!rc && nseeds) rc = add_node(P->first, &last, (const void *)batch_seed_kernel, vgrid(nseeds), 256, args_b);
@@ -566,12 +573,14 @@ int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix
         rc = persistent_grid(persistent_kernel(b.tmask), &grid);
         if (!rc) rc = add_node(P->first, &last, persistent_kernel(b.tmask), grid, kPersistThreads, args_b, &run);
         if (!rc) {
-            // ask for co-residency checks where the runtime offers them; the barrier
-            // itself needs no runtime support and the grid is sized to be resident
+            // a cooperative node: the runtime checks at each replay that the grid
+            // can be co-resident, as hipLaunchCooperativeKernel does
             hipKernelNodeAttrValue v{};
             v.cooperative = 1;
-            if (hipGraphKernelNodeSetAttribute(run, hipKernelNodeAttributeCooperative, &v) != hipSuccess)
+            if (hipGraphKernelNodeSetAttribute(run, hipKernelNodeAttributeCooperative, &v) != hipSuccess) {
                 (void)hipGetLastError();
+                rc = B2SR_ENOTSUP;
+            }
         }
     } else if (!rc) {
         rc = add_levels(P->first, &last, b, kPlanLevels);
@@ -607,6 +616,12 @@ int b2sr_msbfs_batch_plan_launch(b2sr_msbfs_plan plan, uint32_t *iters, hipStrea
     }
     if (iters) *iters = h[2];
     return B2SR_OK;
+}
+
+int b2sr_msbfs_batch_plan_status(b2sr_msbfs_plan plan, uint32_t *iters, hipStream_t stream)
+{
+    if (!plan || !plan->first_exec) return B2SR_EINVAL;
+    return finish_persistent(plan->args, iters, stream);
 }
 
 int b2sr_msbfs_batch_plan_destroy(b2sr_msbfs_plan plan)

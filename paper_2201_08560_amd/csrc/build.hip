@@ -120,7 +120,7 @@ count_tiles_kernel(uint32_t n, const uint32_t *__restrict__ rowptr, const uint32
                    uint32_t logT, uint32_t ntr, uint32_t *__restrict__ tile_rowptr)
 {
     __shared__ uint32_t s_bm[kWinWords];
-    __shared__ uint32_t s_rp[33];
+    __shared__ uint32_t s_rp[65];
     __shared__ uint32_t s_red[kBuildThreads / B2SR_WAVE];
     for (uint32_t I = blockIdx.x; I < ntr; I += gridDim.x) {
         TileRowCtx c = tile_row_setup<LOWER>(n, rowptr, colind, logT, I, s_rp, s_red);
@@ -191,7 +191,7 @@ fill_tiles_kernel(uint32_t n, const uint32_t *__restrict__ rowptr, const uint32_
 {
     __shared__ uint32_t s_bm[kWinWords];
     __shared__ uint32_t s_pre[kWinWords];
-    __shared__ uint32_t s_rp[33];
+    __shared__ uint32_t s_rp[65];
     __shared__ uint32_t s_red[kBuildThreads / B2SR_WAVE];
     __shared__ uint32_t s_thr[kBuildThreads];
     const uint32_t T = 1u << logT;
@@ -244,9 +244,9 @@ fill_tiles_kernel(uint32_t n, const uint32_t *__restrict__ rowptr, const uint32_
                 if (J < wb || off >= nw * 32) continue;
                 uint32_t wi = off >> 5, bi = off & 31;
                 uint32_t pos = s_pre[wi] + __popc(s_bm[wi] & ((1u << bi) - 1u));
-                uint64_t byte = ((uint64_t)(base + pos) * T + r) * rbytes;
-                uint32_t shift = (uint32_t)(byte & 3) * 8 + (j & (T - 1));
-                atomicOr(&bits32[byte >> 2], 1u << shift);
+                // bit (r, j % T) of the tile, counted from the start of bits
+                const uint64_t bit = ((uint64_t)(base + pos) * T + r) * rbytes * 8 + (j & (T - 1));
+                atomicOr(&bits32[bit >> 5], 1u << (bit & 31));
             }
             base += wtotal;
             __syncthreads();
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) pack_bits_kernel(uint32_t n, const uint8_
     }
 }
 
-inline uint32_t log2_tile(uint32_t T) { return T == 4 ? 2 : T == 8 ? 3 : T == 16 ? 4 : 5; }
+inline uint32_t log2_tile(uint32_t T) { return T == 4 ? 2 : T == 8 ? 3 : T == 16 ? 4 : T == 32 ? 5 : 6; }
 
 // ---- CSR transpose (directed graphs: the pull matrix A^T from the CSR of A)
 // Counts land at t_rowptr[v + 1]; the in-place scan above turns them into row

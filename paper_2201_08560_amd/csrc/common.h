@@ -27,15 +27,20 @@ inline int check(hipError_t e, const char *where)
 // Checks the launch status of the kernel just enqueued.
 inline int check_launch(const char *where) { return check(hipGetLastError(), where); }
 
-inline bool valid_tile(uint32_t t) { return t == 4 || t == 8 || t == 16 || t == 32; }
+inline bool valid_tile(uint32_t t) { return t == 4 || t == 8 || t == 16 || t == 32 || t == 64; }
 inline uint32_t n_tile_rows(uint32_t n, uint32_t T) { return (n + T - 1) / T; }
 inline uint32_t n_words(uint32_t n) { return (n + 31) / 32; }
-// Bytes of one bit-row (Table II).
-inline uint32_t row_bytes(uint32_t T) { return T == 32 ? 4 : (T == 16 ? 2 : 1); }
+// Bytes of one bit-row (Table II; 8 for T = 64, the 64-bit packing type of
+// Sec. III-A).
+inline uint32_t row_bytes(uint32_t T) { return T == 64 ? 8 : T == 32 ? 4 : (T == 16 ? 2 : 1); }
 inline uint64_t bits_bytes(uint64_t ntiles, uint32_t T) { return ntiles * T * row_bytes(T); }
 
 // Host validation of a B2SR view; returns B2SR_OK or an error code.
 int validate_matrix(const b2sr_matrix *A);
+
+// Enqueues p[0 .. count) = value on the stream (a fill kernel: no memset nodes
+// in captured graphs).
+int fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
 
 inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap = 1u << 20)
 {
@@ -102,61 +107,42 @@ __device__ __forceinline__ uint32_t sat_add_u32(uint32_t a, uint32_t b)
     return s < a ? 0xFFFFFFFFu : s;
 }
 
+// The register type of one bit-row: T-bit values in 32-bit registers, 64-bit
+// ones for T = 64.
+template <int T> struct RowWord { using type = uint32_t; };
+template <> struct RowWord<64> { using type = uint64_t; };
+template <int T> using row_t = typename RowWord<T>::type;
+
 // Per tile width: lanes per tile (LPT), bit-rows per lane (RPL) and tiles per
-// wave step (TPW).  One lane reads a 16-byte (T = 32, 16), 8-byte (T = 8) or
-// 4-byte (T = 4) piece of a tile, so a wave step reads a contiguous run of
-// whole tiles: 1 KiB for T = 32, 1 KiB for T = 16, 512 B for T = 8 and 256 B
-// for T = 4.
+// wave step (TPW).  One lane reads a 32-byte (T = 64), 16-byte (T = 32, 16),
+// 8-byte (T = 8) or 4-byte (T = 4) piece of a tile, so a wave step reads a
+// contiguous run of whole tiles: 2 KiB for T = 64, 1 KiB for T = 32 and 16,
+// 512 B for T = 8 and 256 B for T = 4.
 template <int T> struct TileShape;
+template <> struct TileShape<64> { static constexpr int LPT = 16, RPL = 4, TPW = 4; };
 template <> struct TileShape<32> { static constexpr int LPT = 8, RPL = 4, TPW = 8; };
 template <> struct TileShape<16> { static constexpr int LPT = 2, RPL = 8, TPW = 32; };
 template <> struct TileShape<8> { static constexpr int LPT = 1, RPL = 8, TPW = 64; };
 template <> struct TileShape<4> { static constexpr int LPT = 1, RPL = 4, TPW = 64; };
 
-// Loads the RPL bit-rows [sub*RPL, sub*RPL + RPL) of tile t as T-bit values.
-template <int T> __device__ __forceinline__ void load_rows(const void *bits, uint32_t t, uint32_t sub,
-                                                           uint32_t (&a)[TileShape<T>::RPL]);
-
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-template <> __device__ __forceinline__ void load_rows<32>(const void *bits, uint32_t t, uint32_t sub,
-                                                          uint32_t (&a)[4])
+// T-bit segment J of a bit vector over n entries (bits [J*T, J*T + T)).  At
+// T = 64 the segment's upper word lies past the vector's last word when n
+// ends in its lower half; it reads as zero then.
+template <int T> __device__ __forceinline__ row_t<T> bit_segment(const uint32_t *x, uint32_t J, uint32_t n)
 {
-    u32x4 v = __builtin_nontemporal_load((const u32x4 *)bits + ((size_t)t * 8 + sub));
-    a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
-}
-template <> __device__ __forceinline__ void load_rows<16>(const void *bits, uint32_t t, uint32_t sub,
-                                                          uint32_t (&a)[8])
-{
-    u32x4 v = __builtin_nontemporal_load((const u32x4 *)bits + ((size_t)t * 2 + sub));
-    a[0] = v.x & 0xFFFFu; a[1] = v.x >> 16; a[2] = v.y & 0xFFFFu; a[3] = v.y >> 16;
-    a[4] = v.z & 0xFFFFu; a[5] = v.z >> 16; a[6] = v.w & 0xFFFFu; a[7] = v.w >> 16;
-}
-template <> __device__ __forceinline__ void load_rows<8>(const void *bits, uint32_t t, uint32_t,
-                                                         uint32_t (&a)[8])
-{
-    u32x2 v = __builtin_nontemporal_load((const u32x2 *)bits + t);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        a[k] = (v.x >> (8 * k)) & 0xFFu;
-        a[4 + k] = (v.y >> (8 * k)) & 0xFFu;
-    }
-}
-template <> __device__ __forceinline__ void load_rows<4>(const void *bits, uint32_t t, uint32_t,
-                                                         uint32_t (&a)[4])
-{
-    uint32_t v = __builtin_nontemporal_load((const uint32_t *)bits + t);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) a[k] = (v >> (8 * k)) & 0xFu;
-}
-
-// T-bit segment J of a bit vector (bits [J*T, J*T + T)).
-template <int T> __device__ __forceinline__ uint32_t bit_segment(const uint32_t *x, uint32_t J)
-{
-    if constexpr (T == 32) {
+    if constexpr (T == 64) {
+        const uint32_t lo = x[2 * (size_t)J];
+        const uint32_t hi = (uint64_t)J * 64 + 32 < n ? x[2 * (size_t)J + 1] : 0u;
+        return ((uint64_t)hi << 32) | lo;
+    } else if constexpr (T == 32) {
+        (void)n;
         return x[J];
     } else {
+        (void)n;
         uint32_t w = x[(J * T) >> 5];
         return (w >> ((J * T) & 31u)) & ((1u << T) - 1u);
     }

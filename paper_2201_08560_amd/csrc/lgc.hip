@@ -140,9 +140,10 @@ __global__ void rank_kernel(uint32_t n, const uint32_t *__restrict__ order, uint
         rank[order[r]] = (uint32_t)r;
 }
 
-template <int T> __device__ __forceinline__ uint32_t row_word(const void *bits, uint64_t t, uint32_t r)
+template <int T> __device__ __forceinline__ row_t<T> row_word(const void *bits, uint64_t t, uint32_t r)
 {
-    if constexpr (T == 32) return ((const uint32_t *)bits)[t * 32 + r];
+    if constexpr (T == 64) return ((const uint64_t *)bits)[t * 64 + r];
+    else if constexpr (T == 32) return ((const uint32_t *)bits)[t * 32 + r];
     else if constexpr (T == 16) return ((const uint16_t *)bits)[t * 16 + r];
     else if constexpr (T == 8) return ((const uint8_t *)bits)[t * 8 + r];
     else return ((const uint8_t *)bits)[t * 4 + r] & 0xFu;
@@ -189,11 +190,11 @@ __global__ void __launch_bounds__(kThreads)
                 ru = u < n ? rank[u] : 0xFFFFFFFFu;
             }
             if (ru >= ntaken) continue;
-            uint32_t word = row_word<T>(bits, t, r);
+            row_t<T> word = row_word<T>(bits, t, r);
             const uint32_t cbase = tile_colind[t] * T;
             while (word) {
-                const uint32_t v = cbase + (uint32_t)(__ffs(word) - 1);
-                word &= word - 1u;
+                const uint32_t v = cbase + (uint32_t)(T == 64 ? __builtin_ctzll(word) : __builtin_ctz((uint32_t)word));
+                word &= word - 1;
                 const uint32_t rv = v < n ? rank[v] : 0u;  // bits past n are never set in a valid matrix
                 if (ru < rv) {
                     ++plus;
@@ -444,6 +445,7 @@ int sweep(const b2sr_matrix *A, const float *score, const Layout &L, uint32_t *o
     case 4: rc = launch_edges<4>(A, L, s); break;
     case 8: rc = launch_edges<8>(A, L, s); break;
     case 16: rc = launch_edges<16>(A, L, s); break;
+    case 64: rc = launch_edges<64>(A, L, s); break;
     default: rc = launch_edges<32>(A, L, s); break;
     }
     if (rc) return rc;

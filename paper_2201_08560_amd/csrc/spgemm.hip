@@ -13,8 +13,13 @@
 //     "is there a tile A_IK, and where" into two LDS reads.
 //   * Its waves take the mask tiles (I, J) of M's tile-row I in turn.  A wave
 //     lists the set bits (r, c) of the mask tile in LDS, then streams Bt's
-//     tile-row J one tile column K per lane; each lane whose K also appears in
-//     A's tile-row adds popcount(A_IK[r] & Bt_JK[c]) over the listed (r, c).
+//     tile-row J one tile column K per lane and looks K up in A's tile-row.
+//   * T <= 8: a tile is one word, so each lane with a match loads both tiles
+//     whole and adds popcount(A_IK[r] & Bt_JK[c]) over the listed (r, c).
+//   * T >= 16: the matches of a round are listed in LDS with a ballot, and the
+//     wave spreads (match, listed bit) items over its lanes: each item loads
+//     its two bit-rows, independent of every other, so the wave keeps many
+//     loads in flight instead of a few lanes walking the list serially.
 //   * Lanes accumulate in 64-bit registers; one atomic add per wave at the end.
 // For triangle counting (A = Bt = M = L, the strict lower triangle) row I of L
 // is read once per workgroup and Bt's rows are re-read from L2/MALL.
@@ -37,17 +42,28 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / B2SR_WAVE;
 constexpr uint32_t kMapWords = 4096;  // bitmap of up to 131072 tile columns
 
-template <int T> __device__ __forceinline__ uint32_t load_word(const void *bits, size_t idx)
+template <int T> __device__ __forceinline__ row_t<T> load_word(const void *bits, size_t idx)
 {
-    if constexpr (T == 32) return ((const uint32_t *)bits)[idx];
+    if constexpr (T == 64) return ((const uint64_t *)bits)[idx];
+    else if constexpr (T == 32) return ((const uint32_t *)bits)[idx];
     else if constexpr (T == 16) return ((const uint16_t *)bits)[idx];
     else return ((const uint8_t *)bits)[idx];
 }
 
+__device__ __forceinline__ uint32_t popc_word(uint32_t v) { return (uint32_t)__popc(v); }
+__device__ __forceinline__ uint32_t popc_word(uint64_t v) { return (uint32_t)__popcll(v); }
+__device__ __forceinline__ uint32_t ctz_word(uint32_t v) { return (uint32_t)__builtin_ctz(v); }
+__device__ __forceinline__ uint32_t ctz_word(uint64_t v) { return (uint32_t)__builtin_ctzll(v); }
+
 #ifndef B2SR_TC_UB
 #define B2SR_TC_UB 4
 #endif
-constexpr int kUB = B2SR_TC_UB;  // Bt tile columns per lane per round
+constexpr int kUB = B2SR_TC_UB;  // streamed tile columns per lane per round
+#ifndef B2SR_TC_IU
+#define B2SR_TC_IU 4
+#endif
+constexpr int kIU = B2SR_TC_IU;  // (tile pair, mask bit) items per lane in flight, T >= 16
+constexpr uint32_t kHitCap = 64 * kUB;  // matched tile pairs of one round (T >= 16)
 #ifndef B2SR_TC_SWAP_CHUNK
 #define B2SR_TC_SWAP_CHUNK 128
 #endif
@@ -78,6 +94,13 @@ struct GemmArgs {
     uint32_t items_bound;  // an upper bound of item_off[ntr] (the launch's grid)
 };
 
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Whether mask tile (I, J) is taken from J's side: A and Bt alias, and A's row
 // I is the shorter non-empty one.
 __device__ __forceinline__ bool swapped(uint32_t len_ai, uint32_t len_btj)
@@ -85,27 +108,54 @@ __device__ __forceinline__ bool swapped(uint32_t len_ai, uint32_t len_btj)
     return len_ai > 0 && len_ai < len_btj;
 }
 
-// sum over the listed mask bits (r, c) of popcount(A_tile[r] & Bt_tile[c]) for
-// the tiles at positions ia (A) and kb (Bt).  Tiles of T <= 8 are loaded whole
-// (T bytes) once; wider tiles are read a row at a time.
+// T <= 8: sum over the listed mask bits (r, c) of popcount(A_tile[r] &
+// Bt_tile[c]) for the tiles at positions ia (A) and kb (Bt), each loaded whole
+// (T bytes) once.
 template <int T>
-__device__ __forceinline__ uint32_t pair_sum(const GemmArgs &g, size_t ia, uint32_t kb, const uint16_t *pairs,
-                                             uint32_t npairs)
+__device__ __forceinline__ uint32_t pair_sum_small(const GemmArgs &g, size_t ia, uint32_t kb, const uint16_t *pairs,
+                                                   uint32_t npairs)
 {
+    static_assert(T <= 8, "whole-tile words");
+    using W = typename std::conditional<T == 8, uint64_t, uint32_t>::type;
+    const W a = ((const W *)g.a_bits)[ia], b = ((const W *)g.b_bits)[kb];
     uint32_t part = 0;
-    if constexpr (T <= 8) {
-        using W = typename std::conditional<T == 8, uint64_t, uint32_t>::type;
-        const W a = ((const W *)g.a_bits)[ia], b = ((const W *)g.b_bits)[kb];
-        for (uint32_t q = 0; q < npairs; ++q) {
+    for (uint32_t q = 0; q < npairs; ++q) {
+        const uint32_t rc = pairs[q];
+        part += __popc((uint32_t)((a >> (8 * (rc >> 8))) & (b >> (8 * (rc & 0xFFu)))) & 0xFFu);
+    }
+    return part;
+}
+
+// T >= 16: the products of nh matched tile pairs (hits[h] = A tile position,
+// Bt tile position) over the npairs listed mask bits, as nh * npairs items
+// spread over the wave's lanes: item x is tile pair x / npairs and mask bit
+// x % npairs, and costs two independent row loads.  Each lane keeps kIU items'
+// loads in flight.  inv = 1 / npairs (the quotient is corrected to exact).
+template <int T>
+__device__ __forceinline__ uint32_t items_sum(const GemmArgs &g, const uint2 *hits, uint32_t nh, const uint16_t *pairs,
+                                              uint32_t npairs, float inv)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t nitems = nh * npairs;  // <= kHitCap * T * T < 2^24, exact in float
+    uint32_t part = 0;
+    for (uint32_t x0 = 0; x0 < nitems; x0 += 64 * kIU) {
+        row_t<T> a[kIU], b[kIU];
+#pragma unroll
+        for (int u = 0; u < kIU; ++u) {
+            const uint32_t x = x0 + 64 * u + lane;
+            const bool ok = x < nitems;
+            const uint32_t xc = ok ? x : 0u;
+            int h = (int)((float)xc * inv);
+            int q = (int)xc - h * (int)npairs;
+            if (q < 0) { --h; q += (int)npairs; }
+            else if (q >= (int)npairs) { ++h; q -= (int)npairs; }
+            const uint2 hp = hits[h];
             const uint32_t rc = pairs[q];
-            part += __popc((uint32_t)((a >> (8 * (rc >> 8))) & (b >> (8 * (rc & 0xFFu)))) & 0xFFu);
+            a[u] = ok ? load_word<T>(g.a_bits, (size_t)hp.x * T + (rc >> 8)) : (row_t<T>)0;
+            b[u] = ok ? load_word<T>(g.b_bits, (size_t)hp.y * T + (rc & 0xFFu)) : (row_t<T>)0;
         }
-    } else {
-        const size_t abase = ia * T, bbase = (size_t)kb * T;
-        for (uint32_t q = 0; q < npairs; ++q) {
-            const uint32_t rc = pairs[q];
-            part += __popc(load_word<T>(g.a_bits, abase + (rc >> 8)) & load_word<T>(g.b_bits, bbase + (rc & 0xFFu)));
-        }
+#pragma unroll
+        for (int u = 0; u < kIU; ++u) part += popc_word(a[u] & b[u]);
     }
     return part;
 }
@@ -115,13 +165,15 @@ __device__ __forceinline__ uint32_t pair_sum(const GemmArgs &g, size_t ia, uint3
 // operations (matched pairs times the mask tile's set bits).
 template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThreads) spgemm_masked_kernel(GemmArgs g)
 {
+    using R = row_t<T>;
+    constexpr bool kItems = T >= 16;
     // the bitmap and its prefix are sized at launch to the matrix's tile columns,
     // so that small matrices leave room for more workgroups per CU
     extern __shared__ uint32_t s_dyn[];
     uint32_t *const s_map = s_dyn, *const s_pre = s_dyn + g.map_words;
     __shared__ uint32_t s_thr[kThreads];
     __shared__ uint16_t s_pairs[kWaves][T * T];
-    __shared__ uint32_t s_cnt[kWaves][B2SR_WAVE];
+    __shared__ uint2 s_hits[kItems ? kWaves : 1][kItems ? kHitCap : 1];
     const uint32_t lane = lane_id(), wv = threadIdx.x / B2SR_WAVE;
     unsigned long long acc = 0;
     [[maybe_unused]] unsigned long long n_tiles = 0, n_lookups = 0, n_matches = 0;
@@ -199,23 +251,23 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
         // this row of Bt = A, gives Bt_JK.
         auto do_tile = [&](uint32_t m, uint32_t p0, uint32_t p1, const uint32_t *ci, bool swap) {
             // list the set bits (r, c) of mask tile m
-            const uint32_t mw = lane < (uint32_t)T ? load_word<T>(g.m_bits, (size_t)m * T + lane) : 0u;
-            const uint32_t cnt = __popc(mw);
+            const R mw = lane < (uint32_t)T ? load_word<T>(g.m_bits, (size_t)m * T + lane) : (R)0;
+            const uint32_t cnt = popc_word(mw);
             uint32_t inc = cnt;
             for (uint32_t d = 1; d < 64; d <<= 1) {
                 const uint32_t o = shfl_up(inc, d);
                 if (lane >= d) inc += o;
             }
             const uint32_t npairs = readlane(inc, 63);
-            uint32_t pos = inc - cnt, w = mw;
+            uint32_t pos = inc - cnt;
+            R w = mw;
             while (w) {
-                const uint32_t c = __builtin_ctz(w);
+                const uint32_t c = ctz_word(w);
                 w &= w - 1;
                 s_pairs[wv][pos++] = (uint16_t)((lane << 8) | c);
             }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_sync();
+            const float inv = 1.0f / (float)npairs;
             // the streamed row, kUB tile columns per lane per round: the column
             // loads and lookups of a round are independent, so they overlap
             unsigned long long part = 0;
@@ -229,23 +281,37 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
                 int64_t hit[kUB];
 #pragma unroll
                 for (int u = 0; u < kUB; ++u) hit[u] = ps[u] < p1 ? lookup(K[u]) : -1;
+                uint32_t nh = 0;  // T >= 16: the round's matched tile pairs, listed in s_hits
 #pragma unroll
                 for (int u = 0; u < kUB; ++u) {
+                    const size_t ia = swap ? (size_t)ps[u] : (size_t)hit[u];
+                    const uint32_t kb = swap ? (uint32_t)hit[u] : ps[u];
                     if constexpr (PROFILE) {
                         n_lookups += ps[u] < p1;
                         if (hit[u] >= 0) {
                             ++n_matches;
                             part += npairs;
                         }
+                    } else if constexpr (kItems) {
+                        const uint64_t bal = __ballot(hit[u] >= 0);
+                        if (hit[u] >= 0)
+                            s_hits[wv][nh + __popcll(bal & ((1ull << lane) - 1ull))] = uint2{(uint32_t)ia, kb};
+                        nh += (uint32_t)__popcll(bal);
                     } else if (hit[u] >= 0) {
-                        part += swap ? pair_sum<T>(g, (size_t)ps[u], (uint32_t)hit[u], s_pairs[wv], npairs)
-                                     : pair_sum<T>(g, (size_t)hit[u], ps[u], s_pairs[wv], npairs);
+                        part += pair_sum_small<T>(g, ia, kb, s_pairs[wv], npairs);
+                    }
+                }
+                if constexpr (kItems && !PROFILE) {
+                    if (nh) {
+                        wave_sync();
+                        part += items_sum<T>(g, s_hits[wv], nh, s_pairs[wv], npairs, inv);
+                        wave_sync();  // the next round rewrites s_hits
                     }
                 }
             }
             acc += part;
             if constexpr (PROFILE) n_tiles += lane == 0;
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();  // s_pairs and s_hits are rewritten by the next tile
         };
 
         for (uint32_t m = m0 + wv; m < m1; m += kWaves) {
@@ -259,7 +325,6 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
             do_tile(m, g.a_rp[Ir], g.a_rp[Ir + 1], g.a_ci, true);
         }
     }
-    (void)s_cnt;
     for (int d = 32; d >= 1; d >>= 1) acc += shfl_xor((uint64_t)acc, d);
     if constexpr (PROFILE) {
         for (int d = 32; d >= 1; d >>= 1) {
@@ -483,6 +548,7 @@ int column_counts(const b2sr_matrix *A, uint32_t *colsum, hipStream_t s)
     case 4: column_counts_kernel<4><<<grid, 256, 0, s>>>(A->tile_colind, A->bits, A->ntiles, colsum); break;
     case 8: column_counts_kernel<8><<<grid, 256, 0, s>>>(A->tile_colind, A->bits, A->ntiles, colsum); break;
     case 16: column_counts_kernel<16><<<grid, 256, 0, s>>>(A->tile_colind, A->bits, A->ntiles, colsum); break;
+    case 64: column_counts_kernel<64><<<grid, 256, 0, s>>>(A->tile_colind, A->bits, A->ntiles, colsum); break;
     default: column_counts_kernel<32><<<grid, 256, 0, s>>>(A->tile_colind, A->bits, A->ntiles, colsum); break;
     }
     return check_launch("column_counts_kernel");
@@ -518,6 +584,7 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
     case 4: return launch_masked<4, true>(g, stream);
     case 8: return launch_masked<8, true>(g, stream);
     case 16: return launch_masked<16, true>(g, stream);
+    case 64: return launch_masked<64, true>(g, stream);
     default: return launch_masked<32, true>(g, stream);
     }
 }
@@ -549,6 +616,7 @@ int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix
         case 4: return launch_unmasked<4>(A, Bt, (uint32_t *)ws, len, sum, stream);
         case 8: return launch_unmasked<8>(A, Bt, (uint32_t *)ws, len, sum, stream);
         case 16: return launch_unmasked<16>(A, Bt, (uint32_t *)ws, len, sum, stream);
+        case 64: return launch_unmasked<64>(A, Bt, (uint32_t *)ws, len, sum, stream);
         default: return launch_unmasked<32>(A, Bt, (uint32_t *)ws, len, sum, stream);
         }
     }
@@ -566,6 +634,7 @@ int spgemm_masked(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_matrix
     case 4: return launch_masked<4>(g, stream);
     case 8: return launch_masked<8>(g, stream);
     case 16: return launch_masked<16>(g, stream);
+    case 64: return launch_masked<64>(g, stream);
     default: return launch_masked<32>(g, stream);
     }
 }
@@ -596,6 +665,7 @@ int spgemm_masked_rows(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2sr_m
     case 4: return launch_masked<4>(g, stream);
     case 8: return launch_masked<8>(g, stream);
     case 16: return launch_masked<16>(g, stream);
+    case 64: return launch_masked<64>(g, stream);
     default: return launch_masked<32>(g, stream);
     }
 }

@@ -5,7 +5,7 @@
 // waves with thousands of tiles, so here every wave takes a fixed CHUNK of
 // consecutive tiles instead, whatever rows they belong to:
 //   * a wave step covers TPW consecutive tiles; LPT lanes share a tile and each
-//     reads one 16/8/4-byte piece holding RPL bit-rows (TileShape), so a step
+//     reads one 32/16/8/4-byte piece holding RPL bit-rows (TileShape), so a step
 //     reads one contiguous run of tile bytes;
 //   * steps are grouped into blocks of U steps whose loads are all issued before
 //     any of them is used (U * 16 bytes of tile data in flight per lane for
@@ -105,7 +105,7 @@ template <int T> __global__ void __launch_bounds__(256) plus_fixup_kernel(SpmvAr
 #pragma unroll 8
     for (uint32_t c2 = c + 1; c2 <= c_last; ++c2) sum += p.ws_part[(size_t)c2 * 2 * T + r];
     const uint32_t row = R * T + r;
-    if (row >= p.n || !((keep_bits<T>(p.mask, p.flags, R) >> r) & 1u)) return;
+    if (row >= p.n || !((keep_bits<T>(p.mask, p.flags, R, p.n) >> r) & 1u)) return;
     float *y = (float *)p.y + row;
     if (p.flags & B2SR_ACCUMULATE) *y = *y + p.alpha * sum;
     else *y = p.alpha * sum + p.beta;
@@ -190,6 +190,7 @@ template <int K> int dispatch(uint32_t T, const SpmvArgs &p, hipStream_t s)
     case 4: return launch<4, K>(p, s);
     case 8: return launch<8, K>(p, s);
     case 16: return launch<16, K>(p, s);
+    case 64: return launch<64, K>(p, s);
     default: return launch<32, K>(p, s);
     }
 }
@@ -212,6 +213,7 @@ uint32_t plus_chunk(uint32_t T, uint32_t ntiles)
     case 4: return chunk_tiles<4, kPlusF32>(ntiles);
     case 8: return chunk_tiles<8, kPlusF32>(ntiles);
     case 16: return chunk_tiles<16, kPlusF32>(ntiles);
+    case 64: return chunk_tiles<64, kPlusF32>(ntiles);
     default: return chunk_tiles<32, kPlusF32>(ntiles);
     }
 }

@@ -3,6 +3,8 @@
 // Internal to libb2sr.so.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 // Tuning knobs (compile-time; the defaults are the measured choices).
@@ -98,7 +100,9 @@ struct SpmvArgs {
 
 // Block shape per tile width and kind.  Bit and count products read the x
 // segment as T bits; the others stage T values per tile in LDS (a fixed budget
-// per wave, so the block shrinks as the vector values widen).
+// per wave, so the block shrinks as the vector values widen).  At T = 64 a
+// bit-product block holds half the steps, so that a lane keeps as many tile
+// bytes in flight (8 KiB per wave) as at T = 32.
 // SHORT (bit and count products): fewer steps per block, for matrices whose
 // tile-rows are shorter than a block and for sparse frontiers; fewer
 // registers then buy occupancy where the long blocks' loads would be cut short.
@@ -108,7 +112,8 @@ template <int T, int K, bool SHORT = false> struct Cfg {
     static constexpr bool kStage = K >= kPlusF32;
     static constexpr int VB = sizeof(typename KindTraits<K>::V);
     static constexpr int U = kStage ? B2SR_STAGE_BYTES / (TPW * T * VB)
-                           : SHORT  ? B2SR_BITS_STEPS_SHORT
+                           : SHORT  ? (T == 64 ? (B2SR_BITS_STEPS_SHORT + 1) / 2 : B2SR_BITS_STEPS_SHORT)
+                           : T == 64 ? (B2SR_BITS_STEPS + 1) / 2
                                     : (T == 32 ? B2SR_BITS_STEPS : B2SR_BITS_STEPS_SMALL);
     static constexpr int BT = U * TPW;                 // tiles per block
     static constexpr int JK = BT >= 64 ? BT / 64 : 1;  // tile-column registers per lane
@@ -116,7 +121,7 @@ template <int T, int K, bool SHORT = false> struct Cfg {
     static_assert(U >= 1 && (64 % TPW) == 0, "block shape");
 };
 
-// Tiles per wave chunk: whole blocks, aiming at about 32K waves per launch,
+// Tiles per wave chunk: whole blocks, aiming at about B2SR_TARGET_WAVES waves per launch,
 // between 1 and 16 blocks.  A pure function of (T, kind, ntiles), so the
 // float-sum workspace query and the launch agree.
 template <int T, int K, bool SHORT = false> inline uint32_t chunk_tiles(uint32_t ntiles)
@@ -130,20 +135,28 @@ template <int T, int K, bool SHORT = false> inline uint32_t chunk_tiles(uint32_t
 
 // One lane's raw piece of a tile.
 template <int T> struct PieceT { using type = u32x4; };
+template <> struct PieceT<64> { using type = u32x8; };
 template <> struct PieceT<8> { using type = u32x2; };
 template <> struct PieceT<4> { using type = uint32_t; };
 
 template <int T> __device__ __forceinline__ typename PieceT<T>::type load_piece(const void *bits, uint32_t t, uint32_t sub)
 {
-    if constexpr (T == 32) return load_stream((const u32x4 *)bits + ((size_t)t * 8 + sub));
+    if constexpr (T == 64) {
+        // two 16-byte loads (rows 4 sub .. 4 sub + 3 of the 512-byte tile)
+        const u32x4 *q = (const u32x4 *)bits + ((size_t)t * 32 + 2 * sub);
+        const u32x4 lo = load_stream(q), hi = load_stream(q + 1);
+        return u32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    }
+    else if constexpr (T == 32) return load_stream((const u32x4 *)bits + ((size_t)t * 8 + sub));
     else if constexpr (T == 16) return load_stream((const u32x4 *)bits + ((size_t)t * 2 + sub));
     else if constexpr (T == 8) return load_stream((const u32x2 *)bits + t);
     else return load_stream((const uint32_t *)bits + t);
 }
 
-// 128 zero bytes, the stand-in tile of lanes that skip their tile: every lane
-// issues every load of a block, so waits count the loads exactly.
-static __device__ __align__(16) uint32_t g_zero_tile[32];
+// 512 zero bytes (the largest tile), the stand-in tile of lanes that skip
+// their tile: every lane issues every load of a block, so waits count the
+// loads exactly.
+static __device__ __align__(16) uint32_t g_zero_tile[128];
 
 // The piece of tile t when `use`, else the same piece of the zero tile.
 template <int T>
@@ -162,9 +175,12 @@ template <int T> __device__ __forceinline__ typename PieceT<T>::type zero_piece(
 
 // The RPL bit-rows of a piece as T-bit values (Table II word layout).
 template <int T>
-__device__ __forceinline__ void piece_rows(const typename PieceT<T>::type &v, uint32_t (&a)[TileShape<T>::RPL])
+__device__ __forceinline__ void piece_rows(const typename PieceT<T>::type &v, row_t<T> (&a)[TileShape<T>::RPL])
 {
-    if constexpr (T == 32) {
+    if constexpr (T == 64) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = ((uint64_t)v[2 * k + 1] << 32) | v[2 * k];
+    } else if constexpr (T == 32) {
         a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
     } else if constexpr (T == 16) {
         a[0] = v.x & 0xFFFFu; a[1] = v.x >> 16; a[2] = v.y & 0xFFFFu; a[3] = v.y >> 16;
@@ -228,14 +244,21 @@ __device__ __forceinline__ uint32_t lane_row(const uint32_t *trp, uint32_t ntr, 
     return row;
 }
 
-// Rows of tile-row I that the mask keeps, as T bits.
-template <int T> __device__ __forceinline__ uint32_t keep_bits(const uint32_t *mask, unsigned flags, uint32_t I)
+// Rows of tile-row I that the mask keeps, as T bits (n: the vector length).
+template <int T>
+__device__ __forceinline__ row_t<T> keep_bits(const uint32_t *mask, unsigned flags, uint32_t I, uint32_t n)
 {
-    constexpr uint32_t full = T == 32 ? 0xFFFFFFFFu : ((1u << T) - 1u);
+    using R = row_t<T>;
+    constexpr R full = T >= 32 ? ~(R)0 : (R)((1u << T) - 1u);
     if (!mask) return full;
-    const uint32_t w = bit_segment<T>(mask, I);
-    return (flags & B2SR_MASK_COMPLEMENT) ? (~w & full) : w;
+    const R w = bit_segment<T>(mask, I, n);
+    return (flags & B2SR_MASK_COMPLEMENT) ? (R)(~w & full) : w;
 }
+
+__device__ __forceinline__ uint32_t popc_row(uint32_t v) { return (uint32_t)__popc(v); }
+__device__ __forceinline__ uint32_t popc_row(uint64_t v) { return (uint32_t)__popcll(v); }
+__device__ __forceinline__ uint32_t ctz_row(uint32_t v) { return (uint32_t)__builtin_ctz(v); }
+__device__ __forceinline__ uint32_t ctz_row(uint64_t v) { return (uint32_t)__builtin_ctzll(v); }
 
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -248,16 +271,24 @@ __device__ __forceinline__ void wave_lds_sync()
 // Row stores
 // ---------------------------------------------------------------------------
 
-template <int T> __device__ __forceinline__ void store_bits(const SpmvArgs &p, uint32_t I, uint32_t m)
+template <int T> __device__ __forceinline__ void store_bits(const SpmvArgs &p, uint32_t I, row_t<T> m)
 {
     if (!m) return;
-    const uint32_t bit = I * T;
-    atomicOr((uint32_t *)p.y + (bit >> 5), m << (bit & 31u));
+    if constexpr (T == 64) {
+        // the two words of the segment; the upper one exists whenever a row in
+        // it does (rows >= n hold no bits)
+        const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+        if (lo) atomicOr((uint32_t *)p.y + 2 * (size_t)I, lo);
+        if (hi) atomicOr((uint32_t *)p.y + 2 * (size_t)I + 1, hi);
+    } else {
+        const uint32_t bit = I * T;
+        atomicOr((uint32_t *)p.y + (bit >> 5), m << (bit & 31u));
+    }
 }
 
 // Stores the RPL rows [sub*RPL, sub*RPL + RPL) of tile-row I.
 template <int T, int K>
-__device__ __forceinline__ void store_values(const SpmvArgs &p, uint32_t I, uint32_t sub, uint32_t keep,
+__device__ __forceinline__ void store_values(const SpmvArgs &p, uint32_t I, uint32_t sub, row_t<T> keep,
                                              const typename KindTraits<K>::V (&v)[TileShape<T>::RPL],
                                              bool straddles, uint32_t chunk_id, uint32_t slot)
 {
@@ -296,7 +327,7 @@ __device__ __forceinline__ void store_values(const SpmvArgs &p, uint32_t I, uint
 // The product kernel, one template for every kind
 // ---------------------------------------------------------------------------
 
-// LDS per wave for the staged kinds (8 KiB, the same for every T and kind).
+// LDS per wave for the staged kinds (the same for every T and kind).
 constexpr uint32_t kStageBytesPerWave = B2SR_STAGE_BYTES;
 
 // Processes tile chunk chunk_id (wave-uniform) of the product described by p.
@@ -312,6 +343,8 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
     static_assert(!C::kStage || BT * T * sizeof(V) <= kStageBytesPerWave, "LDS slice");
     // Partials of one lane: a bit mask for kBits, RPL values otherwise.
     constexpr int NV = K == kBits ? 1 : RPL;
+    using R = row_t<T>;                                                  // one bit-row
+    using AV = typename std::conditional<K == kBits, R, V>::type;        // a partial
 
     const uint32_t lane = lane_id(), grp = lane / LPT, sub = lane % LPT;
     const uint32_t t_begin = chunk_id * p.chunk;
@@ -320,26 +353,26 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
     const uint32_t r_first = find_row(p.trp, p.ntr, t_begin);
     uint32_t r_cur = r_first;
     uint32_t r_end = p.trp[r_cur + 1];
-    uint32_t keep = keep_bits<T>(p.mask, p.flags, r_cur);
+    R keep = keep_bits<T>(p.mask, p.flags, r_cur, p.n);
     // A row straddles chunks when it starts before t_begin or ends after t_end;
     // only the chunk's first and last rows can.
     auto straddles = [&](uint32_t I) { return p.trp[I] < t_begin || p.trp[I + 1] > t_end; };
     auto slot_of = [&](uint32_t I) { return I == r_first ? 0u : 1u; };
 
-    V acc[NV];
+    AV acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = KT::id();
     // Bit products fold raw AND words per bit-row in the common case and form
     // the row bits only when a row is finished.
-    uint32_t raw[K == kBits ? RPL : 1];
+    R raw[K == kBits ? RPL : 1];
 #pragma unroll
     for (int k = 0; k < (K == kBits ? RPL : 1); ++k) raw[k] = 0;
     auto fold_raw = [&]() {
         if constexpr (K == kBits) {
-            uint32_t m = 0;
+            R m = 0;
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
-                m |= (uint32_t)(raw[k] != 0) << (sub * RPL + k);
+                m |= (R)(raw[k] != 0) << (sub * RPL + k);
                 raw[k] = 0;
             }
             acc[0] |= m;
@@ -361,30 +394,30 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
 #pragma unroll
         for (int k = 0; k < JK; ++k) Jr[k] = p.tci[min(blk + 64 * k + lane, t_end - 1)];
         Piece pc[U];
-        uint32_t seg[U];
+        R seg[U];
         if constexpr (!C::kStage) {
-            uint32_t Sr[JK];
+            R Sr[JK];
             // (At T = 32 the measured best is a per-lane branch for the sparse
             // hint and a clamped tile index for the dense case; below T = 32 the
             // zero tile in both.)
             if (p.flags & B2SR_SPARSE_X) {
                 // read a tile only when its x segment has a set bit
 #pragma unroll
-                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k]);
+                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k], p.n);
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
                     const uint32_t ti = i * TPW + grp;
                     seg[i] = shfl(Sr[(i * TPW) / 64], (int)(ti % 64));
                     const bool use = blk + ti < t_end && seg[i];
-                    if constexpr (T == 32) pc[i] = use ? load_piece<T>(p.bits, blk + ti, sub) : zero_piece<T>();
+                    if constexpr (T >= 32) pc[i] = use ? load_piece<T>(p.bits, blk + ti, sub) : zero_piece<T>();
                     else pc[i] = load_piece_or_zero<T>(p.bits, blk + ti, sub, use);
                 }
-            } else if constexpr (T == 32) {
+            } else if constexpr (T >= 32) {
                 // lanes past the chunk read its last tile; their segment is cleared
 #pragma unroll
                 for (int i = 0; i < U; ++i) pc[i] = load_piece<T>(p.bits, min(blk + i * TPW + grp, t_end - 1), sub);
 #pragma unroll
-                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k]);
+                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k], p.n);
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
                     const uint32_t ti = i * TPW + grp;
@@ -399,16 +432,16 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 }
                 // a tile past the chunk holds no bits, whatever its segment
 #pragma unroll
-                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k]);
+                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k], p.n);
 #pragma unroll
                 for (int i = 0; i < U; ++i) seg[i] = shfl(Sr[(i * TPW) / 64], (int)((i * TPW + grp) % 64));
             }
         } else {
             if constexpr (ACT) {
                 // active columns only: a tile whose x segment is wholly inactive is not read
-                uint32_t Sr[JK];
+                R Sr[JK];
 #pragma unroll
-                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>(p.xact, Jr[k]);
+                for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>(p.xact, Jr[k], p.n);
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
                     const uint32_t ti = i * TPW + grp;
@@ -500,22 +533,22 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
             const bool valid = base + grp < t_end;
             const uint32_t t = valid ? base + grp : t_end - 1;
             const uint32_t ti = i * TPW + grp;
-            V part[NV];
+            AV part[NV];
             auto compute = [&]() {
-                uint32_t a[RPL];
+                R a[RPL];
                 piece_rows<T>(pc[i], a);
                 if constexpr (K == kBits) {
-                    uint32_t m = 0;
+                    R m = 0;
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) m |= (uint32_t)((a[k] & seg[i]) != 0) << (sub * RPL + k);
+                    for (int k = 0; k < RPL; ++k) m |= (R)((a[k] & seg[i]) != 0) << (sub * RPL + k);
                     part[0] = m;
                 } else if constexpr (K == kCount) {
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) part[k] = (uint32_t)__popc(a[k] & seg[i]);  // Listing 1's dot
+                    for (int k = 0; k < RPL; ++k) part[k] = popc_row(a[k] & seg[i]);  // Listing 1's dot
                 } else {
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) part[k] = KT::id();
-                    uint32_t any = 0;
+                    R any = 0;
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
                         if constexpr (ACT) a[k] &= seg[i];  // inactive columns contribute the identity
@@ -523,13 +556,13 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                     }
                     if (any) {  // most lanes of a sparse tile hold no set bit
                         const V *xt = xs + ti * T;
-                        if constexpr (T == 32) {
+                        if constexpr (T >= 32) {
                             // the lowest set bit of every row first, the rows' LDS reads
                             // together (about two set bits per tile on power-law graphs);
                             // the sum order within a row is unchanged
                             V v[RPL];
 #pragma unroll
-                            for (int k = 0; k < RPL; ++k) v[k] = xt[a[k] ? __builtin_ctz(a[k]) : 0u];
+                            for (int k = 0; k < RPL; ++k) v[k] = xt[a[k] ? ctz_row(a[k]) : 0u];
                             any = 0;
 #pragma unroll
                             for (int k = 0; k < RPL; ++k) {
@@ -541,9 +574,9 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                         if (any) {
 #pragma unroll
                             for (int k = 0; k < RPL; ++k) {
-                                uint32_t w = a[k];
+                                R w = a[k];
                                 while (w) {
-                                    const uint32_t c = __builtin_ctz(w);
+                                    const uint32_t c = ctz_row(w);
                                     w &= w - 1;
                                     part[k] = KT::op(part[k], xt[c]);
                                 }
@@ -554,7 +587,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
             };
             if (last < r_end) {
                 if constexpr (K == kBits) {
-                    uint32_t a[RPL];
+                    R a[RPL];
                     piece_rows<T>(pc[i], a);
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) raw[k] |= a[k] & seg[i];
@@ -568,7 +601,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
             fold_raw();
             // the step crosses the end of row r_cur
             const uint32_t row = lane_row(p.trp, p.ntr, r_cur, t);
-            const uint32_t rkeep = row == r_cur ? keep : keep_bits<T>(p.mask, p.flags, row);
+            const R rkeep = row == r_cur ? keep : keep_bits<T>(p.mask, p.flags, row, p.n);
             if (valid && rkeep) compute();
             else {
 #pragma unroll
@@ -577,10 +610,10 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
             const uint32_t r_last = readlane(row, 63);
             const bool first_in_cur = readlane(row, 0) == r_cur;
             if constexpr (K == kBits) {
-                uint32_t acc_all = acc[0];
+                R acc_all = acc[0];
 #pragma unroll
                 for (int d = 1; d < 64; d <<= 1) acc_all |= shfl_xor(acc_all, d);
-                uint32_t v = part[0];
+                R v = part[0];
                 if (!first_in_cur) {
                     if (lane == 0) store_bits<T>(p, r_cur, acc_all & keep);
                 } else if (lane == 0) {
@@ -588,12 +621,13 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 }
 #pragma unroll
                 for (uint32_t d = 1; d < 64; d <<= 1) {
-                    const uint32_t o = shfl_up(v, d), ro = shfl_up(row, d);
+                    const R o = shfl_up(v, d);
+                    const uint32_t ro = shfl_up(row, d);
                     if (lane >= d && ro == row) v |= o;
                 }
                 const uint32_t next_row = shfl(row, (int)min(lane + 1, 63u));
                 if ((lane == 63 || next_row != row) && row != r_last) store_bits<T>(p, row, v & rkeep);
-                acc[0] = row == r_last ? part[0] : 0u;
+                acc[0] = row == r_last ? part[0] : (R)0;
             } else {
                 V v[NV], tot[NV];
 #pragma unroll
@@ -627,7 +661,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
             }
             r_cur = r_last;
             r_end = p.trp[r_cur + 1];
-            keep = keep_bits<T>(p.mask, p.flags, r_cur);
+            keep = keep_bits<T>(p.mask, p.flags, r_cur, p.n);
         }
         blk += BT;
         if constexpr (C::kStage) wave_lds_sync();  // the next block's LDS writes follow this block's reads
@@ -635,7 +669,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
     // flush the row the chunk ends in
     if constexpr (K == kBits) {
         fold_raw();
-        uint32_t acc_all = acc[0];
+        R acc_all = acc[0];
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) acc_all |= shfl_xor(acc_all, d);
         if (lane == 0) store_bits<T>(p, r_cur, acc_all & keep);

@@ -4,7 +4,7 @@ import numpy as np
 import graphgen as gg
 
 UNR = 0xFFFFFFFF
-TILES = (4, 8, 16, 32)
+TILES = (4, 8, 16, 32, 64)
 EPS32 = 2.0 ** -24
 
 

@@ -40,8 +40,8 @@ def test_matrix_validation():
     S = None
     x = ctypes.c_void_p(FAKE)
     assert L.spmv_bin_bin(None, x, None, 0, x, S) == -1
-    for bad in (mat(tile=6), mat(tile=64), mat(reserved=1), mat(rp=0), mat(ci=0), mat(bits=0),
-                mat(tile=32, bits=FAKE + 4), mat(ntiles=10**6, n=64, tile=32)):
+    for bad in (mat(tile=6), mat(tile=128), mat(reserved=1), mat(rp=0), mat(ci=0), mat(bits=0),
+                mat(tile=32, bits=FAKE + 4), mat(tile=64, bits=FAKE + 8), mat(ntiles=10**6, n=64, tile=32)):
         assert L.spmv_bin_bin(ctypes.byref(bad), x, None, 0, x, S) == -1
     assert L.spmv_bin_bin(ctypes.byref(mat(n=0xFFFFFFF0)), x, None, 0, x, S) == -2
 

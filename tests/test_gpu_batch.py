@@ -26,7 +26,7 @@ def make_graphs():
 
 
 GRAPHS = make_graphs()
-TILES = [(4, 8, 16, 32)[i % 4] for i in range(len(GRAPHS))]
+TILES = [(4, 8, 16, 32, 64)[i % 5] for i in range(len(GRAPHS))]
 
 
 def sources_for(g, k, seed):
@@ -96,6 +96,40 @@ def test_batch_graph_plan_replays(batch, mode):
         plan.launch()
         torch.cuda.synchronize()
         assert torch.equal(plan.out, eager)
+        # enqueue only, then read the status once
+        plan.launch(check=False)
+        assert plan.status() == eager_it
+        assert torch.equal(plan.out, eager)
+    finally:
+        plan.close()
+
+
+def _flags_word(n):
+    """Index (in 32-bit words) of the batch workspace's flag words: after the
+    F, V, Y frontier arrays and the active bit vector, each 256-byte aligned."""
+    off = 0
+    for nbytes in (n * 8, n * 8, n * 8, (n + 31) // 32 * 4):
+        off = (off + 255) & ~255
+        off += nbytes
+    return ((off + 255) & ~255) // 4
+
+
+def test_persistent_plan_reports_a_timed_out_barrier(batch):
+    """The time-out flag set from the host (as a barrier wait that ran out would
+    set it) makes a persistent replay stop at its first barrier; an enqueue-only
+    launch returns at once, the status read reports the time-out and clears the
+    flag, and the next replay is whole again."""
+    eager, _ = batch.run(b2.BATCH_LEVELS)
+    plan = batch.plan(b2.BATCH_PERSISTENT)
+    try:
+        plan.launch()
+        assert torch.equal(plan.out, eager)
+        plan.ws.view(torch.int32)[_flags_word(batch.n) + 5] = 1
+        plan.launch(check=False)
+        with pytest.raises(b2.B2SRError):
+            plan.status()
+        plan.launch()
+        assert torch.equal(plan.out, eager)
     finally:
         plan.close()
 
@@ -112,8 +146,8 @@ def test_batch_equals_per_graph_launches(batch):
 def test_autotune_exact_counts_match_oracle():
     for g in GRAPHS[:4]:
         T, rep = autotune.choose_tile(g)
-        assert T in (4, 8, 16, 32)
-        for k in (4, 8, 16, 32):
+        assert T in autotune.TILES
+        for k in autotune.TILES:
             assert rep["ntiles"][k] == orc.b2sr_count_tiles(g, k)
 
 

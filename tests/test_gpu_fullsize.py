@@ -68,14 +68,50 @@ def test_algorithms(big):
     g, A, src = big["g"], big["A"], big["sources"]
     print("bfs / msbfs", flush=True)
     assert np.array_equal(b2.as_u32(b2.b2sr_bfs(A, int(src[0]))[0]), orc.bfs(g, int(src[0])))
-    lvm, _ = b2.b2sr_msbfs(A, src[:16])
-    assert np.array_equal(b2.as_u32(lvm), orc.bfs_multi(g, src[:16]))
+    lvm, _ = b2.b2sr_msbfs(A, src)  # all 64 sources of the step: every bit lane of the frontier word
+    assert np.array_equal(b2.as_u32(lvm), orc.bfs_multi(g, src))
     print("sssp / cc", flush=True)
     assert np.array_equal(b2.as_u32(b2.b2sr_sssp(A, int(src[0]))[0]), orc.sssp_unit(g, int(src[0])))
     assert np.array_equal(b2.as_u32(b2.b2sr_cc(A)[0]), orc.cc(g))
     print("pagerank x 50", flush=True)
     pr = b2.b2sr_pagerank(A, 0.85, 50).cpu().numpy()
     assert rel_l1(pr, orc.pagerank(g, 0.85, 50)) <= 1e-5
+
+
+@pytest.mark.parametrize("T", TILES)
+def test_triangle_count_king2048(T):
+    """The 2048 x 2048 king grid of the triangle-counting workload at every tile
+    width: 4 (R - 1)(C - 1) triangles, and the oracle's count."""
+    g = gg.king_grid(2048, 2048)
+    print(f"tc king2048 T={T}", flush=True)
+    assert b2.triangle_count(g.rowptr, g.colind, g.n, T) == orc.tc(g) == 4 * 2047 * 2047
+
+
+def test_triangle_count_unmapped_rows():
+    """A wheel on 2^19 + 2^12 vertices at T = 4 has 132096 tile columns, more
+    than the product's LDS bitmap covers (131072): the hub's tile-row, and in A
+    every rim tile-row far from the hub, look tile columns up by binary search
+    in global memory instead.  Every triangle holds the hub, the largest id, so
+    all n - 1 lie in L's last tile-row and none before it; the A.A masked sum is
+    6 (n - 1).  (Closed forms: the oracle's merge over the hub's row of n - 1
+    entries per edge takes minutes here; the same forms are pinned against the
+    oracle on small wheels.)"""
+    n = (1 << 19) + (1 << 12)
+    g = gg.wheel(n)
+    print(f"tc wheel n={n} T=4", flush=True)
+    ntr = (n + 3) // 4
+    assert ntr > 131072
+    Ld = b2.B2SR.from_graph(g, 4, lower=True)
+    A = b2.B2SR.from_graph(g, 4)
+    assert int(b2.as_u64(b2.spgemm_masked(Ld, Ld, Ld))[0]) == n - 1
+    assert int(b2.as_u64(b2.spgemm_masked(A, A, A))[0]) == 6 * (n - 1)
+    # without the orientation workspace every mask tile scans Bt's row
+    for X, ref in ((Ld, n - 1), (A, 6 * (n - 1))):
+        plain = torch.zeros(1, dtype=torch.int64, device="cuda")
+        assert b2.lib().spgemm_masked(X.view, X.view, X.view, 0, b2._ptr(plain), None, 0, b2._stream()) == 0
+        assert int(b2.as_u64(plain)[0]) == ref
+    assert int(b2.as_u64(b2.spgemm_masked_rows(Ld, Ld, Ld, ntr - 1, ntr))[0]) == n - 1
+    assert int(b2.as_u64(b2.spgemm_masked_rows(Ld, Ld, Ld, 0, ntr - 1))[0]) == 0
 
 
 @pytest.mark.parametrize("T", TILES)

@@ -264,6 +264,16 @@ def test_tc_closed_forms_and_brute_force():
     for g in (gg.path(50), gg.star(40), gg.grid4(9, 11), gg.cycle(30)):
         assert orc.tc(g) == 0
     assert orc.tc(gg.cycle(3)) == 1
+    # wheels (rim cycle 0..n-2, hub n-1): n - 1 triangles, all holding the hub,
+    # the largest id; the A.A masked sum counts each of them 6 times
+    for n in (5, 9, 64, 300):
+        w = gg.wheel(n)
+        A = w.dense().astype(np.int64)
+        assert orc.tc(w) == n - 1 == int(np.trace(A @ A @ A)) // 6
+        assert orc.masked_sum(w, w, w) == 6 * (n - 1)
+        L = orc.tril(w)
+        hub_rows = gg.directed_csr(n, np.full(n - 1, n - 1), np.arange(n - 1))  # L's hub row alone
+        assert orc.masked_sum(L, L, hub_rows) == n - 1
     for g in TINY:
         A = g.dense().astype(np.int64)
         assert orc.tc(g) == int(np.trace(A @ A @ A)) // 6
