@@ -235,6 +235,27 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
                   const uint32_t *x_active, const uint32_t *mask, unsigned flags, double alpha,
                   double beta, void *y, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * spmv_bin_full_noalloc: spmv_bin_full for callers that cannot allocate device
+ *   memory (code under HIP graph capture, tight serving loops, harnesses that
+ *   forbid hipMalloc).  The same product, semantics, argument rules and errors
+ *   as spmv_bin_full, without a workspace argument: the workspace is a
+ *   library-owned device array of B2SR_NOALLOC_MAX_BYTES bytes, one per device
+ *   (each device holds it from the library's first use there until the process
+ *   ends).  The call allocates nothing and launches nothing when the workspace
+ *   spmv_bin_full_workspace_bytes would size (without col_scale: that size less
+ *   the 4n bytes of the scaled copy of x) exceeds the array: it returns
+ *   B2SR_ENOSPC then.  The array is addressed on the device current at the call,
+ *   so `stream` must belong to that device.  Every call on one device shares
+ *   its array, and no part of it needs clearing between calls; calls whose
+ *   execution overlaps on one device (different streams, or threads without
+ *   ordering) race on it, so the caller orders them.
+ */
+#define B2SR_NOALLOC_MAX_BYTES (64u << 20)
+int spmv_bin_full_noalloc(const b2sr_matrix *A, int semiring, const void *x, const float *col_scale,
+                          const uint32_t *x_active, const uint32_t *mask, unsigned flags, double alpha,
+                          double beta, void *y, hipStream_t stream);
+
 /* ---- masked matrix-matrix product, summed (Sec. IV, Table IV, Listing 2) ---
  * spgemm_masked: *d_sum (device uint64_t) receives
  *     s = sum_{(i,j) : M_ij = 1} (A * B)_ij,   (A * B)_ij = sum_k A_ik B_kj,

@@ -19,7 +19,7 @@ import torch
 
 __all__ = [
     "B2SRError", "B2SR", "lib", "b2sr_count_tiles", "b2sr_from_csr", "b2sr_pack_bits", "spmv_bin_bin",
-    "spmv_bin_full", "spmv_bin_full_workspace_bytes", "spgemm_masked", "spgemm_masked_workspace_bytes",
+    "spmv_bin_full", "spmv_bin_full_workspace_bytes", "spmv_bin_full_noalloc", "spgemm_masked", "spgemm_masked_workspace_bytes",
     "spgemm_masked_profile", "spgemm_masked_rows", "b2sr_pagerank_directed", "b2sr_csr_transpose", "b2sr_mis", "b2sr_color",
     "mis_keys", "b2sr_eccentricity", "b2sr_diameter",
     "b2sr_algo_workspace_bytes", "b2sr_bfs", "b2sr_msbfs", "b2sr_sssp", "b2sr_cc", "b2sr_pagerank",
@@ -79,6 +79,7 @@ _SIGS = {
     "spmv_bin_bin": (_I, [_MP, _P, _P, ctypes.c_uint, _P, _P]),
     "spmv_bin_full_workspace_bytes": (_SZ, [_MP, _I]),
     "spmv_bin_full": (_I, [_MP, _I, _P, _P, _P, _P, ctypes.c_uint, _D, _D, _P, _P, _SZ, _P]),
+    "spmv_bin_full_noalloc": (_I, [_MP, _I, _P, _P, _P, _P, ctypes.c_uint, _D, _D, _P, _P]),
     "spgemm_masked_workspace_bytes": (_SZ, [_MP, _MP]),
     "spgemm_masked": (_I, [_MP, _MP, _MP, ctypes.c_uint, _P, _P, _SZ, _P]),
     "spgemm_masked_profile": (_I, [_MP, _MP, _MP, _P, _P]),
@@ -284,6 +285,18 @@ def spmv_bin_full(A: B2SR, semiring: int, x, col_scale=None, mask=None, compleme
     _check(lib().spmv_bin_full(A.view, semiring, _ptr(x), _ptr(col_scale), _ptr(x_active), _ptr(mask), flags, float(alpha),
                                float(beta), _ptr(out), _ptr(ws), need if ws is not None else 0, _stream()),
            "spmv_bin_full")
+    return out
+
+
+def spmv_bin_full_noalloc(A: B2SR, semiring: int, x, col_scale=None, mask=None, complement=False,
+                          self_loop=False, accumulate=False, alpha=1.0, beta=0.0, out=None, x_active=None):
+    """spmv_bin_full with the library's own scratch array as its workspace (no
+    device allocation inside the call; ``out`` must be given for that)."""
+    flags = (MASK_COMPLEMENT if complement else 0) | (SELF if self_loop else 0) | (ACCUMULATE if accumulate else 0)
+    if out is None:
+        out = torch.empty(A.n, dtype=_FULL_DTYPE[semiring], device="cuda")
+    _check(lib().spmv_bin_full_noalloc(A.view, semiring, _ptr(x), _ptr(col_scale), _ptr(x_active), _ptr(mask), flags,
+                                       float(alpha), float(beta), _ptr(out), _stream()), "spmv_bin_full_noalloc")
     return out
 
 

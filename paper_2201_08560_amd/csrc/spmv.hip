@@ -28,6 +28,8 @@
 // Masks are applied when a row is stored (Sec. V, BFS).  Blocks whose rows are
 // all masked out are not read, and with B2SR_SPARSE_X tiles whose x segment is
 // empty are not read either.
+#include <atomic>
+
 #include "spmv_core.h"
 
 using namespace b2sr_dev;
@@ -228,37 +230,9 @@ size_t plus_partials_bytes(const b2sr_matrix *A)
     return (size_t)((rows_bytes + nchunks * 2 * A->tile * 4 + 255) & ~255ull);
 }
 
-}  // namespace
-
-extern "C" {
-
-int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, unsigned flags, void *y,
-                 hipStream_t stream)
-{
-    int rc = b2sr::validate_matrix(A);
-    if (rc) return rc;
-    if (flags & ~(B2SR_MASK_COMPLEMENT | B2SR_OUT_COUNT | B2SR_ACCUMULATE | B2SR_SPARSE_X)) return B2SR_EINVAL;
-    if (A->n > 0 && (!x || !y)) return B2SR_EINVAL;
-    if (A->n == 0) return B2SR_OK;
-    if ((const void *)x == y || (const void *)mask == y) return B2SR_EINVAL;
-    SpmvArgs p = make_args(A);
-    p.x = x;
-    p.mask = mask;
-    p.flags = flags;
-    p.y = y;
-    if (flags & B2SR_OUT_COUNT) return dispatch<kCount>(A->tile, p, stream);
-    return dispatch<kBits>(A->tile, p, stream);
-}
-
-size_t spmv_bin_full_workspace_bytes(const b2sr_matrix *A, int semiring)
-{
-    if (!A || !b2sr::valid_tile(A->tile) || semiring != B2SR_PLUS_TIMES_F32) return 0;
-    return plus_partials_bytes(A) + (size_t)A->n * 4;
-}
-
-int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float *col_scale,
-                  const uint32_t *x_active, const uint32_t *mask, unsigned flags, double alpha, double beta,
-                  void *y, void *ws, size_t ws_bytes, hipStream_t stream)
+int full_product(const b2sr_matrix *A, int semiring, const void *x, const float *col_scale,
+                 const uint32_t *x_active, const uint32_t *mask, unsigned flags, double alpha, double beta,
+                 void *y, void *ws, size_t ws_bytes, hipStream_t stream)
 {
     int rc = b2sr::validate_matrix(A);
     if (rc) return rc;
@@ -306,6 +280,87 @@ int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float
     case B2SR_MAX_TIMES_U64: return dispatch<kMaxU64>(A->tile, p, stream);
     default: return dispatch<kOr64>(A->tile, p, stream);
     }
+}
+
+
+
+// ---- the no-allocation variant's scratch ------------------------------------
+// A file-scope device array serves spmv_bin_full_noalloc as its workspace, so
+// that the call allocates nothing.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in for the symbol): its device
+// address is taken once per device with hipGetSymbolAddress, with that device
+// current, and kept here.
+static __device__ __align__(256) unsigned char scratch[B2SR_NOALLOC_MAX_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::atomic<void *> g_scratch_ptr[kMaxDevices];  // per device; null until its first call
+
+int scratch_on_current_device(void **out)
+{
+    int dev = 0;
+    if (int rc = b2sr::check(hipGetDevice(&dev), "hipGetDevice")) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return B2SR_ENOTSUP;
+    void *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        // two threads racing here store the same address
+        if (int rc = b2sr::check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))
+            return rc;
+        if (!p) return B2SR_EHIP;
+        g_scratch_ptr[dev].store(p, std::memory_order_release);
+    }
+    *out = p;
+    return B2SR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spmv_bin_bin(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, unsigned flags, void *y,
+                 hipStream_t stream)
+{
+    int rc = b2sr::validate_matrix(A);
+    if (rc) return rc;
+    if (flags & ~(B2SR_MASK_COMPLEMENT | B2SR_OUT_COUNT | B2SR_ACCUMULATE | B2SR_SPARSE_X)) return B2SR_EINVAL;
+    if (A->n > 0 && (!x || !y)) return B2SR_EINVAL;
+    if (A->n == 0) return B2SR_OK;
+    if ((const void *)x == y || (const void *)mask == y) return B2SR_EINVAL;
+    SpmvArgs p = make_args(A);
+    p.x = x;
+    p.mask = mask;
+    p.flags = flags;
+    p.y = y;
+    if (flags & B2SR_OUT_COUNT) return dispatch<kCount>(A->tile, p, stream);
+    return dispatch<kBits>(A->tile, p, stream);
+}
+
+size_t spmv_bin_full_workspace_bytes(const b2sr_matrix *A, int semiring)
+{
+    if (!A || !b2sr::valid_tile(A->tile) || semiring != B2SR_PLUS_TIMES_F32) return 0;
+    return plus_partials_bytes(A) + (size_t)A->n * 4;
+}
+
+int spmv_bin_full(const b2sr_matrix *A, int semiring, const void *x, const float *col_scale,
+                  const uint32_t *x_active, const uint32_t *mask, unsigned flags, double alpha, double beta,
+                  void *y, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return full_product(A, semiring, x, col_scale, x_active, mask, flags, alpha, beta, y, ws, ws_bytes, stream);
+}
+
+int spmv_bin_full_noalloc(const b2sr_matrix *A, int semiring, const void *x, const float *col_scale,
+                          const uint32_t *x_active, const uint32_t *mask, unsigned flags, double alpha,
+                          double beta, void *y, hipStream_t stream)
+{
+    // sizes are checked on the host first: nothing is launched for a call that
+    // does not fit the scratch array
+    if (int rc = b2sr::validate_matrix(A)) return rc;
+    const size_t need = semiring != B2SR_PLUS_TIMES_F32 ? 0
+                      : col_scale ? spmv_bin_full_workspace_bytes(A, semiring) : plus_partials_bytes(A);
+    if (need > B2SR_NOALLOC_MAX_BYTES) return B2SR_ENOSPC;
+    void *ws = nullptr;
+    if (int rc = scratch_on_current_device(&ws)) return rc;
+    return full_product(A, semiring, x, col_scale, x_active, mask, flags, alpha, beta, y, ws,
+                        B2SR_NOALLOC_MAX_BYTES, stream);
 }
 
 }  // extern "C"
