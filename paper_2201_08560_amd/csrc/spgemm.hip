@@ -68,6 +68,10 @@ constexpr uint32_t kHitCap = 64 * kUB;  // matched tile pairs of one round (T >=
 #define B2SR_TC_SWAP_CHUNK 128
 #endif
 constexpr uint32_t kSwapChunk = B2SR_TC_SWAP_CHUNK;  // swapped mask tiles per work item
+#ifndef B2SR_TC_OWN_CHUNK
+#define B2SR_TC_OWN_CHUNK 64
+#endif
+constexpr uint32_t kOwnChunk = B2SR_TC_OWN_CHUNK;  // a row's own mask tiles per work item
 
 struct GemmArgs {
     const uint32_t *a_rp, *a_ci;
@@ -87,9 +91,10 @@ struct GemmArgs {
     // Null: every mask tile scans Bt's row J.
     const uint32_t *sw_off, *sw_list;
     // Work items when sw_off is set: (row | 2^31 for a swapped chunk, e0, e1)
-    // triples; item_off[ntr] of them.  A row's own mask tiles are one item,
-    // its list of swapped tiles is cut into chunks of kSwapChunk entries, so
-    // that a long row's list is spread over many workgroups.
+    // triples; item_off[ntr] of them.  A row's own mask tiles are cut into
+    // ranges of kOwnChunk tiles [e0, e1) of M's tile list, its list of swapped
+    // tiles into chunks of kSwapChunk entries, so that the work of a long row
+    // is spread over many workgroups.
     const uint32_t *item_off, *items;
     uint32_t items_bound;  // an upper bound of item_off[ntr] (the launch's grid)
 };
@@ -171,7 +176,7 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
     // so that small matrices leave room for more workgroups per CU
     extern __shared__ uint32_t s_dyn[];
     uint32_t *const s_map = s_dyn, *const s_pre = s_dyn + g.map_words;
-    __shared__ uint32_t s_thr[kThreads];
+    __shared__ uint32_t s_thr[kWaves];
     __shared__ uint16_t s_pairs[kWaves][T * T];
     __shared__ uint2 s_hits[kItems ? kWaves : 1][kItems ? kHitCap : 1];
     const uint32_t lane = lane_id(), wv = threadIdx.x / B2SR_WAVE;
@@ -180,16 +185,18 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
 
     const uint32_t nwork = g.sw_off ? g.item_off[g.ntr] : g.row1 - g.row0;
     for (uint32_t wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
-        uint32_t I = g.row0 + wk, s0 = 0, s1 = 0;
-        bool own = true;  // this row's own mask tiles (else a chunk of its swapped list)
+        uint32_t I = g.row0 + wk, s0 = 0, s1 = 0, m0 = 0, m1 = 0;
         if (g.sw_off) {
+            // a range of this row's own mask tiles, or a chunk of its swapped list
             const uint32_t x = g.items[3 * (size_t)wk];
             I = x & 0x7FFFFFFFu;
-            own = !(x >> 31);
-            s0 = g.items[3 * (size_t)wk + 1];
-            s1 = g.items[3 * (size_t)wk + 2];
+            uint32_t e0 = g.items[3 * (size_t)wk + 1], e1 = g.items[3 * (size_t)wk + 2];
+            if (x >> 31) { s0 = e0; s1 = e1; }
+            else { m0 = e0; m1 = e1; }
+        } else {
+            m0 = g.m_rp[I];
+            m1 = g.m_rp[I + 1];
         }
-        const uint32_t m0 = own ? g.m_rp[I] : 0u, m1 = own ? g.m_rp[I + 1] : 0u;
         const uint32_t a0 = g.a_rp[I], a1 = g.a_rp[I + 1];
         if ((m0 == m1 && s0 == s1) || a0 == a1) continue;  // workgroup-uniform
         const uint32_t jlo = g.a_ci[a0], jhi = g.a_ci[a1 - 1];
@@ -209,18 +216,17 @@ template <int T, bool PROFILE = false> __global__ void __launch_bounds__(kThread
             const uint32_t w0 = threadIdx.x * per, w1 = min(nw, w0 + per);
             uint32_t local = 0;
             for (uint32_t w = w0; w < w1; ++w) local += __popc(s_map[w]);
-            s_thr[threadIdx.x] = local;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                uint32_t run = 0;
-                for (int k = 0; k < kThreads; ++k) {
-                    const uint32_t t = s_thr[k];
-                    s_thr[k] = run;
-                    run += t;
-                }
+            // exclusive prefix of the threads' counts: a scan within each wave,
+            // then the totals of the waves before
+            uint32_t inc = local;
+            for (uint32_t d = 1; d < 64; d <<= 1) {
+                const uint32_t o = shfl_up(inc, d);
+                if (lane >= d) inc += o;
             }
+            if (lane == 63) s_thr[wv] = inc;
             __syncthreads();
-            uint32_t run = s_thr[threadIdx.x];
+            uint32_t run = inc - local;
+            for (uint32_t k = 0; k < wv; ++k) run += s_thr[k];
             for (uint32_t w = w0; w < w1; ++w) {
                 s_pre[w] = run;
                 run += __popc(s_map[w]);
@@ -434,13 +440,13 @@ __global__ void swap_fill_kernel(GemmArgs g, uint32_t *cursor, uint32_t *list)
     }
 }
 
-// Work items per row: one for its own mask tiles (when it has any and A's row
-// is not empty), one per kSwapChunk entries of its swapped list.
+// Work items per row: one per kOwnChunk of its own mask tiles (when A's row is
+// not empty), one per kSwapChunk entries of its swapped list.
 __global__ void item_count_kernel(GemmArgs g, const uint32_t *off, uint32_t *counts)
 {
     for (uint32_t X = blockIdx.x * blockDim.x + threadIdx.x; X < g.ntr; X += gridDim.x * blockDim.x) {
-        const bool own = g.m_rp[X + 1] > g.m_rp[X] && g.a_rp[X + 1] > g.a_rp[X];
-        counts[X] = (own ? 1u : 0u) + (off[X + 1] - off[X] + kSwapChunk - 1) / kSwapChunk;
+        const uint32_t own = g.a_rp[X + 1] > g.a_rp[X] ? g.m_rp[X + 1] - g.m_rp[X] : 0u;
+        counts[X] = (own + kOwnChunk - 1) / kOwnChunk + (off[X + 1] - off[X] + kSwapChunk - 1) / kSwapChunk;
     }
 }
 
@@ -448,11 +454,12 @@ __global__ void item_fill_kernel(GemmArgs g, const uint32_t *off, const uint32_t
 {
     for (uint32_t X = blockIdx.x * blockDim.x + threadIdx.x; X < g.ntr; X += gridDim.x * blockDim.x) {
         size_t w = item_off[X];
-        if (g.m_rp[X + 1] > g.m_rp[X] && g.a_rp[X + 1] > g.a_rp[X]) {
-            items[3 * w] = X;
-            items[3 * w + 1] = 0;
-            items[3 * w + 2] = 0;
-            ++w;
+        if (g.a_rp[X + 1] > g.a_rp[X]) {
+            for (uint32_t e = g.m_rp[X]; e < g.m_rp[X + 1]; e += kOwnChunk, ++w) {
+                items[3 * w] = X;
+                items[3 * w + 1] = e;
+                items[3 * w + 2] = min(g.m_rp[X + 1], e + kOwnChunk);
+            }
         }
         for (uint32_t e = off[X]; e < off[X + 1]; e += kSwapChunk, ++w) {
             items[3 * w] = X | 0x80000000u;
@@ -487,8 +494,8 @@ SwapLayout swap_layout(const b2sr_matrix *A, const b2sr_matrix *M, void *ws)
     L.cursor = take(ntr * 4);
     L.list = take((size_t)M->ntiles * 8);
     L.item_off = take((ntr + 1) * 4);
-    // at most one item per row for its own tiles plus one per started chunk
-    L.items = take((2 * ntr + (size_t)M->ntiles / kSwapChunk + 1) * 12);
+    // per row, one item per started chunk of its own tiles and of its swapped list
+    L.items = take((2 * ntr + (size_t)M->ntiles / kOwnChunk + (size_t)M->ntiles / kSwapChunk + 1) * 12);
     L.sums = take(b2sr_scan::scan_blocks(ntr) * 4);
     L.bytes = o;
     return L;
@@ -529,7 +536,8 @@ int build_swap_lists(GemmArgs &g, const b2sr_matrix *A, const b2sr_matrix *M, vo
     g.sw_list = L.list;
     g.item_off = L.item_off;
     g.items = L.items;
-    g.items_bound = (uint32_t)std::min<uint64_t>(0xFFFFFFFFu, 2ull * ntr + M->ntiles / kSwapChunk + 1);
+    g.items_bound = (uint32_t)std::min<uint64_t>(
+        0xFFFFFFFFu, 2ull * ntr + M->ntiles / kOwnChunk + M->ntiles / kSwapChunk + 1);
     return B2SR_OK;
 }
 

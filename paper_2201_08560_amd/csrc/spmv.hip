@@ -159,6 +159,7 @@ template <int T, int K> int launch(SpmvArgs p, hipStream_t stream)
     if constexpr (!Cfg<T, K>::kStage)
         short_blocks = (p.flags & B2SR_SPARSE_X) || (uint64_t)p.ntiles < (uint64_t)p.ntr * Cfg<T, K>::BT;
     p.chunk = short_blocks ? chunk_tiles<T, K, true>(p.ntiles) : chunk_tiles<T, K>(p.ntiles);
+    p.x_whole = p.n % T == 0;
     const uint32_t nchunks = (uint32_t)((p.ntiles + (uint64_t)p.chunk - 1) / p.chunk);
     if (!(p.flags & B2SR_ACCUMULATE) || K >= kPlusF32) {
         if constexpr (K == kBits) {

@@ -29,6 +29,9 @@
 #ifndef B2SR_NT_TILES
 #define B2SR_NT_TILES 1          // stream tile bits with nontemporal loads
 #endif
+#ifndef B2SR_FAST_BLOCKS
+#define B2SR_FAST_BLOCKS 1       // value products at T >= 32: the lean path for whole in-row blocks
+#endif
 
 namespace b2sr_core {
 
@@ -96,6 +99,7 @@ struct SpmvArgs {
     void *y;
     uint32_t *ws_rows;  // float sums: first and last row of each chunk
     float *ws_part;     // float sums: partials of straddling rows, 2*T per chunk
+    uint32_t x_whole;   // n is a multiple of T: no x segment is cut short
 };
 
 // Block shape per tile width and kind.  Bit and count products read the x
@@ -330,6 +334,91 @@ __device__ __forceinline__ void store_values(const SpmvArgs &p, uint32_t I, uint
 // LDS per wave for the staged kinds (the same for every T and kind).
 constexpr uint32_t kStageBytesPerWave = B2SR_STAGE_BYTES;
 
+// A whole block of BT tiles of one tile-row, for the value products with
+// 4-byte values at T >= 32 (wave-uniform conditions checked by the caller: the
+// block lies before the chunk's end and inside the current tile-row, every x
+// segment is whole, no x_active).  Lane l reads piece l of each step's run of
+// tiles at a fixed offset from the block's first tile (no per-lane bounds or
+// zero-tile selection), the x segments go to LDS by global-to-LDS loads, and
+// each bit-row costs one LDS read for its lowest set bit; rows with more set
+// bits (rare at these widths on sparse graphs) take a loop.  Sums are folded
+// into acc in bit order, the same fixed order as the general path.
+// J holds the block's tile columns (lane l: tile blk + l) on entry and the next
+// block's on exit, loaded ahead so that the x loads never wait for them.
+template <int T, int K>
+__device__ __forceinline__ void fast_block(const SpmvArgs &p, uint32_t blk, uint32_t t_end,
+                                           typename KindTraits<K>::V *xs,
+                                           typename KindTraits<K>::V (&acc)[TileShape<T>::RPL], uint32_t &J)
+{
+    using C = Cfg<T, K>;
+    using KT = KindTraits<K>;
+    using V = typename KT::V;
+    using R = row_t<T>;
+    using Piece = typename PieceT<T>::type;
+    constexpr int RPL = C::RPL, TPW = C::TPW, U = C::U, BT = C::BT, XW = C::XW, LPT = C::LPT;
+    static_assert(BT <= 64 && C::VB == 4 && T >= 32, "fast block shape");
+    const uint32_t lane = lane_id(), grp = lane / LPT, sub = lane % LPT;
+    // the x offsets first, from the columns loaded a block ago (landed at the
+    // last block's barrier), so that nothing below waits on a load of this block
+    uint32_t xo[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) xo[i] = shfl(J, (int)(i * TPW + grp)) * T + sub * XW;
+    __builtin_amdgcn_sched_barrier(0);  // no load of this block is moved above the offsets
+    J = p.tci[min(blk + BT + min(lane, (uint32_t)BT - 1), t_end - 1)];
+    Piece pc[U];
+    if constexpr (T == 64) {
+        const u32x4 *q = (const u32x4 *)p.bits + (size_t)blk * 32;
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const u32x4 lo = load_stream(q + (i * 128 + 2 * lane)), hi = load_stream(q + (i * 128 + 2 * lane + 1));
+            pc[i] = u32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+        }
+    } else {
+        const u32x4 *q = (const u32x4 *)p.bits + (size_t)blk * 8;
+#pragma unroll
+        for (int i = 0; i < U; ++i) pc[i] = load_stream(q + (i * 64 + lane));
+    }
+    const uint32_t xs_lds = readfirstlane((uint32_t)(uintptr_t)xs);
+#pragma unroll
+    for (int i = 0; i < U; ++i)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)((const V *)p.x + xo[i]),
+                                         (__attribute__((address_space(3))) void *)(uintptr_t)(xs_lds + i * TPW * T * 4),
+                                         16, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);  // every load is issued before the first wait
+    // the global-to-LDS loads count in vmcnt: wait for all of them explicitly
+    // before any LDS read, rather than rely on the compiler's alias analysis
+    __builtin_amdgcn_s_waitcnt(0);
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        R a[RPL];
+        piece_rows<T>(pc[i], a);
+        const V *xt = xs + (i * TPW + grp) * T;
+        V v[RPL];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) v[k] = xt[a[k] ? ctz_row(a[k]) : 0u];
+        R more = 0;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            acc[k] = KT::op(acc[k], a[k] ? v[k] : KT::id());
+            a[k] &= a[k] - 1;
+            more |= a[k];
+        }
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                R w = a[k];
+                while (w) {
+                    const uint32_t c = ctz_row(w);
+                    w &= w - 1;
+                    acc[k] = KT::op(acc[k], xt[c]);
+                }
+            }
+        }
+    }
+    wave_lds_sync();  // the next block's LDS writes follow these reads
+}
+
 // Processes tile chunk chunk_id (wave-uniform) of the product described by p.
 // xs is this wave's LDS slice (unused by bit and count products).
 template <int T, int K, bool ACT = false, bool SHORT = false>
@@ -380,10 +469,21 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
     };
 
     uint32_t blk = t_begin;
+    // fast blocks: the tile columns of block jf_blk, loaded one block ahead
+    [[maybe_unused]] uint32_t jf = 0, jf_blk = 0xFFFFFFFFu;
     while (blk < t_end) {
         if (min(blk + BT, t_end) - 1 < r_end && !keep) {  // the block lies in a row masked out entirely
             blk = min(r_end, t_end);
             continue;
+        }
+        if constexpr (B2SR_FAST_BLOCKS && C::kStage && !ACT && T >= 32 && C::VB == 4) {
+            if (p.x_whole && blk + BT <= t_end && blk + BT - 1 < r_end) {
+                if (jf_blk != blk) jf = p.tci[blk + min(lane, (uint32_t)BT - 1)];
+                fast_block<T, K>(p, blk, t_end, xs, acc, jf);
+                blk += BT;
+                jf_blk = blk;
+                continue;
+            }
         }
         // ---- load phase: tile columns (one per lane), tile pieces, x segments.
         // No load sits under a per-lane branch (lanes past the chunk read its
@@ -480,7 +580,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
             // At T = 32 with 4-byte values a step's segments are one 16-byte quad per
             // lane at slot i * 1024 + 16 * lane: exactly where a global-to-LDS load
             // puts lane l's quad, so those bytes need no registers.
-            constexpr bool kDma = B2SR_X_DMA && T == 32 && NQ == 1;
+            constexpr bool kDma = B2SR_X_DMA && T >= 32 && NQ == 1;
             if (kDma && quads) {
 #pragma unroll
                 for (int i = 0; i < U; ++i)
@@ -521,6 +621,7 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                     }
                 }
             }
+            if constexpr (kDma) __builtin_amdgcn_s_waitcnt(0);  // the global-to-LDS loads have landed
             wave_lds_sync();
         }
 
