@@ -22,7 +22,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# B2SR_ORACLE_LIB names another build of oracle.c (the sanitizer test's)
+_LIB = os.environ.get("B2SR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 UNREACHED = 0xFFFFFFFF
 
 _u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
@@ -49,7 +50,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.environ.get("B2SR_ORACLE_LIB") and (
+                not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build(force=True)
         L = ctypes.CDLL(_LIB)
         L.orc_num_threads.restype = ctypes.c_int

@@ -29,7 +29,8 @@ __all__ = [
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libb2sr.so")
+# B2SR_LIB names another build of the same sources (the sanitizer test's host-instrumented one)
+LIB_PATH = os.environ.get("B2SR_LIB") or os.path.join(_HERE, "libb2sr.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "b2sr.h")
 
 # flags and semirings (values from include/b2sr.h)

@@ -25,8 +25,13 @@ def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+def build(verbose: bool = False, jobs: int | None = None, extra_flags: list[str] | None = None,
+          out: str | None = None) -> str:
+    """Builds the library (at `out`, default the package's libb2sr.so) with the
+    standard flags plus `extra_flags`."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    lib = out or LIB
+    flags = HIPCC_FLAGS + list(extra_flags or [])
     inc = ["-I", os.path.join(REPO, "include"), "-I", os.path.join(HERE, "csrc")]
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
@@ -35,20 +40,20 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
         def compile_one(pair):
             src, obj = pair
-            cmd = [hipcc, *HIPCC_FLAGS, *inc, "-c", src, "-o", obj]
+            cmd = [hipcc, *flags, *inc, "-c", src, "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             subprocess.run(cmd, check=True)
 
         with ThreadPoolExecutor(jobs) as pool:
             list(pool.map(compile_one, zip(srcs, objs)))
-        tmp = LIB + ".tmp"
+        tmp = lib + ".tmp"
         link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
         if verbose:
             print(" ".join(link), flush=True)
         subprocess.run(link, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
