@@ -151,11 +151,11 @@ __global__ void batch_advance_kernel(uint32_t *flags, uint32_t max_levels)
 template <int T>
 __global__ void __launch_bounds__(256) batch_product_kernel(SpmvArgs p, uint32_t nchunks, const uint32_t *flags)
 {
-    __shared__ __align__(16) uint64_t s_x[4 * kStageBytesPerWave / sizeof(uint64_t)];
+    __shared__ __align__(16) uint64_t s_x[4 * kSliceBytes / sizeof(uint64_t)];
     if (flags[6]) return;
     const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     if (wave >= nchunks) return;
-    spmv_chunk<T, kOr64, true>(p, wave, s_x + (threadIdx.x / B2SR_WAVE) * (kStageBytesPerWave / sizeof(uint64_t)));
+    spmv_chunk<T, kOr64, true>(p, wave, s_x + (threadIdx.x / B2SR_WAVE) * (kSliceBytes / sizeof(uint64_t)));
 }
 
 template <int T> __device__ __forceinline__ void run_chunk(const Group &g, uint32_t c, uint64_t *xs)
@@ -244,8 +244,8 @@ constexpr unsigned kPersistThreads = B2SR_PERSIST_THREADS;
 template <unsigned TMASK>
 __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batch_persistent_kernel(BatchArgs b)
 {
-    __shared__ __align__(16) uint64_t s_x[kPersistThreads / B2SR_WAVE * kStageBytesPerWave / sizeof(uint64_t)];
-    uint64_t *xs = s_x + (threadIdx.x / B2SR_WAVE) * (kStageBytesPerWave / sizeof(uint64_t));
+    __shared__ __align__(16) uint64_t s_x[kPersistThreads / B2SR_WAVE * kSliceBytes / sizeof(uint64_t)];
+    uint64_t *xs = s_x + (threadIdx.x / B2SR_WAVE) * (kSliceBytes / sizeof(uint64_t));
     const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     const uint32_t nwaves = gridDim.x * (blockDim.x / B2SR_WAVE);
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -81,11 +81,11 @@ __global__ void __launch_bounds__(256, waves_hint(T, K)) spmv_kernel(SpmvArgs p)
 {
     using V = typename KindTraits<K>::V;
     constexpr bool stage = Cfg<T, K>::kStage;
-    __shared__ __align__(16) V s_x[stage ? 4 * kStageBytesPerWave / sizeof(V) : 1];
+    __shared__ __align__(16) V s_x[stage ? 4 * kSliceBytes / sizeof(V) : 1];
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     if (wave * p.chunk >= p.ntiles) return;
     spmv_chunk<T, K, ACT, SHORT>(p, (uint32_t)wave,
-                                 s_x + (stage ? (threadIdx.x / B2SR_WAVE) * kStageBytesPerWave / sizeof(V) : 0));
+                                 s_x + (stage ? (threadIdx.x / B2SR_WAVE) * kSliceBytes / sizeof(V) : 0));
 }
 
 // Float sums of rows that straddle chunks.  One thread per (chunk, row of a

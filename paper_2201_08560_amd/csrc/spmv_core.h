@@ -333,6 +333,17 @@ __device__ __forceinline__ void store_values(const SpmvArgs &p, uint32_t I, uint
 
 // LDS per wave for the staged kinds (the same for every T and kind).
 constexpr uint32_t kStageBytesPerWave = B2SR_STAGE_BYTES;
+// A wave's LDS slice: the staged segments, then 16 bytes whose first value is
+// the semiring's identity (the value an empty bit-row reads).
+constexpr uint32_t kSliceBytes = kStageBytesPerWave + 16;
+
+// The staged x value a bit-row selects first: the value of its lowest set bit
+// in the tile's staged segment xt, or, for an empty row, the identity slot
+// after the wave's slice xs.
+template <class V, class R> __device__ __forceinline__ V xt_or_id(const V *xt, R row, const V *xs)
+{
+    return row ? xt[ctz_row(row)] : xs[kStageBytesPerWave / sizeof(V)];
+}
 
 // A whole block of BT tiles of one tile-row, for the value products with
 // 4-byte values at T >= 32 (wave-uniform conditions checked by the caller: the
@@ -396,11 +407,14 @@ __device__ __forceinline__ void fast_block(const SpmvArgs &p, uint32_t blk, uint
         const V *xt = xs + (i * TPW + grp) * T;
         V v[RPL];
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) v[k] = xt[a[k] ? ctz_row(a[k]) : 0u];
+        // an empty row reads the identity slot after the slice: one address for
+        // all such lanes is a broadcast (each tile's own first value would
+        // conflict across the step's tiles, whose segments all start at bank 0)
+        for (int k = 0; k < RPL; ++k) v[k] = xt_or_id(xt, a[k], xs);
         R more = 0;
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
-            acc[k] = KT::op(acc[k], a[k] ? v[k] : KT::id());
+            acc[k] = KT::op(acc[k], v[k]);
             a[k] &= a[k] - 1;
             more |= a[k];
         }
@@ -439,6 +453,11 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
     const uint32_t t_begin = chunk_id * p.chunk;
     const uint32_t t_end = min(t_begin + p.chunk, p.ntiles);
 
+    if constexpr (C::kStage) {
+        // the identity slot after the slice (read by empty rows, after the first
+        // staging's LDS sync)
+        if (lane == 0) xs[kStageBytesPerWave / sizeof(V)] = KT::id();
+    }
     const uint32_t r_first = find_row(p.trp, p.ntr, t_begin);
     uint32_t r_cur = r_first;
     uint32_t r_end = p.trp[r_cur + 1];
@@ -663,11 +682,11 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                             // the sum order within a row is unchanged
                             V v[RPL];
 #pragma unroll
-                            for (int k = 0; k < RPL; ++k) v[k] = xt[a[k] ? ctz_row(a[k]) : 0u];
+                            for (int k = 0; k < RPL; ++k) v[k] = xt_or_id(xt, a[k], xs);  // empty rows: a broadcast
                             any = 0;
 #pragma unroll
                             for (int k = 0; k < RPL; ++k) {
-                                if (a[k]) part[k] = KT::op(part[k], v[k]);
+                                part[k] = KT::op(part[k], v[k]);
                                 a[k] &= a[k] - 1;
                                 any |= a[k];
                             }
