@@ -12,15 +12,22 @@ HBM.  One step runs every product of the path once over it:
   * BFS from 64 seeded sources as one 64-wide bit-frontier BFS;
   * SSSP (unit weights) from the first source; CC by min-label propagation;
   * 50 PageRank iterations (d = 0.85) in float32.
-value = edges evaluated per second over the step: every matrix product in the
-step counts nnz(A) edges (the product is computed over the whole matrix; tiles
-that cannot contribute are skipped, which changes no result).
+value = edges evaluated per second over the step: a product over the whole
+matrix counts nnz(A); a product that reads only the tiles of its active
+columns (the BFS levels, SSSP and CC iterations) counts the nonzeros inside
+the tiles it reads, which the bench derives exactly from the step's own
+outputs (the tile bytes read per product are reported too).
 
-Also reported (same process, outside the timed step): the CSR -> B2SR
-conversion time, single-source BFS GTEPS (Graph500 style), triangle counting
-(masked SpGEMM) edges/s on R-MAT scale 18 and a 2048 x 2048 king grid for tile
-widths 4..32, the roofline of the headline kernel (masked bin x bin SpMV,
-measured with HIP events on its stream), and the CPU oracle timed on the host.
+Also reported (same process, outside the timed step): the roofline of the
+step's dominant kernel (the plus-times product) and of the headline masked
+bin x bin product, both measured with HIP events on their stream; the CSR ->
+B2SR conversion time; single-source BFS GTEPS (Graph500 style); the
+correctness-scale workload (ER n = 4096, B2SR-8); B2SR storage and product
+times at every tile width (4 .. 64) on R-MAT s20, the king grid and a
+Mycielski graph; the measured autotuner's choice; triangle counting (masked
+SpGEMM) on R-MAT scale 18 and a 2048 x 2048 king grid for every tile width;
+batched against per-graph BFS; serving at several offered rates; and the CPU
+oracle timed on the host (whose results also verify the step's outputs).
 """
 from __future__ import annotations
 
@@ -70,10 +77,10 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(digest: str):
-    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they
-    were taken on the current kernel source."""
-    path = os.path.join(PROFILES, "spmv_bits_t32_rmat20_pmc.txt")
+def read_traffic(digest: str, name: str):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel source."""
+    path = os.path.join(PROFILES, name)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -129,7 +136,9 @@ class Workload:
         self.labels = torch.empty(n, dtype=torch.int32, device="cuda")
         self.rank = torch.empty(n, dtype=torch.float32, device="cuda")
         self.ev = []
+        self.ev_plus = []
         self.products = 0
+        self.it_msbfs = self.it_sssp = self.it_cc = 0
 
     def step(self, record: bool):
         A = self.A
@@ -146,18 +155,169 @@ class Workload:
             e1.record()
             self.ev.append((e0, e1))
         b2.spmv_bin_bin(A, self.x_full, None, count=True, out=self.y_cnt)
+        # the step's dominant kernel: the plus-times product (PageRank's), bracketed the same way
+        if record:
+            p0 = torch.cuda.Event(enable_timing=True)
+            p1 = torch.cuda.Event(enable_timing=True)
+            p0.record()
         b2.spmv_bin_full(A, b2.PLUS_TIMES_F32, self.xf, out=self.y_f, ws=self.ws_plus)
+        if record:
+            p1.record()
+            self.ev_plus.append((p0, p1))
         b2.spmv_bin_full(A, b2.MIN_PLUS_F32, self.xd, self_loop=True, alpha=1.0, out=self.y_f2)
         prods += 4
-        _, it = b2.b2sr_msbfs(A, self.sources, out=self.lv_multi, ws=self.ws[b2.ALGO_MSBFS])
-        prods += it
-        _, it = b2.b2sr_sssp(A, int(self.sources[0]), out=self.dist, ws=self.ws[b2.ALGO_SSSP])
-        prods += it
-        _, it = b2.b2sr_cc(A, out=self.labels, ws=self.ws[b2.ALGO_CC])
-        prods += it
+        _, self.it_msbfs = b2.b2sr_msbfs(A, self.sources, out=self.lv_multi, ws=self.ws[b2.ALGO_MSBFS])
+        _, self.it_sssp = b2.b2sr_sssp(A, int(self.sources[0]), out=self.dist, ws=self.ws[b2.ALGO_SSSP])
+        _, self.it_cc = b2.b2sr_cc(A, out=self.labels, ws=self.ws[b2.ALGO_CC])
+        prods += self.it_msbfs + self.it_sssp + self.it_cc
         b2.b2sr_pagerank(A, 0.85, 50, out=self.rank, ws=self.ws[b2.ALGO_PAGERANK])
         prods += 51  # 50 iterations + the degree count
         self.products = prods
+
+
+ROW_BYTES = {4: 1, 8: 1, 16: 2, 32: 4, 64: 8}
+
+
+def tile_nnz(g: gg.Csr, T: int) -> np.ndarray:
+    """Nonzeros of every non-empty T x T tile, in B2SR tile order (tile-rows
+    in order, tile columns ascending within a row)."""
+    ntc = (g.n + T - 1) // T
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.rowptr.astype(np.int64)))
+    key = (rows // T) * ntc + g.colind.astype(np.int64) // T
+    return np.unique(key, return_counts=True)[1]
+
+
+def _cc_changed_sets(g: gg.Csr, max_iter: int):
+    """The vertices whose label changes in each round of min-label
+    propagation from x_i = i (bookkeeping of the step's CC product reads)."""
+    x = np.arange(g.n, dtype=np.int64)
+    rp = g.rowptr.astype(np.int64)
+    nonempty = np.diff(rp) > 0
+    ci = g.colind.astype(np.int64)
+    out = []
+    for _ in range(max_iter):
+        m = x.copy()
+        m[nonempty] = np.minimum(x[nonempty], np.minimum.reduceat(x[ci], rp[:-1][nonempty]))
+        changed = m != x
+        out.append(changed)
+        x = m
+        if not changed.any():
+            break
+    return out
+
+
+def tile_reads(w: "Workload") -> dict:
+    """Edges (nonzeros of the tiles read) and tile bytes read by each product of
+    the step.  A product over the whole matrix reads every tile.  The products
+    with x_active read only tiles whose column segment holds an active entry:
+    the 64-source BFS at level k the vertices with a source at level k - 1,
+    SSSP at iteration i the vertices at distance i - 1 (unit weights), CC the
+    vertices whose label changed in the round before (all at first); the sets
+    come from the step's outputs (CC's from its propagation rounds)."""
+    g, A = w.g, w.A
+    T = A.tile
+    nnz_t = tile_nnz(g, T)
+    tci = b2.as_u32(A.tile_colind)[: A.ntiles].astype(np.int64)
+    assert nnz_t.size == A.ntiles
+    ntc = (g.n + T - 1) // T
+    per_tile = T * ROW_BYTES[T] + 4  # bit-rows and the tile's column index
+
+    def read(active: np.ndarray):
+        cols = np.zeros(ntc, bool)
+        cols[np.flatnonzero(active) // T] = True
+        sel = cols[tci]
+        return int(nnz_t[sel].sum()), int(sel.sum()) * per_tile
+
+    lv = b2.as_u32(w.lv_multi)
+    msbfs = [read((lv == k - 1).any(axis=0)) for k in range(1, w.it_msbfs + 1)]
+    dist = b2.as_u32(w.dist)
+    sssp = [read(dist == i - 1) for i in range(1, w.it_sssp + 1)]
+    cc_sets = [np.ones(g.n, bool)] + _cc_changed_sets(g, w.it_cc)
+    cc = [read(a) for a in cc_sets[: w.it_cc]]
+    full_products = 4 + 51
+    edges = full_products * g.nnz + sum(e for e, _ in msbfs + sssp + cc)
+    full_bytes = A.ntiles * per_tile
+    return {"edges_per_step": edges, "full_products": full_products,
+            "tile_bytes_full_product": full_bytes,
+            "msbfs_levels": [{"edges": e, "tile_bytes": b, "frac_of_full": b / full_bytes} for e, b in msbfs],
+            "sssp_iterations": [{"edges": e, "tile_bytes": b, "frac_of_full": b / full_bytes} for e, b in sssp],
+            "cc_iterations": [{"edges": e, "tile_bytes": b, "frac_of_full": b / full_bytes} for e, b in cc],
+            "blended_edges_per_step": w.products * g.nnz}
+
+
+def _median_ms(fn, reps: int = 5) -> float:
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def c1_section(reps: int = 20) -> dict:
+    """The correctness-scale workload: ER G(n, m), n = 4096, m = 16384, seed 1,
+    B2SR-8: one bin x bin SpMV (the BFS step from vertex 0), 20 PageRank
+    iterations, and the masked triangle count; launch-bound at this size."""
+    g = gg.er_gnm(4096, 16384, seed=1)
+    A = b2.B2SR.from_graph(g, 8)
+    L = b2.B2SR.from_graph(g, 8, lower=True)
+    x = np.zeros(g.n, bool)
+    x[0] = True
+    xb, visited = pack(x), pack(x)
+    y = torch.empty_like(xb)
+    ws = torch.empty(b2.b2sr_algo_workspace_bytes(A, b2.ALGO_PAGERANK), dtype=torch.uint8, device="cuda")
+    r = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    s = b2.spgemm_masked(L, L, L)
+    t_spmv = _median_ms(lambda: b2.spmv_bin_bin(A, xb, visited, complement=True, out=y), reps)
+    t_pr = _median_ms(lambda: b2.b2sr_pagerank(A, 0.85, 20, out=r, ws=ws), reps)
+    t_tc = _median_ms(lambda: b2.spgemm_masked(L, L, L, out=s), reps)
+    return {"workload": "ER n=4096 m=16384 seed 1, B2SR-8", "nnz": g.nnz, "ntiles": A.ntiles,
+            "spmv_bfs_step_ms": t_spmv, "spmv_gteps": g.nnz / t_spmv / 1e6,
+            "pagerank20_ms": t_pr, "pagerank_gteps": 21 * g.nnz / t_pr / 1e6,
+            "tc_ms": t_tc, "triangles": int(b2.as_u64(s)[0]), "tc_edges_per_s": g.edges / t_tc * 1e3}
+
+
+def tiles_section(step_graph: gg.Csr, reps: int = 5) -> dict:
+    """B2SR storage and product times at every tile width on three patterns
+    (Table VI classes): the step's R-MAT s20 (hybrid power law), the 2048^2 king
+    grid (banded) and the Mycielski graph M15 (block: dense, triangle-free).
+    Products: the full-frontier bin x bin SpMV and the plus-times bin x full SpMV."""
+    out = {}
+    for name, g in (("rmat20_ef16", step_graph), ("king2048", gg.king_grid(2048, 2048)),
+                    ("mycielski15", gg.mycielski(15))):
+        log(f"tile widths: {name}")
+        res = {"n": g.n, "nnz": g.nnz, "csr_bytes": 4 * (g.n + 1) + 4 * g.nnz}
+        x = torch.from_numpy(gg.rng(7).random(g.n).astype(np.float32)).cuda()
+        ones = pack(np.ones(g.n, bool))
+        yb = torch.empty_like(ones)
+        yf = torch.empty(g.n, dtype=torch.float32, device="cuda")
+        for T in (4, 8, 16, 32, 64):
+            A = b2.B2SR.from_graph(g, T)
+            ws = torch.empty(max(b2.spmv_bin_full_workspace_bytes(A, b2.PLUS_TIMES_F32), 1), dtype=torch.uint8,
+                             device="cuda")
+            tb = _median_ms(lambda: b2.spmv_bin_bin(A, ones, out=yb), reps)
+            tp = _median_ms(lambda: b2.spmv_bin_full(A, b2.PLUS_TIMES_F32, x, out=yf, ws=ws), reps)
+            res[f"T{T}"] = {"ntiles": A.ntiles, "bytes": A.nbytes, "bits_ms": tb, "plus_ms": tp,
+                            "bits_gteps": g.nnz / tb / 1e6, "plus_gteps": g.nnz / tp / 1e6,
+                            "bits_GB_per_s": (A.nbytes + g.n // 4) / tb / 1e6}
+            del A, ws
+        out[name] = res
+    return out
+
+
+def autotune_section(g: gg.Csr) -> dict:
+    """The measured autotuner on the step's graph: tile widths pruned by the
+    Algorithm 1 estimate, each timed under every work split (bin x bin and
+    plus-times products); the choice and every candidate's time."""
+    from paper_2201_08560_amd import autotune
+    T, k, rep = autotune.tune(g, kinds=("bits", "plus"), reps=5)
+    rep["sampling_estimate"] = {str(a): v for a, v in rep["sampling_estimate"].items()}
+    return rep
 
 
 def bfs_gteps(w: Workload, nsrc: int = 8) -> dict:
@@ -208,7 +368,7 @@ def tc_section(reps: int = 3) -> dict:
     for name, g in (("rmat18_ef16", gg.rmat(18, 16, seed=18)), ("king2048", gg.king_grid(2048, 2048))):
         log(f"tc {name}: n={g.n} nnz={g.nnz}")
         res = {"edges": g.edges}
-        for T in (4, 8, 16, 32):
+        for T in (4, 8, 16, 32, 64):
             L = b2.B2SR.from_graph(g, T, lower=True)
             s = b2.spgemm_masked(L, L, L)
             torch.cuda.synchronize()
@@ -246,9 +406,9 @@ def batched_section(graphs, reps: int = 3) -> dict:
     count = len(graphs)
     t0 = time.perf_counter()
     tiles = [autotune.choose_tile(g, nsample=256)[0] for g in graphs]   # per-graph launches
-    batch_tile = autotune.choose_batch_tile(graphs)[0]                  # the batched forms
     tune_s = time.perf_counter() - t0
     sources = [gg.sample_sources(g, 64, seed=1000 + i) for i, g in enumerate(graphs)]
+    batch_tile, batch_tune = autotune.tune_batch(graphs, sources)      # the batched forms: measured
     B = GraphBatch(graphs, [batch_tile] * count)
     B.set_sources(sources)
     singles = [b2.B2SR.from_graph(g, t) for g, t in zip(graphs, tiles)]
@@ -287,10 +447,11 @@ def batched_section(graphs, reps: int = 3) -> dict:
                and torch.equal(outs[i], B.levels_of(plan_p.out, i)) for i in range(count))
     plan.close()
     plan_p.close()
-    hist = {str(T): tiles.count(T) for T in (4, 8, 16, 32)}
+    hist = {str(T): tiles.count(T) for T in (4, 8, 16, 32, 64)}
     best = min((k for k in res if k != "per_graph"), key=lambda k: res[k]["ms"])
     return {"graphs": count, "n_total": B.n, "nnz_total": int(sum(g.nnz for g in graphs)),
             "sources_per_graph": 64, "tile_histogram": hist, "batch_tile": batch_tile, "autotune_s": tune_s,
+            "batch_tile_tuning": batch_tune,
             "modes": res,
             "identical_results": bool(same),
             "speedup_best_batched_vs_per_graph": res["per_graph"]["ms"] / res[best]["ms"]}
@@ -318,9 +479,11 @@ def stream_read_ceiling(w: "Workload", reps: int = 7) -> dict:
 
 
 def cold_warm(w: "Workload", reps: int = 5) -> dict:
-    """The headline product timed warm (back to back) and cold (a 1 GiB write
-    between launches evicts the 256 MB Infinity Cache and the L2s)."""
-    scrub = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    """The headline product timed warm (back to back) and cold (a 1 GiB read of
+    an unrelated buffer between launches evicts the 256 MB Infinity Cache and
+    the L2s without leaving dirty lines to write back)."""
+    scrub = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda")
+    scrub_out = b2.b2sr_stream_read(scrub)
 
     def one():
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -333,19 +496,21 @@ def cold_warm(w: "Workload", reps: int = 5) -> dict:
     one()
     warm = float(np.median([one() for _ in range(reps)]))
     cold = []
-    for k in range(reps):
-        scrub.fill_(k)
+    for _ in range(reps):
+        b2.b2sr_stream_read(scrub, out=scrub_out)
         torch.cuda.synchronize()
         cold.append(one())
     cold = float(np.median(cold))
     alg = spmv_bytes(w.A, True)
     return {"warm_ms": 1e3 * warm, "cold_ms": 1e3 * cold, "warm_frac": alg / warm / 1e9 / HBM_PEAK_GBS,
-            "cold_frac": alg / cold / 1e9 / HBM_PEAK_GBS, "scrub_bytes": scrub.numel()}
+            "cold_frac": alg / cold / 1e9 / HBM_PEAK_GBS, "scrub_bytes_read": scrub.numel()}
 
 
-def cpu_baseline(w: Workload, edges_per_step: float, threads: int | None = None, min_s: float = 10.0) -> dict:
-    """The oracle on the host: the same step's results (64 BFS, SSSP, CC,
-    PageRank x 50 and the four single products), timed once."""
+def cpu_baseline(w: Workload, edges_per_step: float, threads: int | None = None, min_s: float = 10.0,
+                 check: bool = False) -> dict:
+    """The oracle on the host: the same step's results (the four single
+    products, 64 BFS, SSSP, CC, PageRank x 50), timed over whole steps.  With
+    `check`, the last step's GPU outputs are compared with these results."""
     import oracle as orc
     g = w.g
     n = g.n
@@ -353,8 +518,8 @@ def cpu_baseline(w: Workload, edges_per_step: float, threads: int | None = None,
     pred = r.random(n) < 0.5  # noqa: F841  (same draws as the GPU inputs)
     ones = np.ones(n, bool)
     mask = r.random(n) < 0.01
-    xf = r.random(n)
-    xd = np.where(r.random(n) < 0.5, r.integers(0, 20, n), np.inf).astype(np.float64)
+    xf = r.random(n).astype(np.float32).astype(np.float64)
+    xd = np.where(r.random(n) < 0.5, r.integers(0, 20, n), np.inf).astype(np.float32).astype(np.float64)
     orc.lib()
     saved = orc.num_threads()
     if threads is not None:
@@ -362,39 +527,39 @@ def cpu_baseline(w: Workload, edges_per_step: float, threads: int | None = None,
     reps = 0
     t0 = time.perf_counter()
     while True:  # whole steps until at least min_s of host work
-        orc.spmv_or(g, ones, mask, True)
-        orc.spmv_count(g, ones)
-        orc.spmv_plus(g, xf)
-        orc.spmv_min_plus(g, xd, 1.0, True)
-        orc.bfs_multi(g, w.sources)
-        orc.sssp_unit(g, int(w.sources[0]))
-        orc.cc(g)
-        orc.pagerank(g, 0.85, 50)
+        y_or = orc.spmv_or(g, ones, mask, True)
+        y_cnt = orc.spmv_count(g, ones)
+        y_plus = orc.spmv_plus(g, xf)
+        y_min = orc.spmv_min_plus(g, xd, 1.0, True)
+        lv = orc.bfs_multi(g, w.sources)
+        dist = orc.sssp_unit(g, int(w.sources[0]))
+        labels = orc.cc(g)
+        pr = orc.pagerank(g, 0.85, 50)
         reps += 1
         if time.perf_counter() - t0 >= min_s:
             break
     dt = (time.perf_counter() - t0) / reps
     cores = orc.num_threads()
     orc.set_num_threads(saved)
-    return {"value": edges_per_step / dt / 1e9, "unit": "GTEPS", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} full steps of the same workload (R-MAT s20: 4 single products, 64 BFS, SSSP, CC, "
-                      f"PageRank x 50), {dt:.2f} s wall each"}
-
-
-def verify(w: Workload) -> dict:
-    """Spot checks of the timed outputs against the oracle."""
-    import oracle as orc
-    g = w.g
-    ok = {}
-    lv = b2.as_u32(w.lv_multi)
-    ref = orc.bfs_multi(g, w.sources[:4])
-    ok["bfs64_first4"] = bool(np.array_equal(lv[:4], ref))
-    ok["sssp"] = bool(np.array_equal(b2.as_u32(w.dist), orc.sssp_unit(g, int(w.sources[0]))))
-    ok["cc"] = bool(np.array_equal(b2.as_u32(w.labels), orc.cc(g)))
-    pr = w.rank.cpu().numpy().astype(np.float64)
-    refp = orc.pagerank(g, 0.85, 50)
-    ok["pagerank_rel_l1"] = float(np.abs(pr - refp).sum() / refp.sum())
-    return ok
+    out = {"value": edges_per_step / dt / 1e9, "unit": "GTEPS", "cores": cores, "kind": "oracle",
+           "sample": f"{reps} full steps of the same workload (R-MAT s20: 4 single products, 64 BFS, SSSP, CC, "
+                     f"PageRank x 50), {dt:.2f} s wall each"}
+    if check:
+        yb = b2.as_u32(w.y_bits)
+        got_or = np.unpackbits(yb.view(np.uint8), bitorder="little")[:n].astype(bool)
+        gp = w.y_f.cpu().numpy().astype(np.float64)
+        gpr = w.rank.cpu().numpy().astype(np.float64)
+        bound = (g.degrees() + 2) * 2.0 ** -24 * y_plus + 1e-30
+        out["verify_step_outputs"] = {
+            "spmv_bits_masked": bool(np.array_equal(got_or, y_or)),
+            "spmv_count": bool(np.array_equal(b2.as_u32(w.y_cnt), y_cnt)),
+            "spmv_plus_within_bound": bool(np.all(np.abs(gp - y_plus) <= bound)),
+            "spmv_min_plus": bool(np.array_equal(w.y_f2.cpu().numpy(), y_min.astype(np.float32))),
+            "bfs_64_sources": bool(np.array_equal(b2.as_u32(w.lv_multi), lv)),
+            "sssp": bool(np.array_equal(b2.as_u32(w.dist), dist)),
+            "cc": bool(np.array_equal(b2.as_u32(w.labels), labels)),
+            "pagerank_rel_l1": float(np.abs(gpr - pr).sum() / pr.sum())}
+    return out
 
 
 def profile_mode(args):
@@ -416,14 +581,22 @@ def profile_mode(args):
         b2.spmv_bin_full(w.A, b2.PLUS_TIMES_F32, w.xf, out=w.y_f, ws=w.ws_plus)
     torch.cuda.synchronize()
     log(json.dumps({"profile_mode": True, "spmv_bits_alg_bytes": spmv_bytes(w.A, True),
+                    "spmv_plus_alg_bytes": w.A.nbytes + 8 * g.n,
                     "copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
                     "kernel_source_digest": source_digest()}))
 
 
-def serving_section(pool, qps: float, seconds: float, budget_bytes: int, seed: int = 77, mix=(0.6, 0.15, 0.15, 0.1),
+def serving_section(pool, rates, seconds: float, budget_bytes: int, seed: int = 77, mix=(0.6, 0.15, 0.15, 0.1),
                     workers: int = 2, streams: int = 4):
-    """Poisson stream of BFS/SSSP/CC/TC queries over a resident pool of R-MAT
-    graphs; continuous batching with admission by a device-memory budget."""
+    """Poisson streams of BFS/SSSP/CC/TC queries over a resident pool of R-MAT
+    graphs, continuous batching with admission by a device-memory budget, at
+    increasing offered rates: each rate runs for `seconds`; the sweep stops
+    after the first rate whose answered rate (queries done or rejected per
+    second) falls below 90 % of the offered one (the knee).  The budget is
+    below a scale-20 graph's BFS session (its 64 level arrays), so those
+    queries are rejected, and sessions of the next scales contend for it.  A
+    sample of each rate's answers is compared with the single-query drivers
+    run alone."""
     from paper_2201_08560_amd import autotune
     from paper_2201_08560_amd.serve import GpuExecutor, Query, Server
     t0 = time.perf_counter()
@@ -434,60 +607,67 @@ def serving_section(pool, qps: float, seconds: float, budget_bytes: int, seed: i
     load_s = time.perf_counter() - t0
     pool_bytes = sum(A.nbytes + L.nbytes for A, L in mats)
     log(f"serving pool: {len(pool)} graphs resident, {pool_bytes / 2**30:.2f} GiB B2SR, {load_s:.1f} s")
-    ex = GpuExecutor(mats, pool, streams=streams, workers=workers)
-    r = np.random.default_rng(seed)
-    nq = int(qps * seconds)
-    arrivals = np.cumsum(r.exponential(1.0 / qps, nq))
-    kinds = r.choice(np.array(["bfs", "sssp", "cc", "tc"]), p=list(mix), size=nq)
-    gidx = r.integers(len(pool), size=nq)
     cand = [np.flatnonzero(g.degrees() > 0) for g in pool]
-    queries = [Query(i, str(kinds[i]), int(gidx[i]), int(r.choice(cand[gidx[i]])), float(arrivals[i]))
-               for i in range(nq)]
     # warm-up: one query of each kind on a small graph (first launches of each kernel)
+    ex = GpuExecutor(mats, pool, streams=streams, workers=workers)
     small = int(np.argmin([g.n for g in pool]))
-    warm = Server(ex, budget_bytes, cache=False)
-    warm.run([Query(-1 - k, kind, small, int(cand[small][0]), 0.0) for k, kind in enumerate(("bfs", "sssp", "cc", "tc"))])
+    Server(ex, budget_bytes, cache=False).run(
+        [Query(-1 - k, kind, small, int(cand[small][0]), 0.0) for k, kind in enumerate(("bfs", "sssp", "cc", "tc"))])
     torch.cuda.synchronize()
-    sample = {}
-    count = [0]
-
-    def on_done(q):
-        count[0] += 1
-        if count[0] % 500 == 0:
-            log(f"serving: {count[0]}/{nq} queries finished")
-        if q.status == "done" and q.qid % 40 == 0:
-            sample[q.qid] = (q, q.result)
-
-    srv = Server(ex, budget_bytes, on_done=on_done, keep_results=False)
-    t1 = time.perf_counter()
-    srv.run(queries)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t1
-    st = srv.stats()
-    # answers of the sample against the single-query drivers, run alone afterwards
-    same = True
-    for qid, (q, res) in sorted(sample.items()):
-        A = mats[q.graph][0]
-        if q.kind == "bfs":
-            ref = b2.b2sr_bfs(A, q.source)[0]
-        elif q.kind == "sssp":
-            ref = b2.b2sr_sssp(A, q.source)[0]
-        elif q.kind == "cc":
-            ref = b2.b2sr_cc(A)[0]
-        else:
-            L = mats[q.graph][1]
-            same &= int(b2.as_u64(res)[0]) == int(b2.as_u64(b2.spgemm_masked(L, L, L))[0])
-            continue
-        same &= bool(torch.equal(res, ref))
     ex.shutdown()
-    st["job_seconds"] = dict(ex.job_seconds)
-    st["job_count"] = dict(ex.job_count)
-    joined = sum(1 for q in srv.done if q.kind == "bfs" and q.joined_step)
-    st.update({"offered_qps": qps, "window_s": seconds, "wall_s": wall, "pool_graphs": len(pool),
-               "pool_scales": sorted({int(np.log2(g.n)) for g in pool}), "pool_bytes": pool_bytes,
-               "pool_load_s": load_s, "tile_histogram": {str(T): tiles.count(T) for T in (4, 8, 16, 32)},
-               "bfs_joined_running_session": joined, "sampled": len(sample), "sample_identical_alone": bool(same)})
-    return st
+    per_rate = []
+    for qps in rates:
+        ex = GpuExecutor(mats, pool, streams=streams, workers=workers)
+        r = np.random.default_rng(seed)
+        nq = int(qps * seconds)
+        arrivals = np.cumsum(r.exponential(1.0 / qps, nq))
+        kinds = r.choice(np.array(["bfs", "sssp", "cc", "tc"]), p=list(mix), size=nq)
+        gidx = r.integers(len(pool), size=nq)
+        queries = [Query(i, str(kinds[i]), int(gidx[i]), int(r.choice(cand[gidx[i]])), float(arrivals[i]))
+                   for i in range(nq)]
+        sample = {}
+
+        def on_done(q, sample=sample):
+            if q.status == "done" and q.qid % 40 == 0:
+                sample[q.qid] = (q, q.result)
+
+        srv = Server(ex, budget_bytes, on_done=on_done, keep_results=False)
+        t1 = time.perf_counter()
+        srv.run(queries)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        ex.shutdown()
+        st = srv.stats()
+        same = True
+        for qid, (q, res) in sorted(sample.items()):
+            A = mats[q.graph][0]
+            if q.kind == "bfs":
+                ref = b2.b2sr_bfs(A, q.source)[0]
+            elif q.kind == "sssp":
+                ref = b2.b2sr_sssp(A, q.source)[0]
+            elif q.kind == "cc":
+                ref = b2.b2sr_cc(A)[0]
+            else:
+                L = mats[q.graph][1]
+                same &= int(b2.as_u64(res)[0]) == int(b2.as_u64(b2.spgemm_masked(L, L, L))[0])
+                continue
+            same &= bool(torch.equal(res, ref))
+        st["job_count"] = dict(ex.job_count)
+        answered = [q for q in srv.done if q.status in ("done", "rejected")]
+        span = max(q.finished for q in answered) - min(q.arrival for q in answered) if answered else 0.0
+        st["answered_qps"] = len(answered) / span if span > 0 else 0.0
+        st.update({"offered_qps": qps, "window_s": seconds, "wall_s": wall,
+                   "session_queries": sum(1 for q in srv.done if q.kind in ("bfs", "sssp") and q.joined_step),
+                   "sampled": len(sample), "sample_identical_alone": bool(same)})
+        per_rate.append(st)
+        log(f"serving {qps:.0f} q/s offered: {st['answered_qps']:.0f} answered, "
+            f"{st.get('queries_per_s', 0):.0f} done per s, p50 {st.get('p50_ms', 0):.2f} ms, "
+            f"p99 {st.get('p99_ms', 0):.2f} ms, waited {st['waited_for_memory']}, rejected {st['rejected']}")
+        if st["answered_qps"] < 0.9 * qps:
+            break
+    return {"pool_graphs": len(pool), "pool_scales": sorted({int(np.log2(g.n)) for g in pool}),
+            "pool_bytes": pool_bytes, "pool_load_s": load_s, "budget_bytes": budget_bytes,
+            "tile_histogram": {str(T): tiles.count(T) for T in (4, 8, 16, 32, 64)}, "rates": per_rate}
 
 
 def profile_tc(args):
@@ -512,9 +692,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-mode", action="store_true")
     ap.add_argument("--profile-tc", action="store_true")
-    ap.add_argument("--serve-qps", type=float, default=400.0)
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
-    ap.add_argument("--serve-budget-gib", type=float, default=0.5)
+    ap.add_argument("--serve-qps", default="250,500,1000,2000,4000",
+                    help="offered rates of the serving sweep (comma-separated, increasing)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=0.25)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     batch_graphs = pool_graphs = None
@@ -557,12 +738,16 @@ def main():
         w.step(record=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    edges_per_step = w.products * g.nnz
+    reads = tile_reads(w)
+    edges_per_step = reads["edges_per_step"]
     value = edges_per_step * args.steps / t / 1e9
     kt = float(np.mean([a.elapsed_time(b) for a, b in w.ev])) / 1e3
+    kp = float(np.mean([a.elapsed_time(b) for a, b in w.ev_plus])) / 1e3
     alg = spmv_bytes(w.A, True)
+    alg_plus = w.A.nbytes + 8 * g.n  # the B2SR arrays once, x and y (float32) once
     digest = source_digest()
-    traffic = read_traffic(digest)
+    traffic = read_traffic(digest, "spmv_plus_t32_rmat20_pmc.txt")
+    traffic_bits = read_traffic(digest, "spmv_bits_t32_rmat20_pmc.txt")
     out = {
         "metric": "B2SR SpMV GTEPS + masked-SpGEMM TC edges/s; batched vs per-graph launches",
         "value": value, "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -571,30 +756,43 @@ def main():
         "config": {"workload": "R-MAT scale 20, edge factor 16 (0.57/0.19/0.19), symmetrised, B2SR-32: "
                                "4 single products + 64-source BFS + SSSP + CC + 50 PageRank iterations",
                    "n": g.n, "nnz": g.nnz, "tile": 32, "ntiles": w.A.ntiles, "products_per_step": w.products,
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "spmv_kernel<32, 0, false, false> (masked bin x bin SpMV, full frontier)",
-                     "achieved": alg / kt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": alg / kt / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg, "ms_per_launch": kt * 1e3, "gteps": g.nnz / kt / 1e9,
+                   "edges_per_step": edges_per_step, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm",
+                     "kernel": "spmv_bin_full plus-times (spmv_kernel<32, 2, false, false> with its output "
+                               "initialisation and split-row fixup kernels), the step's dominant kernel",
+                     "achieved": alg_plus / kp / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg_plus / kp / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_plus, "ms_per_launch": kp * 1e3, "gteps": g.nnz / kp / 1e9,
                      "kernel_source_digest": digest},
+        "roofline_headline_bits": {"bound": "hbm",
+                                   "kernel": "spmv_kernel<32, 0, false, false> (masked bin x bin SpMV, full frontier)",
+                                   "achieved": alg / kt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": alg / kt / 1e9 / HBM_PEAK_GBS, "traffic": traffic_bits,
+                                   "alg_bytes_per_launch": alg, "ms_per_launch": kt * 1e3,
+                                   "gteps": g.nnz / kt / 1e9},
+        "spmv_gteps": g.nnz / kt / 1e9,
+        "step_reads": reads,
+        "step_rate_blended_gteps": reads["blended_edges_per_step"] * args.steps / t / 1e9,
         "convert_ms": w.convert_s * 1e3,
         "convert_device_csr_ms": w.convert_device_s * 1e3,
     }
     ceiling = stream_read_ceiling(w)
-    out["roofline"]["stream_read_ceiling"] = ceiling
-    out["roofline"]["frac_of_stream_read"] = (alg / kt / 1e9) / ceiling["GB_per_s"]
+    out["roofline_headline_bits"]["stream_read_ceiling"] = ceiling
+    out["roofline_headline_bits"]["frac_of_stream_read"] = (alg / kt / 1e9) / ceiling["GB_per_s"]
+    out["roofline"]["frac_of_stream_read"] = (alg_plus / kp / 1e9) / ceiling["GB_per_s"]
     if not args.no_extras:
-        out["verify"] = verify(w)
         out["bfs_single_source"] = bfs_gteps(w)
+        out["c1_er4096"] = c1_section()
+        out["autotune"] = autotune_section(g)
+        out["tile_widths"] = tiles_section(g)
         out["lgc"] = lgc_section(w)
         out["tc"] = tc_section()
         out["batched"] = batched_section(batch_graphs)
-        out["serving"] = serving_section(pool_graphs, args.serve_qps, args.serve_seconds,
-                                         int(args.serve_budget_gib * 2**30))
-    if not args.no_extras:
+        out["serving"] = serving_section(pool_graphs, [float(v) for v in str(args.serve_qps).split(",")],
+                                         args.serve_seconds, int(args.serve_budget_gib * 2**30))
         out["headline_cold_warm"] = cold_warm(w)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, edges_per_step)
+        out["cpu_baseline"] = cpu_baseline(w, edges_per_step, check=True)
         if not args.no_extras:
             log("cpu baseline on one thread ...")
             out["cpu_baseline_1thread"] = cpu_baseline(w, edges_per_step, threads=1, min_s=1.0)

@@ -106,12 +106,22 @@ extern "C" {
                                  y_i = max_{j : A_ij = 1} x_j over uint64_t, the empty
                                  maximum being 0 (MIS and colouring keys) */
 
-/* A non-owning view of a B2SR matrix in device memory (layout above). */
+/* A non-owning view of a B2SR matrix in device memory (layout above).
+ * chunk_blocks sets how the matrix-vector products (spmv_bin_bin,
+ * spmv_bin_full and the algorithms and batches built on them) divide the work:
+ * each wave takes chunk_blocks consecutive blocks of tiles, a block being the
+ * tiles whose loads a wave issues together (for T = 32: 64 tiles for the bit
+ * and count products, 32 for 4-byte values, 16 for 8-byte values).  0 lets
+ * the library size the chunks (about 65536 waves per launch); values above
+ * 64 are EINVAL.  Results do not depend on it, except the rounding of float
+ * sums (each split's order is fixed, so a given split is deterministic); the
+ * plus-times workspace size does.  Other calls ignore it. */
 typedef struct b2sr_matrix {
     uint32_t n;      /* rows = columns                         */
     uint32_t tile;   /* T: 4, 8, 16, 32 or 64                  */
     uint32_t ntiles; /* number of non-empty tiles              */
-    uint32_t reserved; /* must be 0                            */
+    uint32_t chunk_blocks; /* products' work split: 0 = the library's
+                              choice, else 1..64 (see below)           */
     const uint32_t *tile_rowptr; /* device, nTR + 1 entries    */
     const uint32_t *tile_colind; /* device, ntiles entries     */
     const void *bits;            /* device, ntiles * T words   */

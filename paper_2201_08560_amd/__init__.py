@@ -61,7 +61,7 @@ class B2SRError(RuntimeError):
 
 class b2sr_matrix(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("ntiles", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("tile_rowptr", ctypes.c_void_p),
+                ("chunk_blocks", ctypes.c_uint32), ("tile_rowptr", ctypes.c_void_p),
                 ("tile_colind", ctypes.c_void_p), ("bits", ctypes.c_void_p)]
 
 
@@ -192,6 +192,24 @@ class B2SR:
     @property
     def view(self):
         return ctypes.byref(self._view)
+
+    @property
+    def chunk_blocks(self) -> int:
+        """The products' work split (b2sr.h: 0 = the library's choice, else
+        1..64 blocks of tiles per wave)."""
+        return int(self._view.chunk_blocks)
+
+    @chunk_blocks.setter
+    def chunk_blocks(self, k: int):
+        if not 0 <= int(k) <= 64:
+            raise ValueError("chunk_blocks must be in 0..64")
+        self._view.chunk_blocks = int(k)
+
+    def with_split(self, chunk_blocks: int) -> "B2SR":
+        """The same arrays (shared, not copied) under another work split."""
+        other = B2SR(self.n, self.tile, self.tile_rowptr, self.tile_colind, self.bits, self.ntiles)
+        other.chunk_blocks = chunk_blocks
+        return other
 
     @property
     def ntile_rows(self) -> int:

@@ -12,10 +12,17 @@ bytes, against 8 * e bytes of float CSR; the estimate is the mean ratio.
 Step 2, exact: the tile count for every k, from b2sr_count_tiles on the
 device (one call per tile width).
 
-Step 3, the choice: the tile width with the smallest modelled per-product cost
-ntiles * (k * w_k + 4 + beta * k * V) bytes, where V is the width of a vector
-value the product stages per tile column (8 for the 64-wide BFS frontier) and
-beta discounts those re-reads, which mostly hit L2.
+Step 3, the modelled choice (choose_tile): the tile width with the smallest
+modelled per-product cost ntiles * (k * w_k + 4 + beta * k * V) bytes, where V
+is the width of a vector value the product stages per tile column (8 for the
+64-wide BFS frontier) and beta discounts those re-reads, which mostly hit L2.
+
+The measured choice (tune): the Algorithm 1 estimate prunes the tile widths
+(those within a factor of the best estimate, at most a few), then every
+surviving tile width is built on the device and the products are timed with
+HIP events under each work split (the matrix view's chunk_blocks: blocks of
+tiles per wave); the (tile width, split) with the least measured time wins,
+and the report holds every candidate's time.
 """
 from __future__ import annotations
 
@@ -84,6 +91,106 @@ def choose_batch_tile(graphs, value_bytes: int = 8, beta: float = 0.25) -> tuple
     return best, {"cost": total}
 
 
+def prune(estimate: dict, slack: float = 1.5, keep: int = 3) -> list[int]:
+    """Tile widths whose Algorithm 1 storage estimate is within `slack` of the
+    smallest, the `keep` smallest of them (every width when none is > 0)."""
+    pos = {k: v for k, v in estimate.items() if v > 0}
+    if not pos:
+        return list(TILES)
+    best = min(pos.values())
+    cands = sorted((k for k, v in pos.items() if v <= slack * best), key=lambda k: (pos[k], k))
+    return sorted(cands[:keep])
+
+
+SPLITS = (0, 1, 2, 4, 8, 16)
+
+
+def _time_ms(fn, reps: int) -> float:
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def _product_fns(A, kinds, seed: int = 0):
+    """One callable per product kind on matrix A (full frontier / random x)."""
+    from . import OR_U64, PLUS_TIMES_F32, spmv_bin_bin, spmv_bin_full, spmv_bin_full_workspace_bytes
+    n = A.n
+    r = np.random.default_rng(seed)
+    fns = {}
+    if "bits" in kinds:
+        x = torch.full((max((n + 31) // 32, 1),), -1, dtype=torch.int32, device="cuda")
+        if n % 32:
+            x[-1] = (1 << (n % 32)) - 1
+        y = torch.empty_like(x)
+        fns["bits"] = lambda: spmv_bin_bin(A, x, out=y)
+    if "plus" in kinds:
+        xf = torch.from_numpy(r.random(n).astype(np.float32)).cuda()
+        yf = torch.empty(n, dtype=torch.float32, device="cuda")
+        ws = torch.empty(max(spmv_bin_full_workspace_bytes(A, PLUS_TIMES_F32), 1), dtype=torch.uint8, device="cuda")
+        fns["plus"] = lambda: spmv_bin_full(A, PLUS_TIMES_F32, xf, out=yf, ws=ws)
+    if "or64" in kinds:
+        xu = torch.from_numpy(r.integers(0, 2**63, n, dtype=np.int64)).cuda()
+        yu = torch.empty(n, dtype=torch.int64, device="cuda")
+        fns["or64"] = lambda: spmv_bin_full(A, OR_U64, xu, out=yu)
+    return fns
+
+
+def tune(g, kinds=("bits", "plus"), splits=SPLITS, slack: float = 1.5, keep: int = 3, nsample: int = 1024,
+         reps: int = 5, tiles=None) -> tuple[int, int, dict]:
+    """(tile width, chunk_blocks, report) for graph g: candidates pruned by the
+    Algorithm 1 estimate (or the given `tiles`), each timed on the device for
+    every work split in `splits`; the least summed time over `kinds` wins."""
+    import time
+    from . import B2SR
+    t0 = time.perf_counter()
+    est = sampling_profile(g.rowptr, g.colind, g.n, nsample)
+    cands = list(tiles) if tiles is not None else prune(est, slack, keep)
+    times = {}
+    for T in cands:
+        A = B2SR.from_graph(g, T)
+        for k in splits:
+            Ak = A.with_split(k)
+            fns = _product_fns(Ak, kinds)
+            times[(T, k)] = sum(_time_ms(f, reps) for f in fns.values())
+        del A
+    best = min(times, key=lambda tk: (times[tk], tk))
+    report = {"sampling_estimate": est, "candidates": cands, "splits": list(splits), "kinds": list(kinds),
+              "times_ms": {f"T{T}/k{k}": v for (T, k), v in times.items()},
+              "choice": {"tile": best[0], "chunk_blocks": best[1]}, "seconds": time.perf_counter() - t0}
+    return best[0], best[1], report
+
+
+def tune_batch(graphs, sources, candidates=None, keep: int = 2, reps: int = 3) -> tuple[int, dict]:
+    """(tile width, report) for a batch: the `keep` widths with the least
+    modelled summed cost (or the given candidates), each built as the batch's
+    one group and timed as a per-level batched BFS with these sources; the
+    least measured time wins."""
+    import time
+    from . import BATCH_LEVELS
+    from .batch import GraphBatch
+    t0 = time.perf_counter()
+    modelled = choose_batch_tile(graphs)[1]["cost"]
+    cands = list(candidates) if candidates is not None else sorted(sorted(modelled, key=lambda k: (modelled[k], k))[:keep])
+    times = {}
+    for T in cands:
+        B = GraphBatch(graphs, [T] * len(graphs))
+        B.set_sources(sources)
+        times[T] = _time_ms(lambda: B.run(BATCH_LEVELS), reps)
+        del B
+    best = min(times, key=lambda k: (times[k], k))
+    return best, {"modelled_cost": {str(k): v for k, v in modelled.items()}, "candidates": cands,
+                  "times_ms": {str(k): v for k, v in times.items()}, "choice": best,
+                  "seconds": time.perf_counter() - t0}
+
+
 def _load_graph(spec: str):
     """A graph from a generator spec (rmat:SCALE:EF[:SEED], rmat_dir:SCALE:EF[:SEED],
     er:N:M[:SEED], king:R:C) or an .npz file holding n, rowptr and colind."""
@@ -115,6 +222,8 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--value-bytes", type=int, default=8, help="bytes of a vector value staged per tile column")
     ap.add_argument("--no-exact", action="store_true", help="only the sampling profile (no GPU needed)")
+    ap.add_argument("--measure", action="store_true",
+                    help="also time the pruned tile widths under every work split on the GPU (tune)")
     args = ap.parse_args(argv)
     g = _load_graph(args.graph)
     out = {"graph": g.name, "n": g.n, "nnz": g.nnz,
@@ -126,6 +235,9 @@ def main(argv=None) -> int:
             k: (4 * ((g.n + k - 1) // k + 1) + tiles[k] * (4 + k * ROW_BYTES[k])) / (8.0 * g.nnz + 4.0 * (g.n + 1))
             for k in TILES} if g.nnz else {}, "product_cost_bytes": cost,
             "choice": min(cost, key=lambda k: (cost[k], k))})
+    if args.measure:
+        T, k, rep = tune(g, nsample=args.sample)
+        out["measured"] = rep
     print(json.dumps(out, indent=1))
     return 0
 

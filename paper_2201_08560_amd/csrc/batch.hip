@@ -310,7 +310,7 @@ Layout carve(uint32_t n, void *ws)
     return L;
 }
 
-template <int T> uint32_t or64_chunk(uint32_t ntiles) { return chunk_tiles<T, kOr64>(ntiles); }
+template <int T> uint32_t or64_chunk(const b2sr_matrix *A) { return chunk_tiles<T, kOr64>(A->ntiles, A->chunk_blocks); }
 
 int make_args(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t nseeds, const uint32_t *seed_vertex,
               const uint32_t *seed_bit, uint32_t *levels, void *ws, size_t ws_bytes, BatchArgs *out)
@@ -346,9 +346,8 @@ int make_args(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t 
         g.p.n = n;
         g.p.ntr = b2sr::n_tile_rows(n, A->tile);
         g.p.ntiles = A->ntiles;
-        g.p.chunk = A->tile == 4 ? or64_chunk<4>(A->ntiles) : A->tile == 8 ? or64_chunk<8>(A->ntiles)
-                  : A->tile == 16 ? or64_chunk<16>(A->ntiles) : A->tile == 32 ? or64_chunk<32>(A->ntiles)
-                  : or64_chunk<64>(A->ntiles);
+        g.p.chunk = A->tile == 4 ? or64_chunk<4>(A) : A->tile == 8 ? or64_chunk<8>(A)
+                  : A->tile == 16 ? or64_chunk<16>(A) : A->tile == 32 ? or64_chunk<32>(A) : or64_chunk<64>(A);
         g.p.x = L.F;
         g.p.xact = L.act;  // only non-zero frontier words take part
         g.p.y = L.Y;

@@ -20,7 +20,7 @@ void clear_hip_error() { g_last_hip_error[0] = 0; }
 int validate_matrix(const b2sr_matrix *A)
 {
     if (!A) return B2SR_EINVAL;
-    if (!valid_tile(A->tile) || A->reserved != 0) return B2SR_EINVAL;
+    if (!valid_tile(A->tile) || A->chunk_blocks > 64) return B2SR_EINVAL;
     if (A->n > 0xFFFFFF00u) return B2SR_ERANGE;
     if (A->n > 0 && !A->tile_rowptr) return B2SR_EINVAL;
     if (A->ntiles > 0 && (!A->tile_colind || !A->bits)) return B2SR_EINVAL;

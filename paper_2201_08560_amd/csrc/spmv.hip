@@ -158,7 +158,8 @@ template <int T, int K> int launch(SpmvArgs p, hipStream_t stream)
     bool short_blocks = false;
     if constexpr (!Cfg<T, K>::kStage)
         short_blocks = (p.flags & B2SR_SPARSE_X) || (uint64_t)p.ntiles < (uint64_t)p.ntr * Cfg<T, K>::BT;
-    p.chunk = short_blocks ? chunk_tiles<T, K, true>(p.ntiles) : chunk_tiles<T, K>(p.ntiles);
+    p.chunk = short_blocks ? chunk_tiles<T, K, true>(p.ntiles, p.chunk_blocks)
+                           : chunk_tiles<T, K>(p.ntiles, p.chunk_blocks);
     p.x_whole = p.n % T == 0;
     const uint32_t nchunks = (uint32_t)((p.ntiles + (uint64_t)p.chunk - 1) / p.chunk);
     if (!(p.flags & B2SR_ACCUMULATE) || K >= kPlusF32) {
@@ -207,17 +208,19 @@ SpmvArgs make_args(const b2sr_matrix *A)
     p.n = A->n;
     p.ntr = b2sr::n_tile_rows(A->n, A->tile);
     p.ntiles = A->ntiles;
+    p.chunk_blocks = A->chunk_blocks;
     return p;
 }
 
-uint32_t plus_chunk(uint32_t T, uint32_t ntiles)
+uint32_t plus_chunk(const b2sr_matrix *A)
 {
-    switch (T) {
-    case 4: return chunk_tiles<4, kPlusF32>(ntiles);
-    case 8: return chunk_tiles<8, kPlusF32>(ntiles);
-    case 16: return chunk_tiles<16, kPlusF32>(ntiles);
-    case 64: return chunk_tiles<64, kPlusF32>(ntiles);
-    default: return chunk_tiles<32, kPlusF32>(ntiles);
+    const uint32_t nt = A->ntiles, cb = A->chunk_blocks;
+    switch (A->tile) {
+    case 4: return chunk_tiles<4, kPlusF32>(nt, cb);
+    case 8: return chunk_tiles<8, kPlusF32>(nt, cb);
+    case 16: return chunk_tiles<16, kPlusF32>(nt, cb);
+    case 64: return chunk_tiles<64, kPlusF32>(nt, cb);
+    default: return chunk_tiles<32, kPlusF32>(nt, cb);
     }
 }
 
@@ -225,7 +228,7 @@ uint32_t plus_chunk(uint32_t T, uint32_t ntiles)
 // straddling rows' partials (256-byte aligned pieces); x * col_scale follows.
 size_t plus_partials_bytes(const b2sr_matrix *A)
 {
-    const uint32_t chunk = plus_chunk(A->tile, A->ntiles);
+    const uint32_t chunk = plus_chunk(A);
     const uint64_t nchunks = ((uint64_t)A->ntiles + chunk - 1) / chunk;
     const uint64_t rows_bytes = (nchunks * 2 * 4 + 255) & ~255ull;
     return (size_t)((rows_bytes + nchunks * 2 * A->tile * 4 + 255) & ~255ull);
@@ -269,8 +272,7 @@ int full_product(const b2sr_matrix *A, int semiring, const void *x, const float 
     p.w_u32 = semiring == B2SR_MIN_PLUS_U32 ? (uint32_t)alpha : 0u;
     p.y = y;
     if (semiring == B2SR_PLUS_TIMES_F32) {
-        const uint64_t nchunks = ((uint64_t)A->ntiles + plus_chunk(A->tile, A->ntiles) - 1) /
-                                 plus_chunk(A->tile, A->ntiles);
+        const uint64_t nchunks = ((uint64_t)A->ntiles + plus_chunk(A) - 1) / plus_chunk(A);
         p.ws_rows = (uint32_t *)ws;
         p.ws_part = (float *)((char *)ws + ((nchunks * 2 * 4 + 255) & ~255ull));
     }

@@ -100,6 +100,7 @@ struct SpmvArgs {
     uint32_t *ws_rows;  // float sums: first and last row of each chunk
     float *ws_part;     // float sums: partials of straddling rows, 2*T per chunk
     uint32_t x_whole;   // n is a multiple of T: no x segment is cut short
+    uint32_t chunk_blocks;  // blocks per wave chunk (0: sized from the tile count)
 };
 
 // Block shape per tile width and kind.  Bit and count products read the x
@@ -125,12 +126,14 @@ template <int T, int K, bool SHORT = false> struct Cfg {
     static_assert(U >= 1 && (64 % TPW) == 0, "block shape");
 };
 
-// Tiles per wave chunk: whole blocks, aiming at about B2SR_TARGET_WAVES waves per launch,
-// between 1 and 16 blocks.  A pure function of (T, kind, ntiles), so the
-// float-sum workspace query and the launch agree.
-template <int T, int K, bool SHORT = false> inline uint32_t chunk_tiles(uint32_t ntiles)
+// Tiles per wave chunk: `blocks` whole blocks when given (the matrix view's
+// chunk_blocks), else aiming at about B2SR_TARGET_WAVES waves per launch,
+// between 1 and 16 blocks.  A pure function of (T, kind, ntiles, blocks), so
+// the float-sum workspace query and the launch agree.
+template <int T, int K, bool SHORT = false> inline uint32_t chunk_tiles(uint32_t ntiles, uint32_t blocks = 0)
 {
     constexpr uint32_t bt = Cfg<T, K, SHORT>::BT;
+    if (blocks) return bt * blocks;
     constexpr uint64_t waves = B2SR_TARGET_WAVES;
     uint64_t nb = ((uint64_t)ntiles + waves * bt - 1) / (waves * bt);
     nb = nb < 1 ? 1 : (nb > 16 ? 16 : nb);

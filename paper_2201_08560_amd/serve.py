@@ -7,8 +7,12 @@ continuously:
 * BFS queries on one graph share a session of 64 frontier bits
   (``BfsSession``): a query takes a free bit between two levels and leaves when
   its bit reaches no new vertex, so queries that arrive while others run join
-  the running levels instead of waiting for them;
-* SSSP, CC and TC are whole-graph jobs run on worker threads, each with its own
+  the running levels instead of waiting for them.  SSSP queries join the same
+  sessions: with unit edge weights their distances are the BFS levels (Sec. V,
+  the diagonal as zero and each edge costing one), so concurrent SSSP queries
+  on a graph are one multi-source job of up to 64 sources, mixed with its BFS
+  queries;
+* CC and TC are whole-graph jobs run on worker threads, each with its own
   stream, so their kernels overlap the BFS sessions on the device.  Concurrent
   queries asking the same whole-graph question share one job, and CC and TC
   results are kept per graph (the graphs do not change).
@@ -33,6 +37,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 KINDS = ("bfs", "sssp", "cc", "tc")
+SESSION_KINDS = ("bfs", "sssp")  # answered by the 64-source BFS sessions
 
 
 @dataclass
@@ -138,7 +143,7 @@ class Server:
     def _need(self, q: Query, fresh: bool = False) -> int:
         """Bytes admitting q would add now (fresh: assume nothing is running)."""
         res = self.ex.result_bytes(q.kind, q.graph)
-        if q.kind == "bfs":
+        if q.kind in SESSION_KINDS:
             if not fresh and q.graph in self.sessions:
                 return res
             return res + self.ex.session_bytes(q.graph)
@@ -194,7 +199,7 @@ class Server:
             still = []
             for q, token in s.extracting:
                 if self.ex.token_ready(token):
-                    self._release(self.ex.result_bytes("bfs", q.graph))
+                    self._release(self.ex.result_bytes(q.kind, q.graph))
                     self._finish(q, "done", self.ex.token_result(token))
                 else:
                     still.append((q, token))
@@ -230,7 +235,7 @@ class Server:
     def _admit_one(self, q: Query) -> bool:
         now = self.clock()
         res = self.ex.result_bytes(q.kind, q.graph)
-        if q.kind == "bfs":
+        if q.kind in SESSION_KINDS:
             s = self.sessions.get(q.graph)
             if s is not None:
                 free = [k for k in range(64) if k not in s.slots]

@@ -13,8 +13,8 @@ L = b2.lib()
 FAKE = 0x1000  # never dereferenced: every call below fails host validation first
 
 
-def mat(n=64, tile=8, ntiles=4, rp=FAKE, ci=FAKE, bits=FAKE, reserved=0):
-    return b2.b2sr_matrix(n, tile, ntiles, reserved, rp, ci, bits)
+def mat(n=64, tile=8, ntiles=4, rp=FAKE, ci=FAKE, bits=FAKE, chunk_blocks=0):
+    return b2.b2sr_matrix(n, tile, ntiles, chunk_blocks, rp, ci, bits)
 
 
 def test_every_declared_function_is_exported():
@@ -40,7 +40,7 @@ def test_matrix_validation():
     S = None
     x = ctypes.c_void_p(FAKE)
     assert L.spmv_bin_bin(None, x, None, 0, x, S) == -1
-    for bad in (mat(tile=6), mat(tile=128), mat(reserved=1), mat(rp=0), mat(ci=0), mat(bits=0),
+    for bad in (mat(tile=6), mat(tile=128), mat(chunk_blocks=65), mat(rp=0), mat(ci=0), mat(bits=0),
                 mat(tile=32, bits=FAKE + 4), mat(tile=64, bits=FAKE + 8), mat(ntiles=10**6, n=64, tile=32)):
         assert L.spmv_bin_bin(ctypes.byref(bad), x, None, 0, x, S) == -1
     assert L.spmv_bin_bin(ctypes.byref(mat(n=0xFFFFFFF0)), x, None, 0, x, S) == -2

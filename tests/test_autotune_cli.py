@@ -24,3 +24,12 @@ def test_cli_rejects_unknown_spec():
     import pytest
     with pytest.raises(ValueError):
         autotune.main(["torus:3", "--no-exact"])
+
+
+def test_prune_keeps_the_widths_near_the_best_estimate():
+    from paper_2201_08560_amd import autotune
+    est = {4: 0.50, 8: 0.30, 16: 0.31, 32: 0.40, 64: 0.70}
+    assert autotune.prune(est) == [8, 16, 32]                 # within 1.5x of 0.30
+    assert autotune.prune(est, slack=1.1) == [8, 16]
+    assert autotune.prune(est, keep=1) == [8]
+    assert autotune.prune({k: 0.0 for k in autotune.TILES}) == list(autotune.TILES)  # nothing sampled
