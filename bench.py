@@ -445,13 +445,18 @@ def batched_section(graphs, reps: int = 3) -> dict:
         log(f"batched {name}: {1e3 * t:.2f} ms")
     same = all(torch.equal(outs[i], B.levels_of(lv, i)) and torch.equal(outs[i], B.levels_of(plan.out, i))
                and torch.equal(outs[i], B.levels_of(plan_p.out, i)) for i in range(count))
+    # where the persistent kernel's time goes: device wall-clock stamps per level and block
+    lvt, _, ph = b2.b2sr_msbfs_batch_timed(B.n, B.groups, B.seed_vertex, B.seed_bit, ws=ws_b)
+    same = same and all(torch.equal(outs[i], B.levels_of(lvt, i)) for i in range(count))
+    phases = {k: {"total_ms": float(v.sum()) / 1e3, "per_level_us": [round(float(x), 1) for x in v]}
+              for k, v in ph.items()}
     plan.close()
     plan_p.close()
     hist = {str(T): tiles.count(T) for T in (4, 8, 16, 32, 64)}
     best = min((k for k in res if k != "per_graph"), key=lambda k: res[k]["ms"])
     return {"graphs": count, "n_total": B.n, "nnz_total": int(sum(g.nnz for g in graphs)),
             "sources_per_graph": 64, "tile_histogram": hist, "batch_tile": batch_tile, "autotune_s": tune_s,
-            "batch_tile_tuning": batch_tune,
+            "batch_tile_tuning": batch_tune, "persistent_phases": phases,
             "modes": res,
             "identical_results": bool(same),
             "speedup_best_batched_vs_per_graph": res["per_graph"]["ms"] / res[best]["ms"]}

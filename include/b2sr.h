@@ -471,6 +471,22 @@ int b2sr_msbfs_batch(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, ui
                      unsigned mode, void *ws, size_t ws_bytes, uint32_t *iters,
                      hipStream_t stream);
 
+/* b2sr_msbfs_batch_timed: b2sr_msbfs_batch in B2SR_BATCH_PERSISTENT mode that
+ * also records where the persistent kernel's time goes.  For each of the first
+ * stamp_levels levels and each of the first stamp_blocks blocks of the grid,
+ * thread 0 of the block writes five readings of the device wall clock
+ * (stamps[((level - 1) * stamp_blocks + block) * 5 + e], e = 0: level start,
+ * 1: the block's product work done, 2: past the first grid barrier, 3: the
+ * block's update done, 4: past the second barrier).  stamps: device uint64_t,
+ * stamp_levels * stamp_blocks * 5 entries, zeroed first (levels not run stay
+ * 0).  *grid_blocks and *clock_khz (HOST) receive the grid size and the wall
+ * clock's rate in kHz.  Synchronises `stream`.  Errors as b2sr_msbfs_batch. */
+int b2sr_msbfs_batch_timed(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t nseeds,
+                           const uint32_t *seed_vertex, const uint32_t *seed_bit, uint32_t *levels,
+                           void *ws, size_t ws_bytes, uint64_t *stamps, uint32_t stamp_levels,
+                           uint32_t stamp_blocks, uint32_t *grid_blocks, uint32_t *clock_khz,
+                           uint32_t *iters, hipStream_t stream);
+
 /* A plan instantiates the batched BFS as hipGraphs once; each launch replays
  * them.  mode B2SR_BATCH_LEVELS: the first graph holds the initialisation, the
  * seeding and 32 levels of per-level kernels, and a second graph 32 more

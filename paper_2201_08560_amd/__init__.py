@@ -24,7 +24,7 @@ __all__ = [
     "mis_keys", "b2sr_eccentricity", "b2sr_diameter",
     "b2sr_algo_workspace_bytes", "b2sr_bfs", "b2sr_msbfs", "b2sr_sssp", "b2sr_cc", "b2sr_pagerank",
     "triangle_count", "b2sr_strerror", "as_u32", "as_u64", "header_functions", "FLAGS", "SEMIRINGS",
-    "b2sr_msbfs_batch", "b2sr_msbfs_batch_workspace_bytes", "MsbfsPlan", "BfsSession",
+    "b2sr_msbfs_batch", "b2sr_msbfs_batch_workspace_bytes", "b2sr_msbfs_batch_timed", "MsbfsPlan", "BfsSession",
     "b2sr_bfs_session_bytes", "b2sr_lgc", "b2sr_sweep_cut",
 ]
 
@@ -103,6 +103,8 @@ _SIGS = {
     "b2sr_csr_transpose": (_I, [_U32, _U64, _P, _P, _P, _P, _P, _SZ, _P]),
     "b2sr_msbfs_batch_workspace_bytes": (_SZ, [_U32]),
     "b2sr_msbfs_batch": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, ctypes.c_uint, _P, _SZ, ctypes.POINTER(_U32), _P]),
+    "b2sr_msbfs_batch_timed": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, _P, _SZ, _P, _U32, _U32,
+                                    ctypes.POINTER(_U32), ctypes.POINTER(_U32), ctypes.POINTER(_U32), _P]),
     "b2sr_msbfs_batch_plan_create": (_I, [_U32, _U32, _MP, _U32, _P, _P, _P, ctypes.c_uint, _P, _SZ,
                                           ctypes.POINTER(_P)]),
     "b2sr_msbfs_batch_plan_launch": (_I, [_P, ctypes.POINTER(_U32), _P]),
@@ -552,6 +554,33 @@ def b2sr_msbfs_batch(n: int, groups, seed_vertex, seed_bit, mode=BATCH_LEVELS, o
     _check(lib().b2sr_msbfs_batch(n, len(groups), views, seed_vertex.numel(), _ptr(seed_vertex), _ptr(seed_bit),
                                   _ptr(out), mode, _ptr(ws), need, ctypes.byref(it), _stream()), "b2sr_msbfs_batch")
     return out, it.value
+
+
+def b2sr_msbfs_batch_timed(n: int, groups, seed_vertex, seed_bit, out=None, ws=None, stamp_levels: int = 64,
+                           stamp_blocks: int = 4096):
+    """The persistent batched BFS with its phase timestamps (b2sr.h).  Returns
+    (levels, levels run, per-level phase times in microseconds: a dict of
+    arrays over the levels run, each the median over blocks except `product`,
+    the span from the earliest start to the last block's product end)."""
+    out = torch.empty((n, 64), dtype=torch.int32, device="cuda") if out is None else out
+    need = b2sr_msbfs_batch_workspace_bytes(n)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda") if ws is None else ws
+    stamps = torch.zeros(stamp_levels * stamp_blocks * 5, dtype=torch.int64, device="cuda")
+    it, grid, khz = _U32(0), _U32(0), _U32(0)
+    _check(lib().b2sr_msbfs_batch_timed(n, len(groups), _views(groups), seed_vertex.numel(), _ptr(seed_vertex),
+                                        _ptr(seed_bit), _ptr(out), _ptr(ws), need, _ptr(stamps), stamp_levels,
+                                        stamp_blocks, ctypes.byref(grid), ctypes.byref(khz), ctypes.byref(it),
+                                        _stream()), "b2sr_msbfs_batch_timed")
+    nb = min(grid.value, stamp_blocks)
+    lv = min(it.value, stamp_levels)
+    a = stamps.view(stamp_levels, stamp_blocks, 5)[:lv, :nb].cpu().numpy().astype(np.float64) * (1e3 / khz.value)
+    start = a[:, :, 0].min(axis=1, keepdims=True)
+    phases = {"product": a[:, :, 1].max(axis=1) - start[:, 0],
+              "product_median_block": np.median(a[:, :, 1] - start, axis=1),
+              "barrier1_wait": np.median(a[:, :, 2] - a[:, :, 1], axis=1),
+              "update": np.median(a[:, :, 3] - a[:, :, 2], axis=1),
+              "barrier2_wait": np.median(a[:, :, 4] - a[:, :, 3], axis=1)}
+    return out, it.value, phases
 
 
 class MsbfsPlan:

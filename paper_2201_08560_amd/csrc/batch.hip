@@ -34,8 +34,9 @@ namespace {
 
 constexpr uint32_t kMaxGroups = 8;
 // Flag words: [0..7] as listed in BatchArgs; the barrier's arrival count and
-// generation 256 bytes apart, each on a line of its own.
-constexpr uint32_t kBarrierCount = 64, kBarrierGen = 128, kFlagWords = 192;
+// generation, and the persistent kernel's two work counters (one per level
+// parity), 256 bytes apart, each on a line of its own.
+constexpr uint32_t kBarrierCount = 64, kBarrierGen = 128, kClaim = 192, kFlagWords = 320;
 constexpr uint32_t kUnreached = 0xFFFFFFFFu;
 
 struct Group {
@@ -58,7 +59,18 @@ struct BatchArgs {
     uint32_t nseeds;
     uint32_t sticky_timeout;  // plans: initialisation leaves flags[5] for the status call to read
     unsigned tmask;  // tile widths present: bit 0 for 4, 1 for 8, 2 for 16, 3 for 32, 4 for 64
+    // persistent kernel, optional: five wall-clock readings per (level, block)
+    unsigned long long *stamps;
+    uint32_t stamp_levels, stamp_blocks;
 };
+
+// Phase timestamps of the persistent kernel (when b.stamps is set): thread 0 of
+// each block records the device wall clock at event ev of `level`.
+__device__ __forceinline__ void stamp(const BatchArgs &b, uint32_t level, uint32_t ev)
+{
+    if (threadIdx.x == 0 && level <= b.stamp_levels && blockIdx.x < b.stamp_blocks)
+        b.stamps[((size_t)(level - 1) * b.stamp_blocks + blockIdx.x) * 5 + ev] = wall_clock64();
+}
 
 __global__ void batch_init_kernel(BatchArgs b)
 {
@@ -73,6 +85,8 @@ __global__ void batch_init_kernel(BatchArgs b)
     for (uint64_t w = tid; w < (b.n + 31) / 32; w += stride) b.act[w] = 0;
     if (tid < 8 && !(tid == 5 && b.sticky_timeout)) b.flags[tid] = 0;
     if (tid == 8) b.flags[kBarrierCount] = 0;
+    if (tid == 9) b.flags[kClaim] = 0;
+    if (tid == 10) b.flags[kClaim + 64] = 0;
 }
 
 // Seeds are distinct (vertex, bit) pairs, so the level writes never collide and
@@ -234,12 +248,16 @@ __device__ __forceinline__ uint32_t grid_barrier(uint32_t *flags, const uint32_t
 constexpr int persistent_waves(unsigned tmask) { return (tmask & 6u) ? B2SR_PW_WIDE : B2SR_PW_SMALL; }
 
 #ifndef B2SR_PERSIST_MAX_PER_CU
-#define B2SR_PERSIST_MAX_PER_CU 2
+#define B2SR_PERSIST_MAX_PER_CU 3
 #endif
 #ifndef B2SR_PERSIST_THREADS
 #define B2SR_PERSIST_THREADS 512  // threads per block of the persistent kernel
 #endif
 constexpr unsigned kPersistThreads = B2SR_PERSIST_THREADS;
+#ifndef B2SR_PERSIST_CLAIM
+#define B2SR_PERSIST_CLAIM 1
+#endif
+constexpr uint32_t kClaimItems = B2SR_PERSIST_CLAIM;  // work items per claim
 
 template <unsigned TMASK>
 __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batch_persistent_kernel(BatchArgs b)
@@ -250,7 +268,23 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
     const uint32_t nwaves = gridDim.x * (blockDim.x / B2SR_WAVE);
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (uint32_t level = 1; level <= b.max_levels; ++level) {
-        for (uint32_t item = wave; item < b.nitems; item += nwaves) {
+        if (b.stamps) stamp(b, level, 0);
+        // Waves claim kClaimItems consecutive work items at a time from this
+        // level's counter, so a wave that drew light chunks takes more of them
+        // (a fixed stride left the heaviest wave 30 % behind the median).  The
+        // counter only grows during the product phase, so every wave leaves
+        // once it passes nitems; the claims a wave makes are also capped at
+        // nitems.  The other parity's counter is reset in the update phase,
+        // between the two barriers, when no wave claims from it.
+        uint32_t *const counter = b.flags + kClaim + (level & 1) * 64;
+        uint32_t claims = 0;
+        for (;;) {
+            uint32_t first = 0;
+            if (lane_id() == 0) first = atomicAdd(counter, kClaimItems);
+            first = readfirstlane(shfl(first, 0));
+            if (first >= b.nitems || ++claims > b.nitems) break;
+            const uint32_t stop = min(b.nitems, first + kClaimItems);
+            for (uint32_t item = first; item < stop; ++item) {
             uint32_t gi = 0;
             while (gi + 1 < b.ngroups && item >= b.g[gi + 1].item0) ++gi;
             const Group &g = b.g[gi];
@@ -270,8 +304,14 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
             if constexpr ((TMASK & 16u) != 0) {
                 if (g.tile == 64) run_chunk<64>(g, c, xs);
             }
+            }
+        }
+        if (b.stamps) {  // uniform: every thread of the grid takes this branch or none
+            __syncthreads();
+            stamp(b, level, 1);
         }
         if (grid_barrier(b.flags, nullptr) & 1u) break;
+        if (b.stamps) stamp(b, level, 2);
         bool any = false;
         for (uint64_t base = (uint64_t)wave * 64; base < b.n; base += (uint64_t)nwaves * 64)
             any |= update_group(b, base, level);
@@ -279,8 +319,14 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
         if (tid == 0) {
             b.flags[(level + 1) & 1] = 0;
             b.flags[2] = level;
+            b.flags[kClaim + ((level + 1) & 1) * 64] = 0;  // the next level's work counter
+        }
+        if (b.stamps) {
+            __syncthreads();
+            stamp(b, level, 3);
         }
         const uint32_t st = grid_barrier(b.flags, b.flags + (level & 1));
+        if (b.stamps) stamp(b, level, 4);
         if ((st & 1u) || !(st & 2u)) break;
     }
 }
@@ -358,7 +404,8 @@ int make_args(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t 
         g.nchunks = (uint32_t)(((uint64_t)A->ntiles + g.p.chunk - 1) / g.p.chunk);
         items += g.nchunks;
     }
-    if (items >= (1ull << 32)) return B2SR_ERANGE;
+    // the persistent kernel's work counter runs past nitems by at most one claim per wave
+    if (items >= (1ull << 32) - (1ull << 24)) return B2SR_ERANGE;
     b.nitems = (uint32_t)items;
     *out = b;
     return B2SR_OK;
@@ -397,8 +444,9 @@ int persistent_grid(const void *kernel, unsigned *grid)
                              "hipOccupancyMaxActiveBlocksPerMultiprocessor"))
         return rc;
     if (per_cu < 1 || !prop.cooperativeLaunch) return B2SR_ENOTSUP;
-    // at most 2 blocks of 512 threads per CU: more blocks meeting at every
-    // barrier measured slower than the extra waves gain
+    // at most B2SR_PERSIST_MAX_PER_CU blocks per CU (the occupancy API's own
+    // figure is lower for the wider tile widths): with work claimed from a
+    // counter, 3 blocks of 512 threads measured best on the 256-graph batch
     if (per_cu > B2SR_PERSIST_MAX_PER_CU) per_cu = B2SR_PERSIST_MAX_PER_CU;
     *grid = (unsigned)per_cu * (unsigned)prop.multiProcessorCount;
     return B2SR_OK;
@@ -543,6 +591,32 @@ int b2sr_msbfs_batch(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, ui
     } while (!h[6]);
     if (iters) *iters = h[2];
     return B2SR_OK;
+}
+
+int b2sr_msbfs_batch_timed(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t nseeds,
+                           const uint32_t *seed_vertex, const uint32_t *seed_bit, uint32_t *levels, void *ws,
+                           size_t ws_bytes, uint64_t *stamps, uint32_t stamp_levels, uint32_t stamp_blocks,
+                           uint32_t *grid_blocks, uint32_t *clock_khz, uint32_t *iters, hipStream_t stream)
+{
+    if (!stamps || !grid_blocks || !clock_khz || stamp_levels == 0 || stamp_blocks == 0) return B2SR_EINVAL;
+    BatchArgs b;
+    int rc = make_args(n, ngroups, groups, nseeds, seed_vertex, seed_bit, levels, ws, ws_bytes, &b);
+    if (rc) return rc;
+    unsigned grid = 0;
+    if ((rc = persistent_grid(persistent_kernel(b.tmask), &grid))) return rc;
+    int dev = 0, khz = 0;
+    if ((rc = b2sr::check(hipGetDevice(&dev), "hipGetDevice"))) return rc;
+    if ((rc = b2sr::check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "hipDeviceGetAttribute")))
+        return rc;
+    *grid_blocks = grid;
+    *clock_khz = (uint32_t)khz;
+    b.stamps = (unsigned long long *)stamps;
+    b.stamp_levels = stamp_levels;
+    b.stamp_blocks = stamp_blocks;
+    if ((rc = b2sr::fill_u32((uint32_t *)stamps, (uint64_t)stamp_levels * stamp_blocks * 10, 0, stream))) return rc;
+    if ((rc = launch_init(b, stream))) return rc;
+    if ((rc = launch_persistent(b, stream))) return rc;
+    return finish_persistent(b, iters, stream);
 }
 
 int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t nseeds,

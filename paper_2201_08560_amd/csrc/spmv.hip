@@ -44,7 +44,7 @@ namespace {
 #define B2SR_W32_PLUS 5
 #endif
 #ifndef B2SR_W32_MIN
-#define B2SR_W32_MIN 6
+#define B2SR_W32_MIN 5
 #endif
 #ifndef B2SR_W32_U64
 #define B2SR_W32_U64 6

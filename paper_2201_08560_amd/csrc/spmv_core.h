@@ -564,6 +564,33 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 R Sr[JK];
 #pragma unroll
                 for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>(p.xact, Jr[k], p.n);
+                // A block none of whose tiles has an active column contributes the
+                // identity: nothing of it is loaded or staged; only the row the
+                // block ends in is followed, and a row that ends inside it is stored.
+                bool act_any = false;
+#pragma unroll
+                for (int k = 0; k < JK; ++k)
+                    act_any |= Sr[k] != 0 && 64 * k + lane < (uint32_t)BT && blk + 64 * k + lane < t_end;
+                if (!__any(act_any)) {
+                    const uint32_t last = min(blk + BT, t_end) - 1;
+                    if (last >= r_end) {
+                        V tot[NV];
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) {
+                            tot[k] = acc[k];
+#pragma unroll
+                            for (int d = LPT; d < 64; d <<= 1) tot[k] = KT::op(tot[k], shfl_xor(tot[k], d));
+                            acc[k] = KT::id();
+                        }
+                        if (grp == 0)
+                            store_values<T, K>(p, r_cur, sub, keep, tot, straddles(r_cur), chunk_id, slot_of(r_cur));
+                        r_cur = readfirstlane(lane_row(p.trp, p.ntr, r_cur, last));
+                        r_end = p.trp[r_cur + 1];
+                        keep = keep_bits<T>(p.mask, p.flags, r_cur, p.n);
+                    }
+                    blk += BT;
+                    continue;
+                }
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
                     const uint32_t ti = i * TPW + grp;

@@ -163,3 +163,16 @@ def test_batch_tile_is_the_least_summed_cost():
     T, rep = autotune.choose_batch_tile(graphs)
     assert rep["cost"] == pytest.approx(total)
     assert T == min(total, key=lambda k: (total[k], k))
+
+
+def test_persistent_phase_timestamps(batch):
+    """The timed persistent launch gives the same levels, and its per-level
+    phase times are non-negative and add up within the run."""
+    ref, it = batch.run(b2.BATCH_PERSISTENT)
+    lv, it2, ph = b2.b2sr_msbfs_batch_timed(batch.n, batch.groups, batch.seed_vertex, batch.seed_bit)
+    assert it2 == it and torch.equal(lv, ref)
+    check_all(batch, lv)
+    assert set(ph) == {"product", "product_median_block", "barrier1_wait", "update", "barrier2_wait"}
+    for k, v in ph.items():
+        assert v.shape == (min(it, 64),) and np.all(v >= 0), k
+    assert np.all(ph["product_median_block"] <= ph["product"] + 1e-6)
