@@ -314,8 +314,13 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
 
 /* ---- graph algorithms on the products above (Sec. V) ---------------------
  * Each driver runs its iteration loop on the host, launching the kernels
- * above on `stream`, and reads one device flag per iteration to test
- * convergence (so it synchronises `stream`).  The number of iterations run is
+ * above on `stream`, and synchronises `stream` to test convergence.  BFS,
+ * multi-source BFS, SSSP and CC keep their convergence state on the device:
+ * every kernel of an iteration is gated on it, the host enqueues iterations in
+ * batches of 2, 4, 8 and then 16 and reads the state once per batch, and the
+ * iterations enqueued past the end return at once.  MIS, colouring and
+ * eccentricity read one device word per iteration; PageRank runs a fixed
+ * number of iterations and reads nothing.  The number of iterations run is
  * written to the HOST pointer *iters when it is not NULL.  ws is a workspace
  * of b2sr_algo_workspace_bytes(A, algo) bytes.  The drivers read A as the
  * pull matrix: row i lists the vertices whose edges reach i, so each product
@@ -339,8 +344,10 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
 size_t b2sr_algo_workspace_bytes(const b2sr_matrix *A, int algo);
 
 /* BFS (Sec. V): Boolean semiring, masked bin_bin_bin product per level with
- * the complement of the visited set as the mask.  levels (uint32_t[n]):
- * levels[src] = 0, unreachable = 0xFFFFFFFF. */
+ * the complement of the visited set as the mask (a level whose frontier holds
+ * fewer vertices than A has tile-rows reads only the tiles behind a non-empty
+ * frontier segment).  levels (uint32_t[n]): levels[src] = 0, unreachable =
+ * 0xFFFFFFFF.  *iters = levels run, the last one finding nothing. */
 int b2sr_bfs(const b2sr_matrix *A, uint32_t src, uint32_t *levels, void *ws, size_t ws_bytes,
              uint32_t *iters, hipStream_t stream);
 
@@ -360,7 +367,8 @@ int b2sr_sssp(const b2sr_matrix *A, uint32_t src, uint32_t *dist, void *ws, size
 
 /* Connected components (Sec. V): min-label propagation, x = min(x, A x) under
  * min-plus over uint32 with zero edge weight, from x_i = i to a fixpoint.
- * labels (uint32_t[n]) ends as the smallest vertex id of each component. */
+ * labels (uint32_t[n], 16-byte aligned: it is one of the two iterates the
+ * product reads as x) ends as the smallest vertex id of each component. */
 int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, uint32_t *iters,
             hipStream_t stream);
 

@@ -1,9 +1,16 @@
 // Graph algorithms on the B2SR products (Sec. V): BFS, multi-source BFS,
-// SSSP, connected components and PageRank.  Each driver runs its loop on the
-// host and launches the product kernels plus a small element-wise update
-// kernel per iteration; convergence is read back as one device word per
-// iteration (the flags alternate between two words so the update kernel can
-// clear the next one, which saves a launch).
+// SSSP, connected components and PageRank.  Each driver launches the product
+// kernels plus a small element-wise update kernel per iteration.
+//
+// BFS, multi-source BFS, SSSP and CC keep their convergence on the device: a
+// state word says how the next iteration runs (a dense or a sparse-frontier
+// product) or that the algorithm has finished, and every kernel of an
+// iteration returns at once when the state does not select it.  The host
+// enqueues iterations in growing batches (2, 4, 8, then 16) and reads the
+// state once per batch, instead of once per iteration; iterations enqueued
+// after the end cost one empty launch each.  Per-iteration counts alternate
+// between two words so the kernel that advances the state can clear the next
+// one.
 #include <algorithm>
 #include <utility>
 
@@ -12,9 +19,16 @@
 using namespace b2sr_dev;
 
 namespace b2sr {
-int fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
 int column_counts(const b2sr_matrix *A, uint32_t *colsum, hipStream_t s);
 size_t lgc_workspace_bytes(const b2sr_matrix *A);
+// The products with every kernel gated on *gate (spmv.hip): the bit product
+// runs when it is gate_val, and with B2SR_SPARSE_X when it is gate_sparse; the
+// full product runs when it is gate_val and takes B2SR_MIN_PLUS_U32 and
+// B2SR_OR_U64 only.
+int spmv_bits_gated(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, unsigned flags, void *y,
+                    const uint32_t *gate, uint32_t gate_val, uint32_t gate_sparse, hipStream_t stream);
+int spmv_full_gated(const b2sr_matrix *A, int semiring, const void *x, const uint32_t *x_active, unsigned flags,
+                    double alpha, void *y, const uint32_t *gate, uint32_t gate_val, hipStream_t stream);
 }
 
 namespace {
@@ -35,6 +49,62 @@ struct Carver {
     }
 };
 
+// flags[0..1]: per-iteration counts (by parity); flags[2]: the next
+// iteration's run state; flags[3]: iterations run; flags[4]: see below;
+// flags[5], flags[6]: the last iteration's count and the one before.
+constexpr uint32_t kRunDense = 0, kRunSparse = 1, kDone = 2, kFlagWords = 8;
+
+// flags[4]: blocks of the running update kernel that have finished.
+//
+// Run by every thread of a gated update kernel once its block's count is
+// added.  The last block to finish advances the state: none found ends the run
+// (as does the iteration bound), otherwise the next iteration runs the
+// sparse-frontier product when fewer than sparse_below were found; it also
+// clears the next iteration's count and the block counter.
+__device__ void advance_when_last(uint32_t *flags, uint32_t sparse_below, uint32_t max_iters)
+{
+    __shared__ uint32_t last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(flags + 4, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
+    const uint32_t it = flags[3] + 1;  // the iteration that just ran
+    const uint32_t found = atomicAdd(flags + (it & 1), 0u);
+    // atomic writes, as the other blocks' counts in the same words were
+    atomicExch(flags + 6, atomicExch(flags + 5, found));
+    atomicExch(flags + 4, 0u);
+    atomicExch(flags + 3, it);
+    atomicExch(flags + ((it + 1) & 1), 0u);
+    atomicExch(flags + 2, (found == 0 || it >= max_iters) ? kDone : (found < sparse_below ? kRunSparse : kRunDense));
+}
+
+// Runs `one(iteration index)` in batches, reading the device state after each
+// batch (which synchronises the stream), until the device reports the run
+// finished (the last block of an update ends it by max_iters at the latest).
+// Batches double from 2 up to 16 iterations while the counts grow or hold,
+// and fall back to 2 once they shrink: a shrinking frontier is near its end,
+// where every iteration enqueued after the last costs empty launches.
+template <class F> int run_gated(const uint32_t *flags, uint32_t max_iters, uint32_t *iters, hipStream_t s, F one)
+{
+    uint32_t enq = 0, batch = 2;
+    uint32_t h[5] = {kRunDense, 0, 0, 0, 0};  // flags[2..6]
+    for (;;) {
+        for (uint32_t k = 0; k < batch; ++k)
+            if (int rc = one(++enq)) return rc;
+        if (int rc = b2sr::check(hipMemcpyAsync(h, flags + 2, sizeof h, hipMemcpyDeviceToHost, s),
+                                 "hipMemcpyAsync(state)"))
+            return rc;
+        if (int rc = b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize")) return rc;
+        if (h[0] == kDone) break;
+        if (enq > max_iters + 1) return B2SR_EHIP;  // cannot happen: the run ends by max_iters
+        batch = h[3] < h[4] ? 2u : std::min<uint32_t>(batch * 2, 16);
+    }
+    if (iters) *iters = h[1];
+    return B2SR_OK;
+}
+
 int read_flag(const uint32_t *d_flag, uint32_t *h, hipStream_t s)
 {
     if (int rc = b2sr::check(hipMemcpyAsync(h, d_flag, sizeof *h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync(flag)"))
@@ -44,7 +114,7 @@ int read_flag(const uint32_t *d_flag, uint32_t *h, hipStream_t s)
 
 // ---------------------------------------------------------------- BFS
 __global__ void bfs_init_kernel(uint32_t n, uint32_t src, uint32_t *levels, uint32_t *frontier, uint32_t *visited,
-                                uint32_t *flags)
+                                uint32_t *next, uint32_t *flags, uint32_t first_state)
 {
     const uint32_t nw = (n + 31) / 32;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -53,20 +123,27 @@ __global__ void bfs_init_kernel(uint32_t n, uint32_t src, uint32_t *levels, uint
             const uint32_t w = (i == src / 32) ? (1u << (src % 32)) : 0u;
             frontier[i] = w;
             visited[i] = w;
+            next[i] = 0;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kFlagWords) flags[threadIdx.x] = threadIdx.x == 2 ? first_state : 0u;
 }
 
 // Newly reached vertices (next is already masked by NOT visited) get this
-// level and join the visited set; *flag_now receives how many there were.
-__global__ void bfs_update_kernel(uint32_t nw, const uint32_t *next, uint32_t *visited, uint32_t *levels,
-                                  uint32_t level, uint32_t *flag_now, uint32_t *flag_next)
+// level, join the visited set and form the next frontier; next is cleared for
+// the next product, which accumulates into it; the level's count of found
+// vertices goes to its parity's word.
+__global__ void bfs_update_gated_kernel(uint32_t nw, uint32_t *next, uint32_t *frontier, uint32_t *visited,
+                                        uint32_t *levels, uint32_t *flags, uint32_t sparse_below, uint32_t max_iters)
 {
+    if (flags[2] == kDone) return;
+    const uint32_t level = flags[3] + 1;
     uint32_t found = 0;
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t nb = next[w];
+        frontier[w] = nb;
         if (!nb) continue;
+        next[w] = 0;
         found += __popc(nb);
         visited[w] |= nb;
         while (nb) {
@@ -76,8 +153,8 @@ __global__ void bfs_update_kernel(uint32_t nw, const uint32_t *next, uint32_t *v
         }
     }
     for (int d = 32; d >= 1; d >>= 1) found += shfl_xor(found, d);
-    if (lane_id() == 0 && found) atomicAdd(flag_now, found);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
+    if (lane_id() == 0 && found) atomicAdd(flags + (level & 1), found);
+    advance_when_last(flags, sparse_below, max_iters);
 }
 
 // ---------------------------------------------------------------- multi-source BFS
@@ -91,7 +168,7 @@ __global__ void msbfs_init_kernel(uint32_t n, uint32_t nsrc, const uint32_t *src
         F[i] = 0;
         V[i] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kFlagWords) flags[threadIdx.x] = 0;  // state: dense
 }
 
 __global__ void msbfs_seed_kernel(uint32_t n, uint32_t nsrc, const uint32_t *srcs, uint64_t *F, uint64_t *V,
@@ -173,8 +250,10 @@ __global__ void ecc_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, ui
 // the active bit vector (frontier word non-zero) for the next product.  Each
 // wave walks 64 consecutive vertices at a time, so the ballot forms whole words.
 __global__ void msbfs_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, uint64_t *V, uint32_t *levels,
-                                    uint32_t level, uint32_t *act, uint32_t *flag_now, uint32_t *flag_next)
+                                    uint32_t *act, uint32_t *flags, uint32_t max_iters)
 {
+    if (flags[2] == kDone) return;
+    const uint32_t level = flags[3] + 1;
     bool any = false;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
     for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
@@ -197,8 +276,8 @@ __global__ void msbfs_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, 
         }
         store_pred_bits(act, base, n, y != 0);
     }
-    if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(flag_now, 1u);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
+    if (__syncthreads_or(any) && threadIdx.x == 0) atomicAdd(flags + (level & 1), 1u);
+    advance_when_last(flags, 0, max_iters);
 }
 
 // ---------------------------------------------------------------- SSSP / CC
@@ -209,15 +288,16 @@ __global__ void sssp_init_kernel(uint32_t n, uint32_t src, uint32_t *d, uint32_t
         d[i] = i == src ? 0u : kUnreached;
         if (i < nw) act[i] = i == src / 32 ? 1u << (src % 32) : 0u;
     }
-    if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kFlagWords) flags[threadIdx.x] = 0;  // state: dense
 }
 
 // Entries that changed between two iterates: the active bit vector of the next
-// product and the convergence flag.
-template <class V>
-__global__ void changed_kernel(uint32_t n, const V *a, const V *b, uint32_t *act, uint32_t *flag_now,
-                               uint32_t *flag_next)
+// product and the iteration's count (of blocks with a change).
+__global__ void changed_kernel(uint32_t n, const uint32_t *a, const uint32_t *b, uint32_t *act, uint32_t *flags,
+                               uint32_t max_iters)
 {
+    if (flags[2] == kDone) return;
+    const uint32_t it = flags[3] + 1;
     bool diff = false;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
     for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
@@ -227,15 +307,15 @@ __global__ void changed_kernel(uint32_t n, const V *a, const V *b, uint32_t *act
         diff |= d;
         store_pred_bits(act, base, n, d);
     }
-    if (__syncthreads_or(diff) && threadIdx.x == 0) atomicOr(flag_now, 1u);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
+    if (__syncthreads_or(diff) && threadIdx.x == 0) atomicAdd(flags + (it & 1), 1u);
+    advance_when_last(flags, 0, max_iters);
 }
 
 __global__ void iota_kernel(uint32_t n, uint32_t *x, uint32_t *flags)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         x[i] = (uint32_t)i;
-    if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kFlagWords) flags[threadIdx.x] = 0;  // state: dense
 }
 
 __global__ void copy_u32_kernel(uint32_t n, const uint32_t *a, uint32_t *b)
@@ -418,7 +498,7 @@ Layout carve(const b2sr_matrix *A, int algo, void *ws)
         break;
     default: break;
     }
-    L.flags = c.take<uint32_t>(2 * 4);
+    L.flags = c.take<uint32_t>(kFlagWords * 4);
     L.bytes = c.off;
     return L;
 }
@@ -451,26 +531,25 @@ int b2sr_bfs(const b2sr_matrix *A, uint32_t src, uint32_t *levels, void *ws, siz
     int rc = check_algo_args(A, B2SR_ALGO_BFS, ws, ws_bytes, &L);
     if (rc) return rc;
     if (!levels || src >= A->n) return B2SR_EINVAL;
-    const uint32_t n = A->n, nw = b2sr::n_words(n);
-    bfs_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, levels, L.frontier, L.visited, L.flags);
-    if ((rc = b2sr::check_launch("bfs_init_kernel"))) return rc;
+    const uint32_t n = A->n, nw = b2sr::n_words(n), max_iters = n + 1;
     // A frontier with fewer vertices than there are tile columns leaves most x
     // segments empty: then tiles are read only behind a non-empty segment.
     const uint32_t sparse_below = b2sr::n_tile_rows(n, A->tile);
-    uint32_t level = 0, frontier_size = 1;
-    for (;;) {
-        ++level;
-        const unsigned fl = B2SR_MASK_COMPLEMENT | (frontier_size < sparse_below ? B2SR_SPARSE_X : 0u);
-        if ((rc = spmv_bin_bin(A, L.frontier, L.visited, fl, L.next, stream))) return rc;
-        uint32_t *fnow = L.flags + (level & 1), *fnext = L.flags + ((level + 1) & 1);
-        bfs_update_kernel<<<fgrid(nw), 256, 0, stream>>>(nw, L.next, L.visited, levels, level, fnow, fnext);
-        if ((rc = b2sr::check_launch("bfs_update_kernel"))) return rc;
-        if ((rc = read_flag(fnow, &frontier_size, stream))) return rc;
-        if (!frontier_size) break;
-        std::swap(L.frontier, L.next);
-    }
-    if (iters) *iters = level;
-    return B2SR_OK;
+    bfs_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, levels, L.frontier, L.visited, L.next, L.flags,
+                                                  1 < sparse_below ? kRunSparse : kRunDense);
+    if ((rc = b2sr::check_launch("bfs_init_kernel"))) return rc;
+    const uint32_t *state = L.flags + 2;
+    // next = A frontier over unvisited rows, OR-ed into the cleared next; the
+    // update consumes and clears next, so no buffers swap
+    return run_gated(L.flags, max_iters, iters, stream, [&](uint32_t) {
+        // one launch: the dense form, or the sparse-frontier one, as the state says
+        if (int r = b2sr::spmv_bits_gated(A, L.frontier, L.visited, B2SR_MASK_COMPLEMENT | B2SR_ACCUMULATE, L.next,
+                                          state, kRunDense, kRunSparse, stream))
+            return r;
+        bfs_update_gated_kernel<<<fgrid(nw), 256, 0, stream>>>(nw, L.next, L.frontier, L.visited, levels, L.flags,
+                                                               sparse_below, max_iters);
+        return b2sr::check_launch("bfs_update_gated_kernel");
+    });
 }
 
 int b2sr_msbfs(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32_t *levels, void *ws,
@@ -485,7 +564,7 @@ int b2sr_msbfs(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32
         for (uint32_t q = 0; q < s; ++q)
             if (srcs[q] == srcs[s]) return B2SR_EINVAL;
     }
-    const uint32_t n = A->n;
+    const uint32_t n = A->n, max_iters = n + 1;
     if ((rc = b2sr::check(hipMemcpyAsync(L.srcs, srcs, nsrc * 4, hipMemcpyHostToDevice, stream), "hipMemcpyAsync(srcs)")))
         return rc;
     msbfs_init_kernel<<<vgrid((uint64_t)nsrc * n), 256, 0, stream>>>(n, nsrc, L.srcs, L.F, L.V, levels, L.flags);
@@ -493,20 +572,47 @@ int b2sr_msbfs(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32
     if ((rc = b2sr::fill_u32(L.act, b2sr::n_words(n), 0, stream))) return rc;
     msbfs_seed_kernel<<<1, 64, 0, stream>>>(n, nsrc, L.srcs, L.F, L.V, levels, L.act);
     if ((rc = b2sr::check_launch("msbfs_seed_kernel"))) return rc;
-    uint32_t level = 0;
-    for (;;) {
-        ++level;
+    // srcs is read by the seed kernel above; the caller may reuse it once the
+    // first state read has synchronised the stream
+    return run_gated(L.flags, max_iters, iters, stream, [&](uint32_t) {
         // only frontier words that are non-zero take part in the product
-        if ((rc = spmv_bin_full(A, B2SR_OR_U64, L.F, nullptr, L.act, nullptr, 0, 0.0, 0.0, L.Y, nullptr, 0, stream)))
-            return rc;
-        uint32_t *fnow = L.flags + (level & 1), *fnext = L.flags + ((level + 1) & 1);
-        msbfs_update_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, levels, level, L.act, fnow, fnext);
-        if ((rc = b2sr::check_launch("msbfs_update_kernel"))) return rc;
-        uint32_t any = 0;
-        if ((rc = read_flag(fnow, &any, stream))) return rc;
-        if (!any) break;
+        if (int r = b2sr::spmv_full_gated(A, B2SR_OR_U64, L.F, L.act, 0, 0.0, L.Y, L.flags + 2, kRunDense, stream))
+            return r;
+        msbfs_update_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, levels, L.act, L.flags, max_iters);
+        return b2sr::check_launch("msbfs_update_kernel");
+    });
+}
+
+// Min-plus iterations with the SELF term until no entry changes.  Iteration k
+// reads buf[(k - 1) & 1] and writes buf[k & 1]; the enqueued iterations that run
+// are exactly the first ones, so the host picks the buffers by enqueue index.
+// Only entries that changed last iteration can improve a neighbour (the others
+// were folded in when they changed), so the product reads those alone.  Leaves
+// the result in buf[0].
+int min_plus_to_fixpoint(const b2sr_matrix *A, uint32_t weight, uint32_t *buf0, uint32_t *buf1, const Layout &L,
+                         uint32_t *iters, hipStream_t stream)
+{
+    const uint32_t n = A->n, max_iters = n + 1;
+    uint32_t *buf[2] = {buf0, buf1};
+    uint32_t done = 0;
+    int rc = run_gated(L.flags, max_iters, &done, stream, [&](uint32_t k) {
+        const uint32_t *cur = buf[(k - 1) & 1];
+        uint32_t *nxt = buf[k & 1];
+        if (int r = b2sr::spmv_full_gated(A, B2SR_MIN_PLUS_U32, cur, L.act, B2SR_SELF, (double)weight, nxt,
+                                          L.flags + 2, kRunDense, stream))
+            return r;
+        changed_kernel<<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, L.act, L.flags, max_iters);
+        return b2sr::check_launch("changed_kernel");
+    });
+    if (rc) return rc;
+    // the last iteration changed nothing, so both buffers hold the result; the
+    // iteration bound (never reached: a change lowers some entry, and entries
+    // settle within n rounds) would leave it in buf[done & 1]
+    if (done & 1) {
+        copy_u32_kernel<<<vgrid(n), 256, 0, stream>>>(n, buf1, buf0);
+        if ((rc = b2sr::check_launch("copy_u32_kernel"))) return rc;
     }
-    if (iters) *iters = level;
+    if (iters) *iters = done;
     return B2SR_OK;
 }
 
@@ -521,27 +627,9 @@ int b2sr_sssp(const b2sr_matrix *A, uint32_t src, uint32_t *dist, void *ws, size
     sssp_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, L.u0, L.act, L.flags);
     if ((rc = b2sr::check_launch("sssp_init_kernel"))) return rc;
     // hop counts in uint32 with saturating addition: exact for every n
-    uint32_t *cur = L.u0, *nxt = L.u1;
-    uint32_t it = 0;
-    for (;;) {
-        ++it;
-        // only distances that changed last iteration can improve a neighbour; the
-        // others were folded in when they changed (the SELF term keeps x_i)
-        if ((rc = spmv_bin_full(A, B2SR_MIN_PLUS_U32, cur, nullptr, L.act, nullptr, B2SR_SELF, 1.0, 0.0, nxt, nullptr,
-                                0, stream)))
-            return rc;
-        uint32_t *fnow = L.flags + (it & 1), *fnext = L.flags + ((it + 1) & 1);
-        changed_kernel<uint32_t><<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, L.act, fnow, fnext);
-        if ((rc = b2sr::check_launch("changed_kernel"))) return rc;
-        uint32_t any = 0;
-        if ((rc = read_flag(fnow, &any, stream))) return rc;
-        std::swap(cur, nxt);
-        if (!any) break;
-    }
-    copy_u32_kernel<<<vgrid(n), 256, 0, stream>>>(n, cur, dist);
-    if ((rc = b2sr::check_launch("copy_u32_kernel"))) return rc;
-    if (iters) *iters = it;
-    return B2SR_OK;
+    if ((rc = min_plus_to_fixpoint(A, 1, L.u0, L.u1, L, iters, stream))) return rc;
+    copy_u32_kernel<<<vgrid(n), 256, 0, stream>>>(n, L.u0, dist);
+    return b2sr::check_launch("copy_u32_kernel");
 }
 
 int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, uint32_t *iters, hipStream_t stream)
@@ -550,32 +638,13 @@ int b2sr_cc(const b2sr_matrix *A, uint32_t *labels, void *ws, size_t ws_bytes, u
     int rc = check_algo_args(A, B2SR_ALGO_CC, ws, ws_bytes, &L);
     if (rc) return rc;
     if (!labels) return B2SR_EINVAL;
+    if ((uintptr_t)labels & 15) return B2SR_EINVAL;  // the product reads x as 16-byte vectors
     const uint32_t n = A->n;
     iota_kernel<<<vgrid(n), 256, 0, stream>>>(n, labels, L.flags);
     if ((rc = b2sr::check_launch("iota_kernel"))) return rc;
     ones_bits_kernel<<<vgrid(b2sr::n_words(n)), 256, 0, stream>>>(n, L.act);  // every label starts active
     if ((rc = b2sr::check_launch("ones_bits_kernel"))) return rc;
-    uint32_t *cur = labels, *nxt = L.u0;
-    uint32_t it = 0;
-    for (;;) {
-        ++it;
-        if ((rc = spmv_bin_full(A, B2SR_MIN_PLUS_U32, cur, nullptr, L.act, nullptr, B2SR_SELF, 0.0, 0.0, nxt, nullptr,
-                                0, stream)))
-            return rc;
-        uint32_t *fnow = L.flags + (it & 1), *fnext = L.flags + ((it + 1) & 1);
-        changed_kernel<uint32_t><<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, L.act, fnow, fnext);
-        if ((rc = b2sr::check_launch("changed_kernel"))) return rc;
-        uint32_t any = 0;
-        if ((rc = read_flag(fnow, &any, stream))) return rc;
-        std::swap(cur, nxt);
-        if (!any) break;
-    }
-    if (cur != labels) {
-        copy_u32_kernel<<<vgrid(n), 256, 0, stream>>>(n, cur, labels);
-        if ((rc = b2sr::check_launch("copy_u32_kernel"))) return rc;
-    }
-    if (iters) *iters = it;
-    return B2SR_OK;
+    return min_plus_to_fixpoint(A, 0, labels, L.u0, L, iters, stream);
 }
 
 }  // extern "C"

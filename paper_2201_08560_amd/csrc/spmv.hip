@@ -83,7 +83,15 @@ __global__ void __launch_bounds__(256, waves_hint(T, K)) spmv_kernel(SpmvArgs p)
     constexpr bool stage = Cfg<T, K>::kStage;
     __shared__ __align__(16) V s_x[stage ? 4 * kSliceBytes / sizeof(V) : 1];
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
-    if (wave * p.chunk >= p.ntiles) return;
+    if (wave * p.chunk >= p.ntiles || gated_off(p)) return;
+    if constexpr (K == kBits) {
+        if (p.gate && p.gate_sparse != p.gate_val && *p.gate == p.gate_sparse) {
+            SpmvArgs q = p;
+            q.flags |= B2SR_SPARSE_X;
+            spmv_chunk<T, K, ACT, SHORT>(q, (uint32_t)wave, s_x);
+            return;
+        }
+    }
     spmv_chunk<T, K, ACT, SHORT>(p, (uint32_t)wave,
                                  s_x + (stage ? (threadIdx.x / B2SR_WAVE) * kSliceBytes / sizeof(V) : 0));
 }
@@ -96,7 +104,7 @@ __global__ void __launch_bounds__(256, waves_hint(T, K)) spmv_kernel(SpmvArgs p)
 template <int T> __global__ void __launch_bounds__(256) plus_fixup_kernel(SpmvArgs p, uint32_t nchunks)
 {
     const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= (uint64_t)nchunks * T) return;
+    if (id >= (uint64_t)nchunks * T || gated_off(p)) return;
     const uint32_t c = (uint32_t)(id / T), r = (uint32_t)(id % T);
     const uint32_t t_begin = c * p.chunk, t_end = min(t_begin + p.chunk, p.ntiles);
     const uint32_t r_first = p.ws_rows[2 * c], R = p.ws_rows[2 * c + 1];
@@ -119,6 +127,7 @@ template <int K> __global__ void init_values_kernel(SpmvArgs p)
 {
     using KT = KindTraits<K>;
     using V = typename KT::V;
+    if (gated_off(p)) return;
     const bool accumulate = p.flags & B2SR_ACCUMULATE;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += (uint64_t)gridDim.x * blockDim.x) {
         bool keep = true;
@@ -146,8 +155,10 @@ __global__ void scale_x_kernel(uint32_t n, const float *__restrict__ x, const fl
         z[i] = x[i] * s[i];
 }
 
-__global__ void zero_words_kernel(uint32_t *__restrict__ y, uint32_t nwords)
+__global__ void zero_words_kernel(SpmvArgs p, uint32_t nwords)
 {
+    if (gated_off(p)) return;
+    uint32_t *__restrict__ y = (uint32_t *)p.y;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) y[i] = 0;
 }
 
@@ -165,7 +176,7 @@ template <int T, int K> int launch(SpmvArgs p, hipStream_t stream)
     if (!(p.flags & B2SR_ACCUMULATE) || K >= kPlusF32) {
         if constexpr (K == kBits) {
             const uint32_t nw = b2sr::n_words(p.n);
-            zero_words_kernel<<<b2sr::grid_for(nw, 256, 4096), 256, 0, stream>>>((uint32_t *)p.y, nw);
+            zero_words_kernel<<<b2sr::grid_for(nw, 256, 4096), 256, 0, stream>>>(p, nw);
         } else {
             init_values_kernel<K><<<b2sr::grid_for(p.n, 256, 8192), 256, 0, stream>>>(p);
         }
@@ -367,3 +378,44 @@ int spmv_bin_full_noalloc(const b2sr_matrix *A, int semiring, const void *x, con
 }
 
 }  // extern "C"
+
+namespace b2sr {
+// The products for the algorithm drivers' gated iterations: every kernel of the
+// launch returns at once unless *gate is gate_val (or, for the bit product,
+// gate_sparse, which runs it with B2SR_SPARSE_X); arguments as the public
+// calls, validated by the drivers; no plus-times, so no workspace.
+int spmv_bits_gated(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, unsigned flags, void *y,
+                    const uint32_t *gate, uint32_t gate_val, uint32_t gate_sparse, hipStream_t stream)
+{
+    SpmvArgs p = make_args(A);
+    p.x = x;
+    p.mask = mask;
+    p.flags = flags;
+    p.y = y;
+    p.gate = gate;
+    p.gate_val = gate_val;
+    p.gate_sparse = gate_sparse;
+    if (flags & B2SR_OUT_COUNT) return dispatch<kCount>(A->tile, p, stream);
+    return dispatch<kBits>(A->tile, p, stream);
+}
+
+int spmv_full_gated(const b2sr_matrix *A, int semiring, const void *x, const uint32_t *x_active, unsigned flags,
+                    double alpha, void *y, const uint32_t *gate, uint32_t gate_val, hipStream_t stream)
+{
+    SpmvArgs p = make_args(A);
+    p.x = x;
+    p.xact = x_active;
+    p.flags = flags;
+    p.alpha = (float)alpha;
+    p.w_u32 = semiring == B2SR_MIN_PLUS_U32 ? (uint32_t)alpha : 0u;
+    p.y = y;
+    p.gate = gate;
+    p.gate_val = gate_val;
+    p.gate_sparse = gate_val;
+    switch (semiring) {
+    case B2SR_MIN_PLUS_U32: return dispatch<kMinU32>(A->tile, p, stream);
+    case B2SR_OR_U64: return dispatch<kOr64>(A->tile, p, stream);
+    default: return B2SR_ENOTSUP;
+    }
+}
+}  // namespace b2sr

@@ -101,7 +101,18 @@ struct SpmvArgs {
     float *ws_part;     // float sums: partials of straddling rows, 2*T per chunk
     uint32_t x_whole;   // n is a multiple of T: no x segment is cut short
     uint32_t chunk_blocks;  // blocks per wave chunk (0: sized from the tile count)
+    // Iteration gating (the algorithm drivers): when gate is set, every kernel
+    // of the product returns at once unless *gate is gate_val or gate_sparse;
+    // a bit product runs with B2SR_SPARSE_X when it is gate_sparse (the two
+    // are equal when the driver has no sparse form).
+    const uint32_t *gate;
+    uint32_t gate_val, gate_sparse;
 };
+
+__device__ __forceinline__ bool gated_off(const SpmvArgs &p)
+{
+    return p.gate && *p.gate != p.gate_val && *p.gate != p.gate_sparse;
+}
 
 // Block shape per tile width and kind.  Bit and count products read the x
 // segment as T bits; the others stage T values per tile in LDS (a fixed budget
@@ -526,6 +537,31 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 // read a tile only when its x segment has a set bit
 #pragma unroll
                 for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k], p.n);
+                if constexpr (K == kBits) {
+                    // A block none of whose tiles meets a set x bit adds nothing: only
+                    // the row it ends in is followed, and a row that ends inside it is
+                    // stored.
+                    bool seg_any = false;
+#pragma unroll
+                    for (int k = 0; k < JK; ++k)
+                        seg_any |= Sr[k] != 0 && 64 * k + lane < (uint32_t)BT && blk + 64 * k + lane < t_end;
+                    if (!__any(seg_any)) {
+                        const uint32_t last = min(blk + BT, t_end) - 1;
+                        if (last >= r_end) {
+                            fold_raw();
+                            R acc_all = acc[0];
+#pragma unroll
+                            for (int d = 1; d < 64; d <<= 1) acc_all |= shfl_xor(acc_all, d);
+                            if (lane == 0) store_bits<T>(p, r_cur, acc_all & keep);
+                            acc[0] = 0;
+                            r_cur = readfirstlane(lane_row(p.trp, p.ntr, r_cur, last));
+                            r_end = p.trp[r_cur + 1];
+                            keep = keep_bits<T>(p.mask, p.flags, r_cur, p.n);
+                        }
+                        blk += BT;
+                        continue;
+                    }
+                }
 #pragma unroll
                 for (int i = 0; i < U; ++i) {
                     const uint32_t ti = i * TPW + grp;

@@ -425,6 +425,12 @@ def test_triangle_count_closed_forms():
 
 # ------------------------------------------------------------------ algorithms
 
+def last_level(levels):
+    """The largest finite level (hop distance) in an oracle result, -1 if none."""
+    fin = levels[levels != UNR]
+    return int(fin.max()) if fin.size else -1
+
+
 @pytest.mark.parametrize("T", TILES)
 @pytest.mark.parametrize("gi", range(len(GRAPHS)), ids=IDS)
 def test_algorithms(gi, T):
@@ -433,16 +439,23 @@ def test_algorithms(gi, T):
     srcs = np.unique(np.r_[0, gg.rng(gi).integers(0, g.n, 3)]).astype(np.uint32)
     for s in srcs[:3]:
         print(f"bfs/sssp {g.name} T={T} src={s}", flush=True)
-        lv, _ = b2.b2sr_bfs(A, int(s))
+        lv, it = b2.b2sr_bfs(A, int(s))
         ref = orc.bfs(g, int(s))
         assert np.array_equal(b2.as_u32(lv), ref)
-        d, _ = b2.b2sr_sssp(A, int(s))
+        assert it == last_level(ref) + 1  # every level that found vertices, then one that found none
+        d, it = b2.b2sr_sssp(A, int(s))
         assert np.array_equal(b2.as_u32(d), orc.sssp_unit(g, int(s)))
+        assert it == last_level(ref) + 1
     ms = srcs if g.n < 64 else np.unique(gg.rng(gi + 1).choice(g.n, 64, replace=False)).astype(np.uint32)
-    lvm, _ = b2.b2sr_msbfs(A, ms)
-    assert np.array_equal(b2.as_u32(lvm), orc.bfs_multi(g, ms))
-    lab, _ = b2.b2sr_cc(A)
-    assert np.array_equal(b2.as_u32(lab), orc.cc(g))
+    lvm, it = b2.b2sr_msbfs(A, ms)
+    refm = orc.bfs_multi(g, ms)
+    assert np.array_equal(b2.as_u32(lvm), refm)
+    assert it == last_level(refm) + 1
+    lab, it = b2.b2sr_cc(A)
+    refc = orc.cc(g)
+    assert np.array_equal(b2.as_u32(lab), refc)
+    # a label moves one hop per iteration from each component's least vertex
+    assert it == max((last_level(orc.bfs(g, int(r))) for r in np.unique(refc)), default=-1) + 1
     if g.n:
         for iters in (1, 20):
             pr = b2.b2sr_pagerank(A, 0.85, iters).cpu().numpy()
@@ -466,3 +479,25 @@ def test_stream_read_reads_every_word():
         t = torch.from_numpy(h.view(np.int32)).cuda()
         out = b2.as_u32(b2.b2sr_stream_read(t, nbytes))
         assert np.bitwise_xor.reduce(out) == np.bitwise_xor.reduce(h)
+
+
+@pytest.mark.parametrize("T", TILES)
+def test_long_runs_reuse_the_workspace(T):
+    """Hundreds of iterations (many batches of enqueued, device-gated
+    iterations, most of the last batch returning at once), the same workspace
+    reused across sources and drivers' runs: every run matches the oracle."""
+    g = gg.path(700)
+    A = b2sr(g, T)
+    ws = {algo: torch.empty(b2.b2sr_algo_workspace_bytes(A, algo), dtype=torch.uint8, device="cuda")
+          for algo in (b2.ALGO_BFS, b2.ALGO_SSSP, b2.ALGO_CC, b2.ALGO_MSBFS)}
+    for s in (0, 350, 699, 1):
+        print(f"path700 T={T} src={s}", flush=True)
+        ref = orc.bfs(g, s)
+        lv, it = b2.b2sr_bfs(A, s, ws=ws[b2.ALGO_BFS])
+        assert np.array_equal(b2.as_u32(lv), ref) and it == last_level(ref) + 1
+        d, it = b2.b2sr_sssp(A, s, ws=ws[b2.ALGO_SSSP])
+        assert np.array_equal(b2.as_u32(d), ref) and it == last_level(ref) + 1
+        lvm, it = b2.b2sr_msbfs(A, [s, (s + 3) % 700], ws=ws[b2.ALGO_MSBFS])
+        assert np.array_equal(b2.as_u32(lvm), orc.bfs_multi(g, np.array([s, (s + 3) % 700], dtype=np.uint32)))
+        lab, it = b2.b2sr_cc(A, ws=ws[b2.ALGO_CC])
+        assert np.all(b2.as_u32(lab) == 0) and it == 700
