@@ -411,6 +411,11 @@ def batched_section(graphs, reps: int = 3) -> dict:
     batch_tile, batch_tune = autotune.tune_batch(graphs, sources)      # the batched forms: measured
     B = GraphBatch(graphs, [batch_tile] * count)
     B.set_sources(sources)
+    # the other layout: each graph at its own autotuned width (one group per width)
+    Bw = GraphBatch(graphs, tiles)
+    Bw.set_sources(sources)
+    lv_w = torch.empty((Bw.n, 64), dtype=torch.int32, device="cuda")
+    ws_w = torch.empty(b2.b2sr_msbfs_batch_workspace_bytes(Bw.n), dtype=torch.uint8, device="cuda")
     singles = [b2.B2SR.from_graph(g, t) for g, t in zip(graphs, tiles)]
     ws_single = torch.empty(max(b2.b2sr_algo_workspace_bytes(A, b2.ALGO_MSBFS) for A in singles),
                             dtype=torch.uint8, device="cuda")
@@ -429,7 +434,9 @@ def batched_section(graphs, reps: int = 3) -> dict:
              "batched_levels": lambda: B.run(b2.BATCH_LEVELS, out=lv, ws=ws_b),
              "batched_persistent": lambda: B.run(b2.BATCH_PERSISTENT, out=lv, ws=ws_b),
              "batched_hipgraph_levels": lambda: plan.launch(want_iters=True),
-             "batched_hipgraph_persistent": lambda: plan_p.launch(want_iters=True)}
+             "batched_hipgraph_persistent": lambda: plan_p.launch(want_iters=True),
+             "batched_levels_per_graph_width": lambda: Bw.run(b2.BATCH_LEVELS, out=lv_w, ws=ws_w),
+             "batched_persistent_per_graph_width": lambda: Bw.run(b2.BATCH_PERSISTENT, out=lv_w, ws=ws_w)}
     res = {}
     for name, fn in modes.items():
         fn()
@@ -444,7 +451,8 @@ def batched_section(graphs, reps: int = 3) -> dict:
         res[name] = {"ms": 1e3 * t, "graphs_per_s": count / t, "bfs_per_s": 64 * count / t}
         log(f"batched {name}: {1e3 * t:.2f} ms")
     same = all(torch.equal(outs[i], B.levels_of(lv, i)) and torch.equal(outs[i], B.levels_of(plan.out, i))
-               and torch.equal(outs[i], B.levels_of(plan_p.out, i)) for i in range(count))
+               and torch.equal(outs[i], B.levels_of(plan_p.out, i)) and torch.equal(outs[i], Bw.levels_of(lv_w, i))
+               for i in range(count))
     # where the persistent kernel's time goes: device wall-clock stamps per level and block
     lvt, _, ph = b2.b2sr_msbfs_batch_timed(B.n, B.groups, B.seed_vertex, B.seed_bit, ws=ws_b)
     same = same and all(torch.equal(outs[i], B.levels_of(lvt, i)) for i in range(count))
@@ -688,6 +696,27 @@ def profile_tc(args):
         log(json.dumps({"profile_tc": name, "tile": T, "triangles": int(b2.as_u64(s)[0])}))
 
 
+def profile_batch(args, graphs):
+    """A short fixed program for rocprofv3: the batched 64-source BFS over the
+    256-graph Chung-Lu batch at B2SR-4 (the width the batch tuning picks), --steps
+    runs in the per-level mode, then --steps in the persistent mode, then one
+    persistent run with its phase timestamps (printed per level, microseconds)."""
+    from paper_2201_08560_amd.batch import GraphBatch
+    sources = [gg.sample_sources(g, 64, seed=1000 + i) for i, g in enumerate(graphs)]
+    B = GraphBatch(graphs, [4] * len(graphs))
+    B.set_sources(sources)
+    lv = torch.empty((B.n, 64), dtype=torch.int32, device="cuda")
+    ws = torch.empty(b2.b2sr_msbfs_batch_workspace_bytes(B.n), dtype=torch.uint8, device="cuda")
+    for mode, name in ((b2.BATCH_LEVELS, "levels"), (b2.BATCH_PERSISTENT, "persistent")):
+        for _ in range(args.steps):
+            _, it = B.run(mode, out=lv, ws=ws)
+        torch.cuda.synchronize()
+        log(json.dumps({"profile_batch": name, "levels": it}))
+    _, it, ph = b2.b2sr_msbfs_batch_timed(B.n, B.groups, B.seed_vertex, B.seed_bit, ws=ws)
+    log(json.dumps({"profile_batch": "persistent_phases_us",
+                    **{k: [round(float(x), 1) for x in v] for k, v in ph.items()}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -697,6 +726,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-mode", action="store_true")
     ap.add_argument("--profile-tc", action="store_true")
+    ap.add_argument("--profile-batch", action="store_true")
     ap.add_argument("--serve-qps", default="250,500,1000,2000,4000",
                     help="offered rates of the serving sweep (comma-separated, increasing)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -704,7 +734,10 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     batch_graphs = pool_graphs = None
-    if not args.no_extras and not args.profile_mode and not args.profile_tc and args.gpus == 1 and world == 1:
+    if args.profile_batch and args.gpus == 1 and world == 1:
+        batch_graphs = gg.chung_lu_batch(256, 2.1, seed=1000, workers=min(8, os.cpu_count() or 1))
+    profiling = args.profile_mode or args.profile_tc or args.profile_batch
+    if not args.no_extras and not profiling and args.gpus == 1 and world == 1:
         # generated in worker processes before this process touches the GPU
         t0 = time.perf_counter()
         batch_graphs = gg.chung_lu_batch(256, 2.1, seed=1000, workers=min(8, os.cpu_count() or 1))
@@ -727,6 +760,9 @@ def main():
         return
     if args.profile_tc:
         profile_tc(args)
+        return
+    if args.profile_batch:
+        profile_batch(args, batch_graphs)
         return
 
     log("generating R-MAT s20 ef16 ...")

@@ -21,12 +21,10 @@ using namespace b2sr_dev;
 namespace b2sr {
 int column_counts(const b2sr_matrix *A, uint32_t *colsum, hipStream_t s);
 size_t lgc_workspace_bytes(const b2sr_matrix *A);
-// The products with every kernel gated on *gate (spmv.hip): the bit product
-// runs when it is gate_val, and with B2SR_SPARSE_X when it is gate_sparse; the
-// full product runs when it is gate_val and takes B2SR_MIN_PLUS_U32 and
-// B2SR_OR_U64 only.
+// The products with every kernel gated on *gate == gate_val (spmv.hip); the
+// full product takes B2SR_MIN_PLUS_U32 and B2SR_OR_U64 only.
 int spmv_bits_gated(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, unsigned flags, void *y,
-                    const uint32_t *gate, uint32_t gate_val, uint32_t gate_sparse, hipStream_t stream);
+                    const uint32_t *gate, uint32_t gate_val, hipStream_t stream);
 int spmv_full_gated(const b2sr_matrix *A, int semiring, const void *x, const uint32_t *x_active, unsigned flags,
                     double alpha, void *y, const uint32_t *gate, uint32_t gate_val, hipStream_t stream);
 }
@@ -49,35 +47,38 @@ struct Carver {
     }
 };
 
-// flags[0..1]: per-iteration counts (by parity); flags[2]: the next
-// iteration's run state; flags[3]: iterations run; flags[4]: see below;
-// flags[5], flags[6]: the last iteration's count and the one before.
-constexpr uint32_t kRunDense = 0, kRunSparse = 1, kDone = 2, kFlagWords = 8;
+// The drivers' flag words: two 64-bit accumulators, one per iteration
+// parity, each the count of finished update blocks (high half) and the
+// iteration's count of found units (low half); then the next iteration's run
+// state, the iterations run, and the last two iterations' counts.
+constexpr uint32_t kRunDense = 0, kRunSparse = 1, kDone = 2;
+constexpr uint32_t kState = 4, kIters = 5, kLast = 6, kPrev = 7, kFlagWords = 8;
 
-// flags[4]: blocks of the running update kernel that have finished.
-//
-// Run by every thread of a gated update kernel once its block's count is
-// added.  The last block to finish advances the state: none found ends the run
-// (as does the iteration bound), otherwise the next iteration runs the
-// sparse-frontier product when fewer than sparse_below were found; it also
-// clears the next iteration's count and the block counter.
-__device__ void advance_when_last(uint32_t *flags, uint32_t sparse_below, uint32_t max_iters)
+// Ends a gated update kernel (every thread calls it; found_wave is this wave's
+// count, read from lane 0).  Each block adds its count and itself to the
+// iteration's accumulator in one 64-bit atomic, so the block that sees every
+// other block counted is the last and holds the total, with no fence between
+// the two.  It then advances the state: none found ends the run (as does the
+// iteration bound), otherwise the next iteration runs the sparse-frontier
+// product when fewer than sparse_below were found; and it clears the
+// accumulator for iteration it + 2.
+__device__ void finish_iteration(uint32_t *flags, uint32_t it, uint32_t found_wave, uint32_t sparse_below,
+                                 uint32_t max_iters)
 {
-    __shared__ uint32_t last;
-    __threadfence();
+    __shared__ uint32_t s_found;
+    if (threadIdx.x == 0) s_found = 0;
     __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(flags + 4, 1u) == gridDim.x - 1;
+    if (lane_id() == 0 && found_wave) atomicAdd(&s_found, found_wave);
     __syncthreads();
-    if (!last || threadIdx.x != 0) return;
-    __threadfence();
-    const uint32_t it = flags[3] + 1;  // the iteration that just ran
-    const uint32_t found = atomicAdd(flags + (it & 1), 0u);
-    // atomic writes, as the other blocks' counts in the same words were
-    atomicExch(flags + 6, atomicExch(flags + 5, found));
-    atomicExch(flags + 4, 0u);
-    atomicExch(flags + 3, it);
-    atomicExch(flags + ((it + 1) & 1), 0u);
-    atomicExch(flags + 2, (found == 0 || it >= max_iters) ? kDone : (found < sparse_below ? kRunSparse : kRunDense));
+    if (threadIdx.x != 0) return;
+    unsigned long long *acc = (unsigned long long *)flags + (it & 1);
+    const unsigned long long old = atomicAdd(acc, (1ull << 32) | s_found);
+    if ((uint32_t)(old >> 32) != gridDim.x - 1) return;
+    const uint32_t found = (uint32_t)old + s_found;
+    atomicExch(acc, 0ull);
+    atomicExch(flags + kPrev, atomicExch(flags + kLast, found));
+    atomicExch(flags + kIters, it);
+    atomicExch(flags + kState, (found == 0 || it >= max_iters) ? kDone : (found < sparse_below ? kRunSparse : kRunDense));
 }
 
 // Runs `one(iteration index)` in batches, reading the device state after each
@@ -89,17 +90,17 @@ __device__ void advance_when_last(uint32_t *flags, uint32_t sparse_below, uint32
 template <class F> int run_gated(const uint32_t *flags, uint32_t max_iters, uint32_t *iters, hipStream_t s, F one)
 {
     uint32_t enq = 0, batch = 2;
-    uint32_t h[5] = {kRunDense, 0, 0, 0, 0};  // flags[2..6]
+    uint32_t h[4] = {kRunDense, 0, 0, 0};  // state, iterations run, last and previous counts
     for (;;) {
         for (uint32_t k = 0; k < batch; ++k)
             if (int rc = one(++enq)) return rc;
-        if (int rc = b2sr::check(hipMemcpyAsync(h, flags + 2, sizeof h, hipMemcpyDeviceToHost, s),
+        if (int rc = b2sr::check(hipMemcpyAsync(h, flags + kState, sizeof h, hipMemcpyDeviceToHost, s),
                                  "hipMemcpyAsync(state)"))
             return rc;
         if (int rc = b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize")) return rc;
         if (h[0] == kDone) break;
         if (enq > max_iters + 1) return B2SR_EHIP;  // cannot happen: the run ends by max_iters
-        batch = h[3] < h[4] ? 2u : std::min<uint32_t>(batch * 2, 16);
+        batch = h[2] < h[3] ? 2u : std::min<uint32_t>(batch * 2, 16);
     }
     if (iters) *iters = h[1];
     return B2SR_OK;
@@ -126,7 +127,7 @@ __global__ void bfs_init_kernel(uint32_t n, uint32_t src, uint32_t *levels, uint
             next[i] = 0;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x < kFlagWords) flags[threadIdx.x] = threadIdx.x == 2 ? first_state : 0u;
+    if (blockIdx.x == 0 && threadIdx.x < kFlagWords) flags[threadIdx.x] = threadIdx.x == kState ? first_state : 0u;
 }
 
 // Newly reached vertices (next is already masked by NOT visited) get this
@@ -136,8 +137,8 @@ __global__ void bfs_init_kernel(uint32_t n, uint32_t src, uint32_t *levels, uint
 __global__ void bfs_update_gated_kernel(uint32_t nw, uint32_t *next, uint32_t *frontier, uint32_t *visited,
                                         uint32_t *levels, uint32_t *flags, uint32_t sparse_below, uint32_t max_iters)
 {
-    if (flags[2] == kDone) return;
-    const uint32_t level = flags[3] + 1;
+    if (flags[kState] == kDone) return;
+    const uint32_t level = flags[kIters] + 1;
     uint32_t found = 0;
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t nb = next[w];
@@ -153,8 +154,7 @@ __global__ void bfs_update_gated_kernel(uint32_t nw, uint32_t *next, uint32_t *f
         }
     }
     for (int d = 32; d >= 1; d >>= 1) found += shfl_xor(found, d);
-    if (lane_id() == 0 && found) atomicAdd(flags + (level & 1), found);
-    advance_when_last(flags, sparse_below, max_iters);
+    finish_iteration(flags, level, found, sparse_below, max_iters);
 }
 
 // ---------------------------------------------------------------- multi-source BFS
@@ -252,8 +252,8 @@ __global__ void ecc_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, ui
 __global__ void msbfs_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, uint64_t *V, uint32_t *levels,
                                     uint32_t *act, uint32_t *flags, uint32_t max_iters)
 {
-    if (flags[2] == kDone) return;
-    const uint32_t level = flags[3] + 1;
+    if (flags[kState] == kDone) return;
+    const uint32_t level = flags[kIters] + 1;
     bool any = false;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
     for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
@@ -276,8 +276,7 @@ __global__ void msbfs_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, 
         }
         store_pred_bits(act, base, n, y != 0);
     }
-    if (__syncthreads_or(any) && threadIdx.x == 0) atomicAdd(flags + (level & 1), 1u);
-    advance_when_last(flags, 0, max_iters);
+    finish_iteration(flags, level, __any(any) ? 1u : 0u, 0, max_iters);
 }
 
 // ---------------------------------------------------------------- SSSP / CC
@@ -296,8 +295,8 @@ __global__ void sssp_init_kernel(uint32_t n, uint32_t src, uint32_t *d, uint32_t
 __global__ void changed_kernel(uint32_t n, const uint32_t *a, const uint32_t *b, uint32_t *act, uint32_t *flags,
                                uint32_t max_iters)
 {
-    if (flags[2] == kDone) return;
-    const uint32_t it = flags[3] + 1;
+    if (flags[kState] == kDone) return;
+    const uint32_t it = flags[kIters] + 1;
     bool diff = false;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
     for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
@@ -307,8 +306,7 @@ __global__ void changed_kernel(uint32_t n, const uint32_t *a, const uint32_t *b,
         diff |= d;
         store_pred_bits(act, base, n, d);
     }
-    if (__syncthreads_or(diff) && threadIdx.x == 0) atomicAdd(flags + (it & 1), 1u);
-    advance_when_last(flags, 0, max_iters);
+    finish_iteration(flags, it, __any(diff) ? 1u : 0u, 0, max_iters);
 }
 
 __global__ void iota_kernel(uint32_t n, uint32_t *x, uint32_t *flags)
@@ -538,13 +536,16 @@ int b2sr_bfs(const b2sr_matrix *A, uint32_t src, uint32_t *levels, void *ws, siz
     bfs_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, src, levels, L.frontier, L.visited, L.next, L.flags,
                                                   1 < sparse_below ? kRunSparse : kRunDense);
     if ((rc = b2sr::check_launch("bfs_init_kernel"))) return rc;
-    const uint32_t *state = L.flags + 2;
+    const uint32_t *state = L.flags + kState;
     // next = A frontier over unvisited rows, OR-ed into the cleared next; the
     // update consumes and clears next, so no buffers swap
     return run_gated(L.flags, max_iters, iters, stream, [&](uint32_t) {
-        // one launch: the dense form, or the sparse-frontier one, as the state says
-        if (int r = b2sr::spmv_bits_gated(A, L.frontier, L.visited, B2SR_MASK_COMPLEMENT | B2SR_ACCUMULATE, L.next,
-                                          state, kRunDense, kRunSparse, stream))
+        // the dense form or the sparse-frontier one, as the state says (the
+        // other returns at once); the sparse form has a kernel of its own
+        const unsigned fl = B2SR_MASK_COMPLEMENT | B2SR_ACCUMULATE;
+        if (int r = b2sr::spmv_bits_gated(A, L.frontier, L.visited, fl, L.next, state, kRunDense, stream)) return r;
+        if (int r = b2sr::spmv_bits_gated(A, L.frontier, L.visited, fl | B2SR_SPARSE_X, L.next, state, kRunSparse,
+                                          stream))
             return r;
         bfs_update_gated_kernel<<<fgrid(nw), 256, 0, stream>>>(nw, L.next, L.frontier, L.visited, levels, L.flags,
                                                                sparse_below, max_iters);
@@ -576,7 +577,7 @@ int b2sr_msbfs(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32
     // first state read has synchronised the stream
     return run_gated(L.flags, max_iters, iters, stream, [&](uint32_t) {
         // only frontier words that are non-zero take part in the product
-        if (int r = b2sr::spmv_full_gated(A, B2SR_OR_U64, L.F, L.act, 0, 0.0, L.Y, L.flags + 2, kRunDense, stream))
+        if (int r = b2sr::spmv_full_gated(A, B2SR_OR_U64, L.F, L.act, 0, 0.0, L.Y, L.flags + kState, kRunDense, stream))
             return r;
         msbfs_update_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, levels, L.act, L.flags, max_iters);
         return b2sr::check_launch("msbfs_update_kernel");
@@ -599,7 +600,7 @@ int min_plus_to_fixpoint(const b2sr_matrix *A, uint32_t weight, uint32_t *buf0, 
         const uint32_t *cur = buf[(k - 1) & 1];
         uint32_t *nxt = buf[k & 1];
         if (int r = b2sr::spmv_full_gated(A, B2SR_MIN_PLUS_U32, cur, L.act, B2SR_SELF, (double)weight, nxt,
-                                          L.flags + 2, kRunDense, stream))
+                                          L.flags + kState, kRunDense, stream))
             return r;
         changed_kernel<<<fgrid(n), 256, 0, stream>>>(n, cur, nxt, L.act, L.flags, max_iters);
         return b2sr::check_launch("changed_kernel");

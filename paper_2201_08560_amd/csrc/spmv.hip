@@ -84,14 +84,6 @@ __global__ void __launch_bounds__(256, waves_hint(T, K)) spmv_kernel(SpmvArgs p)
     __shared__ __align__(16) V s_x[stage ? 4 * kSliceBytes / sizeof(V) : 1];
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     if (wave * p.chunk >= p.ntiles || gated_off(p)) return;
-    if constexpr (K == kBits) {
-        if (p.gate && p.gate_sparse != p.gate_val && *p.gate == p.gate_sparse) {
-            SpmvArgs q = p;
-            q.flags |= B2SR_SPARSE_X;
-            spmv_chunk<T, K, ACT, SHORT>(q, (uint32_t)wave, s_x);
-            return;
-        }
-    }
     spmv_chunk<T, K, ACT, SHORT>(p, (uint32_t)wave,
                                  s_x + (stage ? (threadIdx.x / B2SR_WAVE) * kSliceBytes / sizeof(V) : 0));
 }
@@ -381,11 +373,10 @@ int spmv_bin_full_noalloc(const b2sr_matrix *A, int semiring, const void *x, con
 
 namespace b2sr {
 // The products for the algorithm drivers' gated iterations: every kernel of the
-// launch returns at once unless *gate is gate_val (or, for the bit product,
-// gate_sparse, which runs it with B2SR_SPARSE_X); arguments as the public
-// calls, validated by the drivers; no plus-times, so no workspace.
+// launch returns at once unless *gate == gate_val (arguments as the public
+// calls, validated by the drivers; no plus-times, so no workspace).
 int spmv_bits_gated(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, unsigned flags, void *y,
-                    const uint32_t *gate, uint32_t gate_val, uint32_t gate_sparse, hipStream_t stream)
+                    const uint32_t *gate, uint32_t gate_val, hipStream_t stream)
 {
     SpmvArgs p = make_args(A);
     p.x = x;
@@ -394,7 +385,6 @@ int spmv_bits_gated(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mas
     p.y = y;
     p.gate = gate;
     p.gate_val = gate_val;
-    p.gate_sparse = gate_sparse;
     if (flags & B2SR_OUT_COUNT) return dispatch<kCount>(A->tile, p, stream);
     return dispatch<kBits>(A->tile, p, stream);
 }
@@ -411,7 +401,6 @@ int spmv_full_gated(const b2sr_matrix *A, int semiring, const void *x, const uin
     p.y = y;
     p.gate = gate;
     p.gate_val = gate_val;
-    p.gate_sparse = gate_val;
     switch (semiring) {
     case B2SR_MIN_PLUS_U32: return dispatch<kMinU32>(A->tile, p, stream);
     case B2SR_OR_U64: return dispatch<kOr64>(A->tile, p, stream);

@@ -32,6 +32,9 @@
 #ifndef B2SR_FAST_BLOCKS
 #define B2SR_FAST_BLOCKS 1       // value products at T >= 32: the lean path for whole in-row blocks
 #endif
+#ifndef B2SR_FAST_PIPE
+#define B2SR_FAST_PIPE 1         // runs of lean blocks load the next block's tiles before a block's wait
+#endif
 
 namespace b2sr_core {
 
@@ -102,17 +105,12 @@ struct SpmvArgs {
     uint32_t x_whole;   // n is a multiple of T: no x segment is cut short
     uint32_t chunk_blocks;  // blocks per wave chunk (0: sized from the tile count)
     // Iteration gating (the algorithm drivers): when gate is set, every kernel
-    // of the product returns at once unless *gate is gate_val or gate_sparse;
-    // a bit product runs with B2SR_SPARSE_X when it is gate_sparse (the two
-    // are equal when the driver has no sparse form).
+    // of the product returns at once unless *gate == gate_val.
     const uint32_t *gate;
-    uint32_t gate_val, gate_sparse;
+    uint32_t gate_val;
 };
 
-__device__ __forceinline__ bool gated_off(const SpmvArgs &p)
-{
-    return p.gate && *p.gate != p.gate_val && *p.gate != p.gate_sparse;
-}
+__device__ __forceinline__ bool gated_off(const SpmvArgs &p) { return p.gate && *p.gate != p.gate_val; }
 
 // Block shape per tile width and kind.  Bit and count products read the x
 // segment as T bits; the others stage T values per tile in LDS (a fixed budget
@@ -447,6 +445,113 @@ __device__ __forceinline__ void fast_block(const SpmvArgs &p, uint32_t blk, uint
     wave_lds_sync();  // the next block's LDS writes follow these reads
 }
 
+// s_waitcnt limiting only the vector-memory counter (the gfx9 encoding: vmcnt
+// in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima).
+template <int N> __device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// nb >= 1 consecutive lean blocks from blk, all inside one tile-row and the
+// chunk, software-pipelined: block b + 1's tile pieces are loaded before block
+// b's wait, so they stream in while block b is reduced.  Vector loads complete
+// in issue order, so waiting until at most the next block's piece loads remain
+// covers this block's pieces, columns and x segments.  The run's last block
+// has no successor to load and waits for everything.  On entry J holds the
+// tile columns of block blk (loaded, one per lane); on return those of the
+// block after the run.
+template <int T, int K>
+__device__ __forceinline__ void fast_run(const SpmvArgs &p, uint32_t blk, uint32_t nb, uint32_t t_end,
+                                         typename KindTraits<K>::V *xs,
+                                         typename KindTraits<K>::V (&acc)[TileShape<T>::RPL], uint32_t &J)
+{
+    using C = Cfg<T, K>;
+    using KT = KindTraits<K>;
+    using V = typename KT::V;
+    using R = row_t<T>;
+    using Piece = typename PieceT<T>::type;
+    constexpr int RPL = C::RPL, TPW = C::TPW, U = C::U, BT = C::BT, XW = C::XW, LPT = C::LPT;
+    constexpr int kPieceLoads = (T == 64 ? 2 : 1) * U;  // vector loads per block's pieces
+    static_assert(BT <= 64 && C::VB == 4 && T >= 32, "fast block shape");
+    const uint32_t lane = lane_id(), grp = lane / LPT, sub = lane % LPT;
+    const uint32_t xs_lds = readfirstlane((uint32_t)(uintptr_t)xs);
+    Piece cur[U], nxt[U];
+    auto load_pieces = [&](uint32_t b, Piece(&pc)[U]) {
+        if constexpr (T == 64) {
+            const u32x4 *q = (const u32x4 *)p.bits + (size_t)b * 32;
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                const u32x4 lo = load_stream(q + (i * 128 + 2 * lane)), hi = load_stream(q + (i * 128 + 2 * lane + 1));
+                pc[i] = u32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+            }
+        } else {
+            const u32x4 *q = (const u32x4 *)p.bits + (size_t)b * 8;
+#pragma unroll
+            for (int i = 0; i < U; ++i) pc[i] = load_stream(q + (i * 64 + lane));
+        }
+    };
+    // the next block's columns, then this block's x segments into LDS
+    auto stage_x = [&]() {
+        uint32_t xo[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) xo[i] = shfl(J, (int)(i * TPW + grp)) * T + sub * XW;
+        __builtin_amdgcn_sched_barrier(0);
+        J = p.tci[min(blk + BT + min(lane, (uint32_t)BT - 1), t_end - 1)];
+#pragma unroll
+        for (int i = 0; i < U; ++i)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)((const V *)p.x + xo[i]),
+                                             (__attribute__((address_space(3))) void *)(uintptr_t)(xs_lds + i * TPW * T * 4),
+                                             16, 0, 0);
+    };
+    auto reduce = [&]() {
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            R a[RPL];
+            piece_rows<T>(cur[i], a);
+            const V *xt = xs + (i * TPW + grp) * T;
+            V v[RPL];
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) v[k] = xt_or_id(xt, a[k], xs);  // empty rows: a broadcast
+            R rest = 0;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                acc[k] = KT::op(acc[k], v[k]);
+                a[k] &= a[k] - 1;
+                rest |= a[k];
+            }
+            if (rest) {
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    R w = a[k];
+                    while (w) {
+                        const uint32_t c = ctz_row(w);
+                        w &= w - 1;
+                        acc[k] = KT::op(acc[k], xt[c]);
+                    }
+                }
+            }
+        }
+        wave_lds_sync();  // the next block's LDS writes follow these reads
+        blk += BT;
+    };
+    load_pieces(blk, cur);
+    for (uint32_t k = 1; k < nb; ++k) {
+        stage_x();
+        load_pieces(blk + BT, nxt);
+        __builtin_amdgcn_sched_barrier(0);  // every load is issued before the wait
+        wait_vmcnt<kPieceLoads>();
+        reduce();
+#pragma unroll
+        for (int i = 0; i < U; ++i) cur[i] = nxt[i];
+    }
+    stage_x();
+    __builtin_amdgcn_sched_barrier(0);
+    wait_vmcnt<0>();
+    reduce();
+}
+
 // Processes tile chunk chunk_id (wave-uniform) of the product described by p.
 // xs is this wave's LDS slice (unused by bit and count products).
 template <int T, int K, bool ACT = false, bool SHORT = false>
@@ -512,8 +617,14 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
         if constexpr (B2SR_FAST_BLOCKS && C::kStage && !ACT && T >= 32 && C::VB == 4) {
             if (p.x_whole && blk + BT <= t_end && blk + BT - 1 < r_end) {
                 if (jf_blk != blk) jf = p.tci[blk + min(lane, (uint32_t)BT - 1)];
-                fast_block<T, K>(p, blk, t_end, xs, acc, jf);
-                blk += BT;
+                if constexpr (B2SR_FAST_PIPE) {
+                    const uint32_t nb = (min(r_end, t_end) - blk) / BT;  // >= 1
+                    fast_run<T, K>(p, blk, nb, t_end, xs, acc, jf);
+                    blk += nb * BT;
+                } else {
+                    fast_block<T, K>(p, blk, t_end, xs, acc, jf);
+                    blk += BT;
+                }
                 jf_blk = blk;
                 continue;
             }
@@ -537,29 +648,21 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
                 // read a tile only when its x segment has a set bit
 #pragma unroll
                 for (int k = 0; k < JK; ++k) Sr[k] = bit_segment<T>((const uint32_t *)p.x, Jr[k], p.n);
-                if constexpr (K == kBits) {
-                    // A block none of whose tiles meets a set x bit adds nothing: only
-                    // the row it ends in is followed, and a row that ends inside it is
-                    // stored.
-                    bool seg_any = false;
+                if constexpr (K == kBits && SHORT) {
+                    // A block inside the current row none of whose tiles meets a set x
+                    // bit adds nothing to it (a block across a row end takes the
+                    // general path, which stores the row).  Only in the short-block
+                    // form, which sparse frontiers use: in the long one the test costs
+                    // the dense path registers.
+                    if (min(blk + BT, t_end) - 1 < r_end) {
+                        bool seg_any = false;
 #pragma unroll
-                    for (int k = 0; k < JK; ++k)
-                        seg_any |= Sr[k] != 0 && 64 * k + lane < (uint32_t)BT && blk + 64 * k + lane < t_end;
-                    if (!__any(seg_any)) {
-                        const uint32_t last = min(blk + BT, t_end) - 1;
-                        if (last >= r_end) {
-                            fold_raw();
-                            R acc_all = acc[0];
-#pragma unroll
-                            for (int d = 1; d < 64; d <<= 1) acc_all |= shfl_xor(acc_all, d);
-                            if (lane == 0) store_bits<T>(p, r_cur, acc_all & keep);
-                            acc[0] = 0;
-                            r_cur = readfirstlane(lane_row(p.trp, p.ntr, r_cur, last));
-                            r_end = p.trp[r_cur + 1];
-                            keep = keep_bits<T>(p.mask, p.flags, r_cur, p.n);
+                        for (int k = 0; k < JK; ++k)
+                            seg_any |= Sr[k] != 0 && 64 * k + lane < (uint32_t)BT && blk + 64 * k + lane < t_end;
+                        if (!__any(seg_any)) {
+                            blk += BT;
+                            continue;
                         }
-                        blk += BT;
-                        continue;
                     }
                 }
 #pragma unroll
