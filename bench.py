@@ -727,7 +727,7 @@ def main():
     ap.add_argument("--profile-mode", action="store_true")
     ap.add_argument("--profile-tc", action="store_true")
     ap.add_argument("--profile-batch", action="store_true")
-    ap.add_argument("--serve-qps", default="250,500,1000,2000,4000",
+    ap.add_argument("--serve-qps", default="250,500,1000,2000,4000,8000,16000",
                     help="offered rates of the serving sweep (comma-separated, increasing)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-budget-gib", type=float, default=0.25)
