@@ -35,6 +35,9 @@
 #ifndef B2SR_FAST_PIPE
 #define B2SR_FAST_PIPE 1         // runs of lean blocks load the next block's tiles before a block's wait
 #endif
+#ifndef B2SR_ACT_PREFETCH
+#define B2SR_ACT_PREFETCH 1      // products with x_active load the next block's tile columns a block ahead
+#endif
 
 namespace b2sr_core {
 
@@ -609,6 +612,10 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
     uint32_t blk = t_begin;
     // fast blocks: the tile columns of block jf_blk, loaded one block ahead
     [[maybe_unused]] uint32_t jf = 0, jf_blk = 0xFFFFFFFFu;
+    // products with x_active: the next block's tile columns, loaded while this
+    // block is examined (most blocks of a small frontier are skipped after
+    // reading only their columns and those columns' activity bits)
+    [[maybe_unused]] uint32_t jn[JK], jn_blk = 0xFFFFFFFFu;
     while (blk < t_end) {
         if (min(blk + BT, t_end) - 1 < r_end && !keep) {  // the block lies in a row masked out entirely
             blk = min(r_end, t_end);
@@ -635,8 +642,21 @@ __device__ __forceinline__ void spmv_chunk(const SpmvArgs &p, uint32_t chunk_id,
         // the column loads come first, and the x reads that depend on them are
         // issued while the tile pieces are still in flight.
         uint32_t Jr[JK];
+        if constexpr (ACT && B2SR_ACT_PREFETCH) {
+            if (jn_blk == blk) {
 #pragma unroll
-        for (int k = 0; k < JK; ++k) Jr[k] = p.tci[min(blk + 64 * k + lane, t_end - 1)];
+                for (int k = 0; k < JK; ++k) Jr[k] = jn[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < JK; ++k) Jr[k] = p.tci[min(blk + 64 * k + lane, t_end - 1)];
+            }
+            jn_blk = blk + BT;
+#pragma unroll
+            for (int k = 0; k < JK; ++k) jn[k] = p.tci[min(jn_blk + 64 * k + lane, t_end - 1)];
+        } else {
+#pragma unroll
+            for (int k = 0; k < JK; ++k) Jr[k] = p.tci[min(blk + 64 * k + lane, t_end - 1)];
+        }
         Piece pc[U];
         R seg[U];
         if constexpr (!C::kStage) {
