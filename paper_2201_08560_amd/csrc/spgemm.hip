@@ -41,6 +41,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / B2SR_WAVE;
 constexpr uint32_t kMapWords = 4096;  // bitmap of up to 131072 tile columns
+constexpr unsigned kMaxGroups = 8192;  // workgroups of a masked-product launch
 
 template <int T> __device__ __forceinline__ row_t<T> load_word(const void *bits, size_t idx)
 {
@@ -386,7 +387,11 @@ template <int T, bool PROFILE = false> int launch_masked(GemmArgs g, hipStream_t
     const uint32_t lds_words = T == 32 ? kMapWords : g.map_words;
     if (!g.sw_off && g.row1 <= g.row0) return B2SR_OK;
     const uint32_t work = g.sw_off ? g.items_bound : g.row1 - g.row0;
-    spgemm_masked_kernel<T, PROFILE><<<b2sr::grid_for(work, 1, 1u << 16), kThreads, 2 * lds_words * 4, s>>>(g);
+    // At most kMaxGroups workgroups, each looping over work items: one workgroup
+    // per item (up to 65,536) measured slower wherever items are short, their
+    // launches then dominating (king grid T = 32: 3.23 -> 1.07 ms; R-MAT s18 T = 8:
+    // 2.98 -> 2.47 ms).
+    spgemm_masked_kernel<T, PROFILE><<<b2sr::grid_for(work, 1, kMaxGroups), kThreads, 2 * lds_words * 4, s>>>(g);
     return b2sr::check_launch("spgemm_masked_kernel");
 }
 
@@ -516,7 +521,7 @@ int build_swap_lists(GemmArgs &g, const b2sr_matrix *A, const b2sr_matrix *M, vo
     int rc;
     // list offsets: off[0] = 0, off[J + 1] = swapped tiles of rows 0 .. J
     if ((rc = b2sr::fill_u32(L.off, (uint64_t)ntr + 1, 0, s))) return rc;
-    const unsigned wgrid = b2sr::grid_for(ntr, 256 / B2SR_WAVE, 1u << 16);
+    const unsigned wgrid = b2sr::grid_for(ntr, 256 / B2SR_WAVE, kMaxGroups);  // grid-stride over tile-rows
     swap_count_kernel<<<wgrid, 256, 0, s>>>(g, L.off + 1);
     if ((rc = b2sr::check_launch("swap_count_kernel"))) return rc;
     if ((rc = device_scan<uint32_t>(ntr, LoadArray<uint32_t>{L.off + 1}, L.off + 1, true, L.sums, s))) return rc;
