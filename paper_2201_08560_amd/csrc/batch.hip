@@ -255,9 +255,11 @@ constexpr int persistent_waves(unsigned tmask) { return (tmask & 6u) ? B2SR_PW_W
 #endif
 constexpr unsigned kPersistThreads = B2SR_PERSIST_THREADS;
 #ifndef B2SR_PERSIST_CLAIM
-#define B2SR_PERSIST_CLAIM 1
+#define B2SR_PERSIST_CLAIM 1         // work items per claim after a large frontier
 #endif
-constexpr uint32_t kClaimItems = B2SR_PERSIST_CLAIM;  // work items per claim
+#ifndef B2SR_PERSIST_CLAIM_SPARSE
+#define B2SR_PERSIST_CLAIM_SPARSE 2  // the same after a small one
+#endif
 
 template <unsigned TMASK>
 __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batch_persistent_kernel(BatchArgs b)
@@ -276,14 +278,20 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
         // once it passes nitems; the claims a wave makes are also capped at
         // nitems.  The other parity's counter is reset in the update phase,
         // between the two barriers, when no wave claims from it.
+        // A level whose items are light (most chunks inactive after a small
+        // frontier: fewer frontier vertices than items; the seeds before level
+        // 1) claims two items at a time, halving its claims on the one counter
+        // (256-graph batch: 24.9 -> 22.8 ms; 4 items 23.3, 8 items 24.1).
         uint32_t *const counter = b.flags + kClaim + (level & 1) * 64;
+        const uint32_t frontier = readfirstlane(level == 1 ? b.nseeds : b.flags[(level - 1) & 1]);
+        const uint32_t per_claim = frontier < b.nitems ? B2SR_PERSIST_CLAIM_SPARSE : B2SR_PERSIST_CLAIM;
         uint32_t claims = 0;
         for (;;) {
             uint32_t first = 0;
-            if (lane_id() == 0) first = atomicAdd(counter, kClaimItems);
+            if (lane_id() == 0) first = atomicAdd(counter, per_claim);
             first = readfirstlane(shfl(first, 0));
             if (first >= b.nitems || ++claims > b.nitems) break;
-            const uint32_t stop = min(b.nitems, first + kClaimItems);
+            const uint32_t stop = min(b.nitems, first + per_claim);
             for (uint32_t item = first; item < stop; ++item) {
             uint32_t gi = 0;
             while (gi + 1 < b.ngroups && item >= b.g[gi + 1].item0) ++gi;
@@ -312,10 +320,17 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
         }
         if (grid_barrier(b.flags, nullptr) & 1u) break;
         if (b.stamps) stamp(b, level, 2);
-        bool any = false;
+        // the level's count of new frontier vertices: the convergence test (zero
+        // or not) and the next level's claim size
+        __shared__ uint32_t s_count;
+        if (threadIdx.x == 0) s_count = 0;
+        __syncthreads();
+        uint32_t count = 0;
         for (uint64_t base = (uint64_t)wave * 64; base < b.n; base += (uint64_t)nwaves * 64)
-            any |= update_group(b, base, level);
-        if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(b.flags + (level & 1), 1u);
+            count += (uint32_t)__popcll(__ballot(update_group(b, base, level)));
+        if (lane_id() == 0 && count) atomicAdd(&s_count, count);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_count) atomicAdd(b.flags + (level & 1), s_count);
         if (tid == 0) {
             b.flags[(level + 1) & 1] = 0;
             b.flags[2] = level;
