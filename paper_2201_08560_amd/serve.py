@@ -83,8 +83,12 @@ class Server:
     """Continuous-batching scheduler (see the module docstring)."""
 
     def __init__(self, executor, budget_bytes: int, clock=time.perf_counter, cache: bool = True,
-                 on_done=None, keep_results: bool = True):
+                 on_done=None, keep_results: bool = True, scan_limit: int = 256):
         self.ex = executor
+        # queries a round may find unable to start before it stops looking: a
+        # long queue behind a full budget otherwise costs every round a pass
+        # over all of it
+        self.scan_limit = int(scan_limit)
         self.on_done = on_done
         self.keep_results = keep_results
         self.budget = int(budget_bytes)
@@ -227,7 +231,10 @@ class Server:
 
     def _admit(self):
         waiting = []
-        for q in self.queue:
+        for i, q in enumerate(self.queue):
+            if len(waiting) >= self.scan_limit:
+                waiting.extend(self.queue[i:])  # the rest keep their order for later rounds
+                break
             if not self._admit_one(q):
                 waiting.append(q)
         self.queue = waiting

@@ -165,3 +165,25 @@ def test_bad_queries():
         srv.submit(Query(0, "diameter", 0))
     with pytest.raises(ValueError):
         srv.submit(Query(1, "bfs", 0, GRAPHS[0].n))
+
+
+def test_admission_scan_stops_after_scan_limit_waiting_queries():
+    """A round stops looking after scan_limit queries that cannot start; the
+    rest keep their order and start in later rounds, every answer unchanged."""
+    n = GRAPHS[2].n
+    budget = 280 * n + 1024 + 4 * n  # one session of graph 2 and one result
+    clock = FakeClock(tick=1e-3)
+    srv = Server(FakeExecutor(GRAPHS), budget, clock=clock, scan_limit=2)
+    qs = [Query(i, "bfs", 2, i, 0.0) for i in range(4)] + [Query(4, "cc", 1, 0, 0.0)]
+    for q in qs:
+        srv.submit(q)
+    srv.tick()
+    # q0 runs; q1 and q2 cannot start (no memory for a second result) and end the
+    # scan, so q3 and the CC query are not looked at in this round
+    assert qs[0].status == "running"
+    assert [q.qid for q in srv.queue] == [1, 2, 3, 4]
+    while not srv.idle:
+        srv.tick()
+    for q in qs:
+        check(q)
+    assert srv.peak_in_use <= budget and srv.in_use == 0
