@@ -260,6 +260,9 @@ constexpr unsigned kPersistThreads = B2SR_PERSIST_THREADS;
 #ifndef B2SR_PERSIST_CLAIM_SPARSE
 #define B2SR_PERSIST_CLAIM_SPARSE 2  // the same after a small one
 #endif
+#ifndef B2SR_PERSIST_SPARSE_FACTOR
+#define B2SR_PERSIST_SPARSE_FACTOR 4  // a frontier is small below this many vertices per item
+#endif
 
 template <unsigned TMASK>
 __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batch_persistent_kernel(BatchArgs b)
@@ -279,12 +282,13 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
         // nitems.  The other parity's counter is reset in the update phase,
         // between the two barriers, when no wave claims from it.
         // A level whose items are light (most chunks inactive after a small
-        // frontier: fewer frontier vertices than items; the seeds before level
-        // 1) claims two items at a time, halving its claims on the one counter
-        // (256-graph batch: 24.9 -> 22.8 ms; 4 items 23.3, 8 items 24.1).
+        // frontier: fewer than 4 frontier vertices per item; the seeds before
+        // level 1) claims two items at a time, halving its claims on the one
+        // counter (256-graph batch: 24.9 -> 22.7 ms; 4 items 23.3, 8 items 24.1).
         uint32_t *const counter = b.flags + kClaim + (level & 1) * 64;
         const uint32_t frontier = readfirstlane(level == 1 ? b.nseeds : b.flags[(level - 1) & 1]);
-        const uint32_t per_claim = frontier < b.nitems ? B2SR_PERSIST_CLAIM_SPARSE : B2SR_PERSIST_CLAIM;
+        const uint32_t per_claim = (uint64_t)frontier < (uint64_t)b.nitems * B2SR_PERSIST_SPARSE_FACTOR
+                                       ? B2SR_PERSIST_CLAIM_SPARSE : B2SR_PERSIST_CLAIM;
         uint32_t claims = 0;
         for (;;) {
             uint32_t first = 0;
