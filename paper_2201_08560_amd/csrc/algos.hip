@@ -266,15 +266,19 @@ __global__ void msbfs_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, 
             if (y) {
                 any = true;
                 V[i] |= y;
-                uint64_t b = y;
-                while (b) {
-                    const uint32_t s = __builtin_ctzll(b);
-                    b &= b - 1;
-                    levels[(size_t)s * n + i] = level;
-                }
             }
         }
         store_pred_bits(act, base, n, y != 0);
+        // levels are source-major: one source at a time, the lanes' consecutive
+        // vertices make one store into that source's row
+        uint64_t srcs = y;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) srcs |= shfl_xor(srcs, d);
+        while (srcs) {
+            const uint32_t s = __builtin_ctzll(srcs);
+            srcs &= srcs - 1;
+            if ((y >> s) & 1) levels[(size_t)s * n + i] = level;
+        }
     }
     finish_iteration(flags, level, __any(any) ? 1u : 0u, 0, max_iters);
 }

@@ -104,34 +104,34 @@ __global__ void batch_seed_kernel(BatchArgs b)
     }
 }
 
-// One vertex: take the new frontier bits, mark them visited, record their
-// level, and clear Y for the next level's product.  Returns the new frontier word.
-__device__ __forceinline__ uint64_t update_vertex(const BatchArgs &b, uint64_t i, uint32_t level)
-{
-    uint64_t y = b.Y[i] & ~b.V[i];
-    b.Y[i] = 0;
-    b.F[i] = y;
-    if (!y) return 0;
-    b.V[i] |= y;
-    uint32_t *lv = b.levels + i * 64;
-    uint64_t m = y;
-    while (m) {
-        const uint32_t s = __builtin_ctzll(m);
-        m &= m - 1;
-        lv[s] = level;
-    }
-    return y;
-}
-
-// Updates the vertices [base, base + 64) held one per lane (base a multiple of
-// 64) and writes their two words of the active bit vector.
+// Updates the vertices [base, base + 64), held one per lane (base a multiple
+// of 64): takes each one's new frontier bits Y & ~V, marks them visited, clears
+// Y for the next level's product, writes the two words of the active bit
+// vector, and records the level of every new (vertex, source) pair.  The level
+// rows are vertex-major (64 words per vertex), so the wave writes them one
+// vertex at a time, lane s storing source s: one store per vertex covers its
+// row's contiguous words, where a lane per vertex would scatter 4-byte stores
+// over 64 rows.  Returns whether this lane's vertex has new bits.
 __device__ __forceinline__ bool update_group(const BatchArgs &b, uint64_t base, uint32_t level)
 {
-    const uint64_t i = base + lane_id();
-    const uint64_t y = i < b.n ? update_vertex(b, i, level) : 0;
+    const uint32_t lane = lane_id();
+    const uint64_t i = base + lane;
+    uint64_t y = 0;
+    if (i < b.n) {
+        y = b.Y[i] & ~b.V[i];
+        b.Y[i] = 0;
+        b.F[i] = y;
+        if (y) b.V[i] |= y;
+    }
     const uint64_t m = __ballot(y != 0);
-    const uint64_t w = base / 32 + lane_id();
-    if (lane_id() < 2 && w < (b.n + 31u) / 32u) b.act[w] = (uint32_t)(m >> (32 * lane_id()));
+    const uint64_t w = base / 32 + lane;
+    if (lane < 2 && w < (b.n + 31u) / 32u) b.act[w] = (uint32_t)(m >> (32 * lane));
+    for (uint64_t todo = m; todo;) {
+        const uint32_t k = (uint32_t)__builtin_ctzll(todo);
+        todo &= todo - 1;
+        const uint64_t yk = ((uint64_t)readlane((uint32_t)(y >> 32), (int)k) << 32) | readlane((uint32_t)y, (int)k);
+        if ((yk >> lane) & 1) b.levels[(base + k) * 64 + lane] = level;
+    }
     return y != 0;
 }
 

@@ -104,20 +104,20 @@ __global__ void session_update_kernel(uint32_t n, uint64_t *Y, uint64_t *F, uint
             y = Y[i] & ~V[i];
             Y[i] = 0;
             F[i] = y;
-            if (y) {
-                V[i] |= y;
-                uint64_t b = y;
-                while (b) {
-                    const uint32_t s = __builtin_ctzll(b);
-                    b &= b - 1;
-                    steps[i * 64 + s] = step;
-                }
-            }
+            if (y) V[i] |= y;
         }
         const uint64_t m = __ballot(y != 0);
         const uint64_t w = base / 32 + lane_id();
         if (lane_id() < 2 && w < (n + 31u) / 32u) act[w] = (uint32_t)(m >> (32 * lane_id()));
         seen |= y;
+        // the step rows are vertex-major (64 words per vertex): one vertex at a
+        // time, lane s storing slot s, so one store covers the row's words
+        for (uint64_t todo = m; todo;) {
+            const uint32_t k = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint64_t yk = ((uint64_t)readlane((uint32_t)(y >> 32), (int)k) << 32) | readlane((uint32_t)y, (int)k);
+            if ((yk >> lane_id()) & 1) steps[(base + k) * 64 + lane_id()] = step;
+        }
     }
     // OR over the wave, then one atomic per wave
 #pragma unroll
