@@ -42,6 +42,9 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / B2SR_WAVE;
 constexpr uint32_t kMapWords = 4096;  // bitmap of up to 131072 tile columns
 constexpr unsigned kMaxGroups = 8192;  // workgroups of a masked-product launch
+#ifndef B2SR_TC_FLAT_SWAP
+#define B2SR_TC_FLAT_SWAP 1  // orientation lists built one thread per mask tile
+#endif
 
 template <int T> __device__ __forceinline__ row_t<T> load_word(const void *bits, size_t idx)
 {
@@ -429,6 +432,35 @@ __global__ void swap_count_kernel(GemmArgs g, uint32_t *counts)
     }
 }
 
+// The tile-row of every mask tile: rowof[m] = I for m in [m_rp[I], m_rp[I + 1]),
+// one wave per tile-row writing its range with contiguous stores.
+__global__ void tile_rows_kernel(GemmArgs g, uint32_t *rowof)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t I = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B2SR_WAVE; I < g.ntr; I += nwaves)
+        for (uint32_t m = g.m_rp[I] + lane; m < g.m_rp[I + 1]; m += B2SR_WAVE) rowof[m] = (uint32_t)I;
+}
+
+// The same counts and lists as swap_count_kernel and swap_fill_kernel, one
+// thread per mask tile: its loads are independent of every other thread's, where
+// a wave per tile-row leaves most lanes idle on short rows.
+template <bool FILL>
+__global__ void swap_flat_kernel(GemmArgs g, const uint32_t *rowof, uint32_t ntiles_m, uint32_t *counts,
+                                 uint32_t *list)
+{
+    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < ntiles_m;
+         m += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t I = rowof[m], J = g.m_ci[m];
+        if (!swapped(g.a_rp[I + 1] - g.a_rp[I], g.b_rp[J + 1] - g.b_rp[J])) continue;
+        const uint32_t e = atomicAdd(&counts[J], 1u);
+        if constexpr (FILL) {
+            list[2 * (size_t)e] = I;
+            list[2 * (size_t)e + 1] = (uint32_t)m;
+        }
+    }
+}
+
 __global__ void swap_fill_kernel(GemmArgs g, uint32_t *cursor, uint32_t *list)
 {
     const uint32_t lane = lane_id();
@@ -480,7 +512,7 @@ __global__ void copy_u32_kernel(uint32_t n, const uint32_t *__restrict__ a, uint
 }
 
 struct SwapLayout {
-    uint32_t *off, *cursor, *list, *item_off, *items, *sums;
+    uint32_t *off, *cursor, *list, *item_off, *items, *sums, *rowof;
     size_t bytes;
 };
 
@@ -502,6 +534,7 @@ SwapLayout swap_layout(const b2sr_matrix *A, const b2sr_matrix *M, void *ws)
     // per row, one item per started chunk of its own tiles and of its swapped list
     L.items = take((2 * ntr + (size_t)M->ntiles / kOwnChunk + (size_t)M->ntiles / kSwapChunk + 1) * 12);
     L.sums = take(b2sr_scan::scan_blocks(ntr) * 4);
+    L.rowof = B2SR_TC_FLAT_SWAP ? take((size_t)M->ntiles * 4) : nullptr;
     L.bytes = o;
     return L;
 }
@@ -522,13 +555,26 @@ int build_swap_lists(GemmArgs &g, const b2sr_matrix *A, const b2sr_matrix *M, vo
     // list offsets: off[0] = 0, off[J + 1] = swapped tiles of rows 0 .. J
     if ((rc = b2sr::fill_u32(L.off, (uint64_t)ntr + 1, 0, s))) return rc;
     const unsigned wgrid = b2sr::grid_for(ntr, 256 / B2SR_WAVE, kMaxGroups);  // grid-stride over tile-rows
-    swap_count_kernel<<<wgrid, 256, 0, s>>>(g, L.off + 1);
-    if ((rc = b2sr::check_launch("swap_count_kernel"))) return rc;
+    const unsigned tgrid = b2sr::grid_for(M->ntiles, 256, kMaxGroups);       // grid-stride over mask tiles
+    if constexpr (B2SR_TC_FLAT_SWAP) {
+        tile_rows_kernel<<<wgrid, 256, 0, s>>>(g, L.rowof);
+        if ((rc = b2sr::check_launch("tile_rows_kernel"))) return rc;
+        swap_flat_kernel<false><<<tgrid, 256, 0, s>>>(g, L.rowof, M->ntiles, L.off + 1, nullptr);
+        if ((rc = b2sr::check_launch("swap_flat_kernel"))) return rc;
+    } else {
+        swap_count_kernel<<<wgrid, 256, 0, s>>>(g, L.off + 1);
+        if ((rc = b2sr::check_launch("swap_count_kernel"))) return rc;
+    }
     if ((rc = device_scan<uint32_t>(ntr, LoadArray<uint32_t>{L.off + 1}, L.off + 1, true, L.sums, s))) return rc;
     copy_u32_kernel<<<b2sr::grid_for(ntr, 256, 4096), 256, 0, s>>>(ntr, L.off, L.cursor);
     if ((rc = b2sr::check_launch("copy_u32_kernel"))) return rc;
-    swap_fill_kernel<<<wgrid, 256, 0, s>>>(g, L.cursor, L.list);
-    if ((rc = b2sr::check_launch("swap_fill_kernel"))) return rc;
+    if constexpr (B2SR_TC_FLAT_SWAP) {
+        swap_flat_kernel<true><<<tgrid, 256, 0, s>>>(g, L.rowof, M->ntiles, L.cursor, L.list);
+        if ((rc = b2sr::check_launch("swap_flat_kernel"))) return rc;
+    } else {
+        swap_fill_kernel<<<wgrid, 256, 0, s>>>(g, L.cursor, L.list);
+        if ((rc = b2sr::check_launch("swap_fill_kernel"))) return rc;
+    }
     // work items: item_off[0] = 0, item_off[X + 1] = items of rows 0 .. X
     if ((rc = b2sr::fill_u32(L.item_off, 1, 0, s))) return rc;
     item_count_kernel<<<b2sr::grid_for(ntr, 256, 4096), 256, 0, s>>>(g, L.off, L.item_off + 1);
