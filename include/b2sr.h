@@ -315,11 +315,12 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
 /* ---- graph algorithms on the products above (Sec. V) ---------------------
  * Each driver runs its iteration loop on the host, launching the kernels
  * above on `stream`, and synchronises `stream` to test convergence.  BFS,
- * multi-source BFS, SSSP and CC keep their convergence state on the device:
+ * multi-source BFS, SSSP, CC and eccentricity keep their convergence state on
+ * the device:
  * every kernel of an iteration is gated on it, the host enqueues iterations in
  * batches of 2, 4, 8 and then 16 and reads the state once per batch, and the
- * iterations enqueued past the end return at once.  MIS, colouring and
- * eccentricity read one device word per iteration; PageRank runs a fixed
+ * iterations enqueued past the end return at once.  MIS and colouring read
+ * one device word per iteration; PageRank runs a fixed
  * number of iterations and reads nothing.  The number of iterations run is
  * written to the HOST pointer *iters when it is not NULL.  ws is a workspace
  * of b2sr_algo_workspace_bytes(A, algo) bytes.  The drivers read A as the
@@ -400,7 +401,9 @@ int b2sr_color(const b2sr_matrix *A, const uint64_t *key, uint32_t *colors, void
  * one frontier word, as b2sr_msbfs, without storing levels): ecc[s] = the
  * largest finite BFS level from srcs[s] (0 for a vertex that reaches nothing).
  * srcs and ecc are HOST arrays of nsrc entries (any count; repeats allowed).
- * Reads one word per level, so it synchronises `stream`.  Workspace:
+ * Convergence is kept on the device (as for b2sr_msbfs); the host reads the
+ * state once per batch of levels and the eccentricities once per 64 sources,
+ * so it synchronises `stream`.  Workspace:
  * b2sr_algo_workspace_bytes(A, B2SR_ALGO_ECC). */
 int b2sr_eccentricity(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc, uint32_t *ecc,
                       void *ws, size_t ws_bytes, hipStream_t stream);

@@ -62,7 +62,8 @@ constexpr uint32_t kState = 4, kIters = 5, kLast = 6, kPrev = 7, kFlagWords = 8;
 // iteration bound), otherwise the next iteration runs the sparse-frontier
 // product when fewer than sparse_below were found; and it clears the
 // accumulator for iteration it + 2.
-__device__ void finish_iteration(uint32_t *flags, uint32_t it, uint32_t found_wave, uint32_t sparse_below,
+// Returns true in thread 0 of the last block only.
+__device__ bool finish_iteration(uint32_t *flags, uint32_t it, uint32_t found_wave, uint32_t sparse_below,
                                  uint32_t max_iters)
 {
     __shared__ uint32_t s_found;
@@ -70,15 +71,16 @@ __device__ void finish_iteration(uint32_t *flags, uint32_t it, uint32_t found_wa
     __syncthreads();
     if (lane_id() == 0 && found_wave) atomicAdd(&s_found, found_wave);
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x != 0) return false;
     unsigned long long *acc = (unsigned long long *)flags + (it & 1);
     const unsigned long long old = atomicAdd(acc, (1ull << 32) | s_found);
-    if ((uint32_t)(old >> 32) != gridDim.x - 1) return;
+    if ((uint32_t)(old >> 32) != gridDim.x - 1) return false;
     const uint32_t found = (uint32_t)old + s_found;
     atomicExch(acc, 0ull);
     atomicExch(flags + kPrev, atomicExch(flags + kLast, found));
     atomicExch(flags + kIters, it);
     atomicExch(flags + kState, (found == 0 || it >= max_iters) ? kDone : (found < sparse_below ? kRunSparse : kRunDense));
+    return true;
 }
 
 // Runs `one(iteration index)` in batches, reading the device state after each
@@ -195,10 +197,10 @@ __device__ __forceinline__ void store_pred_bits(uint32_t *bits, uint64_t base, u
 
 // ---------------------------------------------------------------- eccentricity
 // 64 sources at a time as bits of one frontier word per vertex, as the
-// multi-source BFS does, but no levels are stored: each level ORs its new
-// frontier words into alive[level & 1], and the host reads which sources still
-// reached new vertices.  A source's eccentricity is its last live level.
-__global__ void ecc_init_kernel(uint32_t n, uint64_t *F, uint64_t *V, uint32_t *act, uint64_t *alive)
+// multi-source BFS does, but no levels are stored per vertex: each level ORs
+// the sources that reached new vertices into one word for that level, and a
+// source's eccentricity is the last level whose word holds its bit.
+__global__ void ecc_init_kernel(uint32_t n, uint64_t *F, uint64_t *V, uint32_t *act, uint64_t *hist, uint32_t *flags)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -207,7 +209,8 @@ __global__ void ecc_init_kernel(uint32_t n, uint64_t *F, uint64_t *V, uint32_t *
         V[i] = 0;
     }
     for (uint64_t w = tid; w < (n + 31) / 32; w += stride) act[w] = 0;
-    if (tid < 2) alive[tid] = 0;
+    if (tid < 2) hist[1 + tid] = 0;  // level 1's word (later levels are cleared as the run goes)
+    if (tid < kFlagWords) flags[tid] = 0;  // state: dense
 }
 
 __global__ void ecc_seed_kernel(uint32_t nsrc, const uint32_t *srcs, uint64_t *F, uint64_t *V, uint32_t *act)
@@ -221,9 +224,15 @@ __global__ void ecc_seed_kernel(uint32_t nsrc, const uint32_t *srcs, uint64_t *F
         }
 }
 
-__global__ void ecc_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, uint64_t *V, uint32_t *act,
-                                  uint64_t *alive, uint32_t level)
+// The gated form: the level comes from the device state, every wave ORs the
+// sources that reached new vertices into hist[level] (one 64-bit word per
+// level), and the last block clears hist[level + 1] for the next level.  After
+// the run, a source's eccentricity is the last level whose word holds its bit.
+__global__ void ecc_update_gated_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, uint64_t *V, uint32_t *act,
+                                        uint64_t *hist, uint32_t *flags, uint32_t max_iters)
 {
+    if (flags[kState] == kDone) return;
+    const uint32_t level = flags[kIters] + 1;
     uint64_t seen = 0;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
     for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
@@ -236,14 +245,23 @@ __global__ void ecc_update_kernel(uint32_t n, const uint64_t *Y, uint64_t *F, ui
             if (y) V[i] |= y;
         }
         seen |= y;
-        const uint64_t m = __ballot(y != 0);
-        const uint64_t w = base / 32 + lane_id();
-        if (lane_id() < 2 && w < (n + 31u) / 32u) act[w] = (uint32_t)(m >> (32 * lane_id()));
+        store_pred_bits(act, base, n, y != 0);
     }
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) seen |= shfl_xor(seen, d);
-    if (lane_id() == 0 && seen) atomicOr((unsigned long long *)alive + (level & 1), (unsigned long long)seen);
-    if (blockIdx.x == 0 && threadIdx.x == 0) alive[(level + 1) & 1] = 0;
+    if (lane_id() == 0 && seen) atomicOr((unsigned long long *)hist + level, (unsigned long long)seen);
+    if (finish_iteration(flags, level, seen ? 1u : 0u, 0, max_iters)) atomicExch((unsigned long long *)hist + level + 1, 0ull);
+}
+
+// Eccentricities of the k sources of a batch from the per-level words: lane s
+// takes the last level 1 .. flags[kIters] whose word holds bit s (0 if none).
+__global__ void ecc_final_kernel(const uint64_t *hist, const uint32_t *flags, uint32_t k, uint32_t *ecc)
+{
+    const uint32_t s = threadIdx.x, levels = flags[kIters];
+    uint32_t e = 0;
+    for (uint32_t l = 1; l <= levels; ++l)
+        if ((hist[l] >> s) & 1u) e = l;
+    if (s < k) ecc[s] = e;
 }
 
 // New frontier words: Y & ~V.  Marks them visited, records levels, and writes
@@ -478,7 +496,8 @@ Layout carve(const b2sr_matrix *A, int algo, void *ws)
         L.Y = c.take<uint64_t>(n * 8);
         L.srcs = c.take<uint32_t>(64 * 4);
         L.act = c.take<uint32_t>(nw * 4);
-        L.alive = c.take<uint64_t>(2 * 8);
+        L.alive = c.take<uint64_t>(((size_t)n + 3) * 8);  // one word per level 0 .. n + 2
+        L.u0 = c.take<uint32_t>(64 * 4);                   // the batch's eccentricities
         break;
     case B2SR_ALGO_MIS:
     case B2SR_ALGO_COLOR:
@@ -792,29 +811,28 @@ int b2sr_eccentricity(const b2sr_matrix *A, const uint32_t *srcs, uint32_t nsrc,
         if (srcs[s] >= n) return B2SR_EINVAL;
     for (uint32_t b = 0; b < nsrc; b += 64) {
         const uint32_t k = std::min<uint32_t>(64, nsrc - b);
-        for (uint32_t s = 0; s < k; ++s) ecc[b + s] = 0;
         if ((rc = b2sr::check(hipMemcpyAsync(L.srcs, srcs + b, k * 4, hipMemcpyHostToDevice, stream),
                               "hipMemcpyAsync(srcs)")))
             return rc;
-        ecc_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, L.F, L.V, L.act, L.alive);
+        ecc_init_kernel<<<vgrid(n), 256, 0, stream>>>(n, L.F, L.V, L.act, L.alive, L.flags);
         if ((rc = b2sr::check_launch("ecc_init_kernel"))) return rc;
         ecc_seed_kernel<<<1, 64, 0, stream>>>(k, L.srcs, L.F, L.V, L.act);
         if ((rc = b2sr::check_launch("ecc_seed_kernel"))) return rc;
-        for (uint32_t level = 1;; ++level) {
-            if ((rc = spmv_bin_full(A, B2SR_OR_U64, L.F, nullptr, L.act, nullptr, 0, 0.0, 0.0, L.Y, nullptr, 0,
-                                    stream)))
-                return rc;
-            ecc_update_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, L.act, L.alive, level);
-            if ((rc = b2sr::check_launch("ecc_update_kernel"))) return rc;
-            uint64_t alive = 0;
-            if ((rc = b2sr::check(hipMemcpyAsync(&alive, L.alive + (level & 1), 8, hipMemcpyDeviceToHost, stream),
-                                  "hipMemcpyAsync(alive)")))
-                return rc;
-            if ((rc = b2sr::check(hipStreamSynchronize(stream), "hipStreamSynchronize"))) return rc;
-            if (!alive) break;
-            for (uint32_t s = 0; s < k; ++s)
-                if ((alive >> s) & 1u) ecc[b + s] = level;
-        }
+        const uint32_t max_iters = n + 1;
+        if ((rc = run_gated(L.flags, max_iters, nullptr, stream, [&](uint32_t) {
+                 if (int r = b2sr::spmv_full_gated(A, B2SR_OR_U64, L.F, L.act, 0, 0.0, L.Y, L.flags + kState, kRunDense,
+                                                   stream))
+                     return r;
+                 ecc_update_gated_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.Y, L.F, L.V, L.act, L.alive, L.flags,
+                                                                       max_iters);
+                 return b2sr::check_launch("ecc_update_gated_kernel");
+             })))
+            return rc;
+        ecc_final_kernel<<<1, 64, 0, stream>>>(L.alive, L.flags, k, L.u0);
+        if ((rc = b2sr::check_launch("ecc_final_kernel"))) return rc;
+        if ((rc = b2sr::check(hipMemcpyAsync(ecc + b, L.u0, k * 4, hipMemcpyDeviceToHost, stream), "hipMemcpyAsync(ecc)")))
+            return rc;
+        if ((rc = b2sr::check(hipStreamSynchronize(stream), "hipStreamSynchronize"))) return rc;
     }
     return B2SR_OK;
 }
