@@ -22,6 +22,15 @@
 //                            error instead of hanging;
 //   * a plan: the persistent launch (with its initialisation) instantiated as a
 //     hipGraph once and replayed.
+// A work item (one chunk of one group) whose tile columns meet no frontier
+// vertex is skipped after two reads: each call first records every item's
+// column range, and each level's update marks, one bit per 1024 vertices,
+// which ranges hold frontier vertices.  Late levels, when most graphs of the
+// batch have finished, then skip those graphs' items instead of reading all
+// their tile columns (every per-level product; in the persistent kernel the
+// levels whose summary has under a quarter of its bits set, which it runs at
+// a fixed stride rather than by claims).
+#include <algorithm>
 #include <new>
 #include <utility>
 
@@ -37,6 +46,9 @@ constexpr uint32_t kMaxGroups = 8;
 // generation, and the persistent kernel's two work counters (one per level
 // parity), 256 bytes apart, each on a line of its own.
 constexpr uint32_t kBarrierCount = 64, kBarrierGen = 128, kClaim = 192, kFlagWords = 320;
+// Words 8 and 9 (by level parity): the persistent kernel's count of summary
+// bits its update set.
+constexpr uint32_t kLiveBits = 8;
 constexpr uint32_t kUnreached = 0xFFFFFFFFu;
 
 struct Group {
@@ -46,11 +58,24 @@ struct Group {
     uint32_t nchunks;
 };
 
+// Activity summary for skipping work items: bit k of a summary is set when a
+// vertex in [k * 1024, (k + 1) * 1024) is in the frontier.
+constexpr uint32_t kCoarseShift = 10;
+// At most this many items have a recorded column range (beyond it no item is
+// skipped): 8 MiB of workspace.
+constexpr uint64_t kMaxRangeItems = 1u << 20;
+
 struct BatchArgs {
     uint32_t n, ngroups, nitems, max_levels;
     Group g[kMaxGroups];
     uint64_t *F, *V, *Y;
     uint32_t *act;     // bit vector: vertices whose frontier word is non-zero
+    // per item, the summary bits its tile columns fall in: [lo, hi] (nullptr:
+    // no item is skipped); two summaries by level parity: the update of level l
+    // writes coarse + (l & 1) * coarse_words (level 0: the seeds) and clears the
+    // other, which the product of level l has just read
+    uint32_t *ranges, *coarse;
+    uint32_t coarse_words;
     uint32_t *levels;  // n x 64, vertex-major
     uint32_t *flags;   // [0], [1]: per-level parity flags; [2]: levels run;
                        // [5]: barrier timed out (the barrier's own words are further on);
@@ -83,10 +108,12 @@ __global__ void batch_init_kernel(BatchArgs b)
         b.Y[i] = 0;
     }
     for (uint64_t w = tid; w < (b.n + 31) / 32; w += stride) b.act[w] = 0;
+    for (uint64_t w = tid; w < 2ull * b.coarse_words; w += stride) b.coarse[w] = 0;
     if (tid < 8 && !(tid == 5 && b.sticky_timeout)) b.flags[tid] = 0;
     if (tid == 8) b.flags[kBarrierCount] = 0;
     if (tid == 9) b.flags[kClaim] = 0;
     if (tid == 10) b.flags[kClaim + 64] = 0;
+    if (tid == 11 || tid == 12) b.flags[kLiveBits + tid - 11] = 0;
 }
 
 // Seeds are distinct (vertex, bit) pairs, so the level writes never collide and
@@ -100,9 +127,71 @@ __global__ void batch_seed_kernel(BatchArgs b)
         atomicOr((unsigned long long *)b.F + v, 1ull << s);
         atomicOr((unsigned long long *)b.V + v, 1ull << s);
         atomicOr(b.act + (v >> 5), 1u << (v & 31));
+        atomicOr(b.coarse + (v >> kCoarseShift) / 32, 1u << ((v >> kCoarseShift) & 31));  // level 0's summary
         b.levels[(size_t)v * 64 + s] = 0;
     }
 }
+
+// Every item's column range, as the summary bits [lo, hi] its tile columns
+// fall in: one wave per item, a min and max over its tiles.
+__global__ void batch_ranges_kernel(BatchArgs b)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t waves = gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint32_t item = blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE; item < b.nitems;
+         item += waves) {
+        uint32_t gi = 0;
+        while (gi + 1 < b.ngroups && item >= b.g[gi + 1].item0) ++gi;
+        const Group &g = b.g[gi];
+        const uint32_t t0 = (item - g.item0) * g.p.chunk, t1 = min(t0 + g.p.chunk, g.p.ntiles);
+        uint32_t lo = 0xFFFFFFFFu, hi = 0;
+        // eight independent loads per lane in flight (a load per iteration left
+        // the kernel waiting on each in turn)
+        for (uint32_t t = t0 + lane; t < t1; t += 8 * B2SR_WAVE) {
+            uint32_t j[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) j[u] = g.p.tci[min(t + u * B2SR_WAVE, t1 - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                lo = min(lo, j[u]);
+                hi = max(hi, j[u]);
+            }
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            lo = min(lo, shfl_xor(lo, d));
+            hi = max(hi, shfl_xor(hi, d));
+        }
+        if (lane == 0) {
+            const bool empty = lo > hi;  // no tiles: never live
+            b.ranges[2 * (size_t)item] = empty ? 1u : (uint32_t)(((uint64_t)lo * g.tile) >> kCoarseShift);
+            b.ranges[2 * (size_t)item + 1] =
+                empty ? 0u : (uint32_t)(((uint64_t)hi * g.tile + g.tile - 1) >> kCoarseShift);
+        }
+    }
+}
+
+// Whether work item `item` may meet the frontier summarised in `coarse` (wave-
+// uniform): any summary bit set within the item's range.  The summary is read
+// with agent-scope loads, past any stale cached copy of an earlier level's.
+// Not inlined: inside the persistent kernel's claim loop the inlined check
+// raised the kernel's registers from 76 to 84 VGPRs (6 -> 5 waves per SIMD);
+// as a call it costs 80 and keeps 6.
+__device__ __attribute__((noinline)) bool item_live(const uint32_t *ranges, const uint32_t *coarse, uint32_t item)
+{
+    if (!ranges) return true;
+    const uint32_t lo = readfirstlane(ranges[2 * (size_t)item]), hi = readfirstlane(ranges[2 * (size_t)item + 1]);
+    if (lo > hi) return false;
+    bool any = false;
+    for (uint32_t w = lo / 32 + lane_id(); w <= hi / 32; w += B2SR_WAVE) {
+        uint32_t m = __hip_atomic_load(coarse + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (w == lo / 32) m &= ~0u << (lo & 31);
+        if (w == hi / 32) m &= ~0u >> (31 - (hi & 31));
+        any |= m != 0;
+    }
+    return __any(any);
+}
+
 
 // Updates the vertices [base, base + 64), held one per lane (base a multiple
 // of 64): takes each one's new frontier bits Y & ~V, marks them visited, clears
@@ -135,6 +224,50 @@ __device__ __forceinline__ bool update_group(const BatchArgs &b, uint64_t base, 
     return y != 0;
 }
 
+// The update of `level` for wave `wave` of `nwaves`: a contiguous run of
+// 64-vertex groups, so that the wave sets each summary bit its run reaches
+// once (one atomic per bit and wave; a wave per group in a grid-stride order
+// put an atomic per group on the summary's few cache lines, and the update
+// took 20 % longer).  Returns the number of vertices with new bits.
+template <bool BITS = false>
+__device__ __forceinline__ uint32_t update_run(const BatchArgs &b, uint64_t wave, uint64_t nwaves, uint32_t level,
+                                               uint32_t *fresh_bits = nullptr)
+{
+    const uint64_t groups = ((uint64_t)b.n + 63) / 64, per = (groups + nwaves - 1) / nwaves;
+    uint32_t *const c = b.coarse + (level & 1) * b.coarse_words;
+    uint32_t count = 0, pend = 0xFFFFFFFFu;  // the summary bit waiting to be set
+    uint32_t fresh = 0;                      // (BITS) bits this wave set first
+    auto set = [&](uint32_t k) {
+        uint32_t f = 0;
+        if (lane_id() == 0) {
+            if constexpr (BITS) f = (atomicOr(c + k / 32, 1u << (k & 31)) >> (k & 31)) & 1u ? 0u : 1u;
+            else atomicOr(c + k / 32, 1u << (k & 31));
+        }
+        if constexpr (BITS) fresh += readfirstlane(f);
+    };
+    for (uint64_t g = wave * per, ge = min(g + per, groups); g < ge; ++g) {
+        const uint64_t m = __ballot(update_group(b, g * 64, level));
+        if (!m) continue;
+        count += (uint32_t)__popcll(m);
+        const uint32_t k = (uint32_t)((g * 64) >> kCoarseShift);
+        if (k != pend) {
+            if (pend != 0xFFFFFFFFu) set(pend);
+            pend = k;
+        }
+    }
+    if (pend != 0xFFFFFFFFu) set(pend);
+    if constexpr (BITS) *fresh_bits = fresh;
+    return count;
+}
+
+// The update of `level` clears the summary the product of `level` read (the
+// one the update of level + 1 writes).
+__device__ __forceinline__ void clear_other_summary(const BatchArgs &b, uint32_t level, uint64_t tid, uint64_t stride)
+{
+    uint32_t *c = b.coarse + ((level + 1) & 1) * b.coarse_words;
+    for (uint64_t w = tid; w < b.coarse_words; w += stride) c[w] = 0;
+}
+
 // Per-level kernels keep the level count and the finished flag on the device,
 // so a fixed sequence of levels can be replayed from a hipGraph: once the BFS
 // has finished, every later kernel returns at once.
@@ -142,11 +275,9 @@ __global__ void batch_update_kernel(BatchArgs b)
 {
     if (b.flags[6]) return;
     const uint32_t level = b.flags[2] + 1;
-    bool any = false;
+    clear_other_summary(b, level, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x);
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
-    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < b.n;
-         base += waves * 64)
-        any |= update_group(b, base, level);
+    const bool any = update_run(b, (uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE, waves, level) != 0;
     if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(b.flags + (level & 1), 1u);
 }
 
@@ -162,13 +293,21 @@ __global__ void batch_advance_kernel(uint32_t *flags, uint32_t max_levels)
 }
 
 // One group's product for one level (per-level modes): one wave per chunk.
+// The item skip's arguments for one group's per-level product.
+struct Skip {
+    const uint32_t *ranges, *coarse;
+    uint32_t coarse_words, item0;
+};
+
 template <int T>
-__global__ void __launch_bounds__(256) batch_product_kernel(SpmvArgs p, uint32_t nchunks, const uint32_t *flags)
+__global__ void __launch_bounds__(256) batch_product_kernel(SpmvArgs p, uint32_t nchunks, const uint32_t *flags, Skip sk)
 {
     __shared__ __align__(16) uint64_t s_x[4 * kSliceBytes / sizeof(uint64_t)];
     if (flags[6]) return;
     const uint32_t wave = blockIdx.x * (blockDim.x / B2SR_WAVE) + readfirstlane(threadIdx.x / B2SR_WAVE);
     if (wave >= nchunks) return;
+    // this level's product reads the summary of the last level's frontier
+    if (!item_live(sk.ranges, sk.coarse + (flags[2] & 1) * sk.coarse_words, sk.item0 + wave)) return;
     spmv_chunk<T, kOr64, true>(p, wave, s_x + (threadIdx.x / B2SR_WAVE) * (kSliceBytes / sizeof(uint64_t)));
 }
 
@@ -245,7 +384,14 @@ __device__ __forceinline__ uint32_t grid_barrier(uint32_t *flags, const uint32_t
 #ifndef B2SR_PW_WIDE
 #define B2SR_PW_WIDE 1   // the same for masks holding T = 8 or 16
 #endif
-constexpr int persistent_waves(unsigned tmask) { return (tmask & 6u) ? B2SR_PW_WIDE : B2SR_PW_SMALL; }
+#ifndef B2SR_PW_T4
+#define B2SR_PW_T4 6     // the same for a batch all at T = 4: 80 VGPRs with a few 8-byte
+                         // spills outside the product loop, 6 waves per SIMD instead of 5
+#endif
+constexpr int persistent_waves(unsigned tmask)
+{
+    return tmask == 1u ? B2SR_PW_T4 : (tmask & 6u) ? B2SR_PW_WIDE : B2SR_PW_SMALL;
+}
 
 #ifndef B2SR_PERSIST_MAX_PER_CU
 #define B2SR_PERSIST_MAX_PER_CU 3
@@ -259,6 +405,9 @@ constexpr unsigned kPersistThreads = B2SR_PERSIST_THREADS;
 #endif
 #ifndef B2SR_PERSIST_CLAIM_SPARSE
 #define B2SR_PERSIST_CLAIM_SPARSE 2  // the same after a small one
+#endif
+#ifndef B2SR_PERSIST_STRIDE_BELOW
+#define B2SR_PERSIST_STRIDE_BELOW 4  // a fixed stride when under 1/4 of the summary bits are set
 #endif
 #ifndef B2SR_PERSIST_SPARSE_FACTOR
 #define B2SR_PERSIST_SPARSE_FACTOR 4  // a frontier is small below this many vertices per item
@@ -287,16 +436,30 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
         // counter (256-graph batch: 24.9 -> 22.7 ms; 4 items 23.3, 8 items 24.1).
         uint32_t *const counter = b.flags + kClaim + (level & 1) * 64;
         const uint32_t frontier = readfirstlane(level == 1 ? b.nseeds : b.flags[(level - 1) & 1]);
-        const uint32_t per_claim = (uint64_t)frontier < (uint64_t)b.nitems * B2SR_PERSIST_SPARSE_FACTOR
-                                       ? B2SR_PERSIST_CLAIM_SPARSE : B2SR_PERSIST_CLAIM;
-        uint32_t claims = 0;
+        // When under 1/4 of the summary bits are set (and every item has a
+        // column range), waves take items at a fixed stride instead: per_claim
+        // 0.  Most items are then dead, and a claim per item on the one counter
+        // (about 18 ns each, serialised) set the level's time whatever the
+        // work.  Level 1's summary (the seeds) is not counted: it claims.
+        const uint32_t live_bits = level == 1 ? 0xFFFFFFFFu : readfirstlane(b.flags[kLiveBits + ((level - 1) & 1)]);
+        const bool few = b.ranges && (uint64_t)live_bits * B2SR_PERSIST_STRIDE_BELOW < (((uint64_t)b.n + (1u << kCoarseShift) - 1) >> kCoarseShift);
+        const bool small = (uint64_t)frontier < (uint64_t)b.nitems * B2SR_PERSIST_SPARSE_FACTOR;
+        const uint32_t per_claim = few ? 0u : small ? B2SR_PERSIST_CLAIM_SPARSE : B2SR_PERSIST_CLAIM;
+        uint32_t claims = 0, next = wave;
         for (;;) {
             uint32_t first = 0;
-            if (lane_id() == 0) first = atomicAdd(counter, per_claim);
-            first = readfirstlane(shfl(first, 0));
+            if (per_claim) {
+                if (lane_id() == 0) first = atomicAdd(counter, per_claim);
+                first = readfirstlane(shfl(first, 0));
+            } else {
+                first = next;
+                next += nwaves;
+            }
             if (first >= b.nitems || ++claims > b.nitems) break;
-            const uint32_t stop = min(b.nitems, first + per_claim);
+            const uint32_t stop = min(b.nitems, first + max(per_claim, 1u));
             for (uint32_t item = first; item < stop; ++item) {
+            // (this level reads the summary of the last level's frontier)
+            if (!per_claim && !item_live(b.ranges, b.coarse + ((level - 1) & 1) * b.coarse_words, item)) continue;
             uint32_t gi = 0;
             while (gi + 1 < b.ngroups && item >= b.g[gi + 1].item0) ++gi;
             const Group &g = b.g[gi];
@@ -326,17 +489,20 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
         if (b.stamps) stamp(b, level, 2);
         // the level's count of new frontier vertices: the convergence test (zero
         // or not) and the next level's claim size
-        __shared__ uint32_t s_count;
-        if (threadIdx.x == 0) s_count = 0;
+        __shared__ uint32_t s_count, s_fresh;
+        if (threadIdx.x == 0) s_count = s_fresh = 0;
         __syncthreads();
-        uint32_t count = 0;
-        for (uint64_t base = (uint64_t)wave * 64; base < b.n; base += (uint64_t)nwaves * 64)
-            count += (uint32_t)__popcll(__ballot(update_group(b, base, level)));
+        clear_other_summary(b, level, tid, (uint64_t)gridDim.x * blockDim.x);
+        uint32_t fresh = 0;
+        const uint32_t count = update_run<true>(b, wave, nwaves, level, &fresh);
         if (lane_id() == 0 && count) atomicAdd(&s_count, count);
+        if (lane_id() == 0 && fresh) atomicAdd(&s_fresh, fresh);
         __syncthreads();
         if (threadIdx.x == 0 && s_count) atomicAdd(b.flags + (level & 1), s_count);
+        if (threadIdx.x == 0 && s_fresh) atomicAdd(b.flags + kLiveBits + (level & 1), s_fresh);
         if (tid == 0) {
             b.flags[(level + 1) & 1] = 0;
+            b.flags[kLiveBits + ((level + 1) & 1)] = 0;
             b.flags[2] = level;
             b.flags[kClaim + ((level + 1) & 1) * 64] = 0;  // the next level's work counter
         }
@@ -352,7 +518,8 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
 
 struct Layout {
     uint64_t *F, *V, *Y;
-    uint32_t *act, *flags;
+    uint32_t *act, *flags, *coarse, *ranges;
+    uint32_t coarse_words, range_items;
     size_t bytes;
 };
 
@@ -371,6 +538,12 @@ Layout carve(uint32_t n, void *ws)
     L.Y = (uint64_t *)take((size_t)n * 8);
     L.act = (uint32_t *)take(((size_t)n + 31) / 32 * 4);
     L.flags = (uint32_t *)take(kFlagWords * 4);
+    L.coarse_words = (uint32_t)((((uint64_t)n + (1u << kCoarseShift) - 1) >> kCoarseShift) + 31) / 32;
+    L.coarse = (uint32_t *)take((size_t)L.coarse_words * 2 * 4);
+    // no more items than tiles: at most 8 groups of (n / 4)^2 tiles
+    const uint64_t ntr4 = ((uint64_t)n + 3) / 4;
+    L.range_items = (uint32_t)(ntr4 > 362 ? kMaxRangeItems : std::min<uint64_t>(kMaxRangeItems, 8 * ntr4 * ntr4));
+    L.ranges = (uint32_t *)take((size_t)L.range_items * 2 * 4);
     L.bytes = off;
     return L;
 }
@@ -426,6 +599,9 @@ int make_args(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, uint32_t 
     // the persistent kernel's work counter runs past nitems by at most one claim per wave
     if (items >= (1ull << 32) - (1ull << 24)) return B2SR_ERANGE;
     b.nitems = (uint32_t)items;
+    b.coarse = L.coarse;
+    b.coarse_words = L.coarse_words;
+    b.ranges = items <= L.range_items ? L.ranges : nullptr;
     *out = b;
     return B2SR_OK;
 }
@@ -436,6 +612,10 @@ int launch_init(const BatchArgs &b, hipStream_t stream)
 {
     batch_init_kernel<<<vgrid((uint64_t)b.n * 64), 256, 0, stream>>>(b);
     if (int rc = b2sr::check_launch("batch_init_kernel")) return rc;
+    if (b.ranges && b.nitems) {
+        batch_ranges_kernel<<<b2sr::grid_for(b.nitems, 4, 16384), 256, 0, stream>>>(b);
+        if (int rc = b2sr::check_launch("batch_ranges_kernel")) return rc;
+    }
     if (b.nseeds) {
         batch_seed_kernel<<<vgrid(b.nseeds), 256, 0, stream>>>(b);
         if (int rc = b2sr::check_launch("batch_seed_kernel")) return rc;
@@ -504,6 +684,8 @@ int finish_persistent(const BatchArgs &b, uint32_t *iters, hipStream_t s)
     return B2SR_OK;
 }
 
+Skip skip_of(const BatchArgs &b, const Group &g) { return Skip{b.ranges, b.coarse, b.coarse_words, g.item0}; }
+
 // One level: each group's product, the update, the advance (stream order).
 int launch_level(const BatchArgs &b, hipStream_t stream)
 {
@@ -511,12 +693,13 @@ int launch_level(const BatchArgs &b, hipStream_t stream)
         const Group &g = b.g[k];
         if (!g.nchunks) continue;
         const unsigned grid = b2sr::grid_for(g.nchunks, 4);
+        const Skip sk = skip_of(b, g);
         switch (g.tile) {
-        case 4: batch_product_kernel<4><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
-        case 8: batch_product_kernel<8><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
-        case 16: batch_product_kernel<16><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
-        case 64: batch_product_kernel<64><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
-        default: batch_product_kernel<32><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags); break;
+        case 4: batch_product_kernel<4><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags, sk); break;
+        case 8: batch_product_kernel<8><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags, sk); break;
+        case 16: batch_product_kernel<16><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags, sk); break;
+        case 64: batch_product_kernel<64><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags, sk); break;
+        default: batch_product_kernel<32><<<grid, 256, 0, stream>>>(g.p, g.nchunks, b.flags, sk); break;
         }
         if (int rc = b2sr::check_launch("batch_product_kernel")) return rc;
     }
@@ -567,7 +750,8 @@ int add_levels(hipGraph_t g, hipGraphNode_t *last, BatchArgs &b, uint32_t levels
         for (uint32_t k = 0; k < b.ngroups; ++k) {
             Group &gr = b.g[k];
             if (!gr.nchunks) continue;
-            void *args_p[] = {&gr.p, &gr.nchunks, &b.flags};
+            Skip sk = skip_of(b, gr);  // (a node copies its arguments)
+            void *args_p[] = {&gr.p, &gr.nchunks, &b.flags, &sk};
             const void *f = gr.tile == 4    ? (const void *)batch_product_kernel<4>
                             : gr.tile == 8  ? (const void *)batch_product_kernel<8>
                             : gr.tile == 16 ? (const void *)batch_product_kernel<16>
@@ -658,6 +842,8 @@ int b2sr_msbfs_batch_plan_create(uint32_t n, uint32_t ngroups, const b2sr_matrix
     if (!rc) rc = b2sr::check(hipMemset(b.flags + 5, 0, sizeof(uint32_t)), "hipMemset(time-out flag)");
     if (!rc) rc = b2sr::check(hipGraphCreate(&P->first, 0), "hipGraphCreate");
     if (!rc) rc = add_node(P->first, &last, (const void *)batch_init_kernel, vgrid((uint64_t)n * 64), 256, args_b);
+    if (!rc && b.ranges && b.nitems)
+        rc = add_node(P->first, &last, (const void *)batch_ranges_kernel, b2sr::grid_for(b.nitems, 4, 16384), 256, args_b);
     if (!rc && nseeds) rc = add_node(P->first, &last, (const void *)batch_seed_kernel, vgrid(nseeds), 256, args_b);
     if (!rc && mode == B2SR_BATCH_PERSISTENT) {
         unsigned grid = 0;
