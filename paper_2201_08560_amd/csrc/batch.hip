@@ -224,38 +224,36 @@ __device__ __forceinline__ bool update_group(const BatchArgs &b, uint64_t base, 
     return y != 0;
 }
 
-// The update of `level` for wave `wave` of `nwaves`: a contiguous run of
-// 64-vertex groups, so that the wave sets each summary bit its run reaches
-// once (one atomic per bit and wave; a wave per group in a grid-stride order
-// put an atomic per group on the summary's few cache lines, and the update
-// took 20 % longer).  Returns the number of vertices with new bits.
+// The update of `level` for wave `wave` of `nwaves`: whole 1024-vertex runs
+// (16 groups of 64, one summary bit) in a grid-stride order, so that the wave
+// sets a run's summary bit once (a wave per group put an atomic per group on
+// the summary's few cache lines, and the update took 20 % longer; one
+// contiguous stretch per wave was slower still at light levels).  Returns the
+// number of vertices with new bits; with BITS, *fresh_bits receives the
+// number of summary bits this wave set first.
 template <bool BITS = false>
 __device__ __forceinline__ uint32_t update_run(const BatchArgs &b, uint64_t wave, uint64_t nwaves, uint32_t level,
                                                uint32_t *fresh_bits = nullptr)
 {
-    const uint64_t groups = ((uint64_t)b.n + 63) / 64, per = (groups + nwaves - 1) / nwaves;
+    constexpr uint32_t kRunGroups = (1u << kCoarseShift) / 64;
+    const uint32_t groups = (uint32_t)(((uint64_t)b.n + 63) / 64);
+    const uint32_t runs = (groups + kRunGroups - 1) / kRunGroups;
     uint32_t *const c = b.coarse + (level & 1) * b.coarse_words;
-    uint32_t count = 0, pend = 0xFFFFFFFFu;  // the summary bit waiting to be set
-    uint32_t fresh = 0;                      // (BITS) bits this wave set first
-    auto set = [&](uint32_t k) {
+    uint32_t count = 0, fresh = 0;
+    for (uint64_t r = wave; r < runs; r += nwaves) {
+        const uint32_t g0 = (uint32_t)r * kRunGroups, g1 = min(g0 + kRunGroups, groups);
+        uint32_t found = 0;
+        for (uint32_t g = g0; g < g1; ++g) found += (uint32_t)__popcll(__ballot(update_group(b, (uint64_t)g * 64, level)));
+        if (!found) continue;
+        count += found;
         uint32_t f = 0;
         if (lane_id() == 0) {
-            if constexpr (BITS) f = (atomicOr(c + k / 32, 1u << (k & 31)) >> (k & 31)) & 1u ? 0u : 1u;
-            else atomicOr(c + k / 32, 1u << (k & 31));
+            const uint32_t bit = 1u << (r & 31);
+            if constexpr (BITS) f = (atomicOr(c + r / 32, bit) & bit) ? 0u : 1u;
+            else atomicOr(c + r / 32, bit);
         }
         if constexpr (BITS) fresh += readfirstlane(f);
-    };
-    for (uint64_t g = wave * per, ge = min(g + per, groups); g < ge; ++g) {
-        const uint64_t m = __ballot(update_group(b, g * 64, level));
-        if (!m) continue;
-        count += (uint32_t)__popcll(m);
-        const uint32_t k = (uint32_t)((g * 64) >> kCoarseShift);
-        if (k != pend) {
-            if (pend != 0xFFFFFFFFu) set(pend);
-            pend = k;
-        }
     }
-    if (pend != 0xFFFFFFFFu) set(pend);
     if constexpr (BITS) *fresh_bits = fresh;
     return count;
 }
