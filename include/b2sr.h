@@ -321,7 +321,11 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
  * batches of 2, 4, 8 and then 16 and reads the state once per batch, and the
  * iterations enqueued past the end return at once.  MIS and colouring read
  * one device word per iteration; PageRank runs a fixed
- * number of iterations and reads nothing.  The number of iterations run is
+ * number of iterations and reads nothing.  These reads (and the tile count
+ * of b2sr_count_tiles, and the batched BFS's flags) land in 64 bytes of pinned
+ * host memory held per host thread, allocated on the thread's first read and
+ * kept until the process ends (a read into pageable memory costs a staging
+ * copy on the device).  The number of iterations run is
  * written to the HOST pointer *iters when it is not NULL.  ws is a workspace
  * of b2sr_algo_workspace_bytes(A, algo) bytes.  The drivers read A as the
  * pull matrix: row i lists the vertices whose edges reach i, so each product

@@ -96,10 +96,7 @@ template <class F> int run_gated(const uint32_t *flags, uint32_t max_iters, uint
     for (;;) {
         for (uint32_t k = 0; k < batch; ++k)
             if (int rc = one(++enq)) return rc;
-        if (int rc = b2sr::check(hipMemcpyAsync(h, flags + kState, sizeof h, hipMemcpyDeviceToHost, s),
-                                 "hipMemcpyAsync(state)"))
-            return rc;
-        if (int rc = b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize")) return rc;
+        if (int rc = b2sr::read_words(flags + kState, h, 4, s)) return rc;
         if (h[0] == kDone) break;
         if (enq > max_iters + 1) return B2SR_EHIP;  // cannot happen: the run ends by max_iters
         batch = h[2] < h[3] ? 2u : std::min<uint32_t>(batch * 2, 16);
@@ -108,12 +105,7 @@ template <class F> int run_gated(const uint32_t *flags, uint32_t max_iters, uint
     return B2SR_OK;
 }
 
-int read_flag(const uint32_t *d_flag, uint32_t *h, hipStream_t s)
-{
-    if (int rc = b2sr::check(hipMemcpyAsync(h, d_flag, sizeof *h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync(flag)"))
-        return rc;
-    return b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize");
-}
+int read_flag(const uint32_t *d_flag, uint32_t *h, hipStream_t s) { return b2sr::read_words(d_flag, h, 1, s); }
 
 // ---------------------------------------------------------------- BFS
 __global__ void bfs_init_kernel(uint32_t n, uint32_t src, uint32_t *levels, uint32_t *frontier, uint32_t *visited,

@@ -659,18 +659,11 @@ int launch_persistent(BatchArgs &b, hipStream_t stream)
                        "hipLaunchCooperativeKernel(batch_persistent_kernel)");
 }
 
-int read_u32(const uint32_t *d, uint32_t *h, hipStream_t s)
-{
-    if (int rc = b2sr::check(hipMemcpyAsync(h, d, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync")) return rc;
-    return b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize");
-}
-
 // Reads the levels run and the barrier time-out flag after a persistent run.
 int finish_persistent(const BatchArgs &b, uint32_t *iters, hipStream_t s)
 {
     uint32_t h[6] = {0, 0, 0, 0, 0, 0};
-    if (int rc = b2sr::check(hipMemcpyAsync(h, b.flags, sizeof h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync")) return rc;
-    if (int rc = b2sr::check(hipStreamSynchronize(s), "hipStreamSynchronize")) return rc;
+    if (int rc = b2sr::read_words(b.flags, h, 6, s)) return rc;
     if (h[5]) {
         // clear the flag so that the next launch runs again, then report the time-out
         if (int rc = b2sr::fill_u32(b.flags + 5, 1, 0, s)) return rc;
@@ -786,9 +779,7 @@ int b2sr_msbfs_batch(uint32_t n, uint32_t ngroups, const b2sr_matrix *groups, ui
     uint32_t h[8] = {0};
     do {
         if ((rc = launch_level(b, stream))) return rc;
-        if ((rc = b2sr::check(hipMemcpyAsync(h, b.flags, sizeof h, hipMemcpyDeviceToHost, stream), "hipMemcpyAsync")))
-            return rc;
-        if ((rc = b2sr::check(hipStreamSynchronize(stream), "hipStreamSynchronize"))) return rc;
+        if ((rc = b2sr::read_words(b.flags, h, 8, stream))) return rc;
     } while (!h[6]);
     if (iters) *iters = h[2];
     return B2SR_OK;
@@ -883,10 +874,7 @@ int b2sr_msbfs_batch_plan_launch(b2sr_msbfs_plan plan, uint32_t *iters, hipStrea
     // per-level plan: replay the continuation until the device says the BFS finished
     uint32_t h[8] = {0};
     for (;;) {
-        if ((rc = b2sr::check(hipMemcpyAsync(h, plan->args.flags, sizeof h, hipMemcpyDeviceToHost, stream),
-                              "hipMemcpyAsync")))
-            return rc;
-        if ((rc = b2sr::check(hipStreamSynchronize(stream), "hipStreamSynchronize"))) return rc;
+        if ((rc = b2sr::read_words(plan->args.flags, h, 8, stream))) return rc;
         if (h[6]) break;
         if ((rc = b2sr::check(hipGraphLaunch(plan->more_exec, stream), "hipGraphLaunch"))) return rc;
     }

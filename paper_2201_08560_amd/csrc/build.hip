@@ -353,10 +353,7 @@ int b2sr_count_tiles(uint32_t n, uint64_t nnz, const uint32_t *rowptr, const uin
     scan_counts_kernel<<<1, 1024, 0, stream>>>(ntr, tile_rowptr);
     if ((rc = b2sr::check_launch("scan_counts_kernel"))) return rc;
     uint32_t total = 0;
-    if ((rc = b2sr::check(hipMemcpyAsync(&total, tile_rowptr + ntr, sizeof total, hipMemcpyDeviceToHost, stream),
-                          "hipMemcpyAsync(tile count)")))
-        return rc;
-    if ((rc = b2sr::check(hipStreamSynchronize(stream), "hipStreamSynchronize"))) return rc;
+    if ((rc = b2sr::read_words(tile_rowptr + ntr, &total, 1, stream))) return rc;
     *ntiles = total;
     return B2SR_OK;
 }

@@ -17,6 +17,27 @@ void set_hip_error(hipError_t e, const char *where)
 
 void clear_hip_error() { g_last_hip_error[0] = 0; }
 
+int read_words(const uint32_t *d, uint32_t *h, uint32_t count, hipStream_t stream)
+{
+    constexpr uint32_t kPinnedWords = 16;
+    thread_local uint32_t *pinned = nullptr;
+    thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        if (hipHostMalloc((void **)&pinned, kPinnedWords * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            pinned = nullptr;
+        }
+    }
+    uint32_t *const dst = pinned && count <= kPinnedWords ? pinned : h;
+    if (int rc = check(hipMemcpyAsync(dst, d, (size_t)count * sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
+                       "hipMemcpyAsync(device words)"))
+        return rc;
+    if (int rc = check(hipStreamSynchronize(stream), "hipStreamSynchronize")) return rc;
+    if (dst != h) memcpy(h, dst, (size_t)count * sizeof(uint32_t));
+    return B2SR_OK;
+}
+
 int validate_matrix(const b2sr_matrix *A)
 {
     if (!A) return B2SR_EINVAL;

@@ -15,6 +15,12 @@ namespace b2sr {
 
 void set_hip_error(hipError_t e, const char *where);
 void clear_hip_error();
+// Reads `count` (<= 16) words of device memory at d into the host array h and
+// synchronises `stream`.  The copy lands in pinned host words held per host
+// thread (allocated on the thread's first read, kept until the process ends):
+// a copy into pageable memory goes through a staging blit of about 20 us.
+// Falls back to copying into h directly if that allocation failed.
+int read_words(const uint32_t *d, uint32_t *h, uint32_t count, hipStream_t stream);
 
 // Returns B2SR_EHIP (recording the text) when e is not hipSuccess.
 inline int check(hipError_t e, const char *where)
