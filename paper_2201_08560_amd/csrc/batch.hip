@@ -164,9 +164,11 @@ __global__ void batch_ranges_kernel(BatchArgs b)
         }
         if (lane == 0) {
             const bool empty = lo > hi;  // no tiles: never live
+            // (the last tile column's padding past n would reach one bit past the summary)
+            const uint32_t last = (uint32_t)(((uint64_t)b.n - 1) >> kCoarseShift);
             b.ranges[2 * (size_t)item] = empty ? 1u : (uint32_t)(((uint64_t)lo * g.tile) >> kCoarseShift);
             b.ranges[2 * (size_t)item + 1] =
-                empty ? 0u : (uint32_t)(((uint64_t)hi * g.tile + g.tile - 1) >> kCoarseShift);
+                empty ? 0u : min(last, (uint32_t)(((uint64_t)hi * g.tile + g.tile - 1) >> kCoarseShift));
         }
     }
 }
