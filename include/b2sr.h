@@ -315,13 +315,13 @@ int spgemm_masked_profile(const b2sr_matrix *A, const b2sr_matrix *Bt, const b2s
 /* ---- graph algorithms on the products above (Sec. V) ---------------------
  * Each driver runs its iteration loop on the host, launching the kernels
  * above on `stream`, and synchronises `stream` to test convergence.  BFS,
- * multi-source BFS, SSSP, CC and eccentricity keep their convergence state on
- * the device:
+ * multi-source BFS, SSSP, CC, eccentricity, MIS and colouring keep their
+ * convergence state on the device:
  * every kernel of an iteration is gated on it, the host enqueues iterations in
  * batches of 2, 4, 8 and then 16 and reads the state once per batch, and the
- * iterations enqueued past the end return at once.  MIS and colouring read
- * one device word per iteration; PageRank runs a fixed
- * number of iterations and reads nothing.  These reads (and the tile count
+ * iterations enqueued past the end return at once (MIS and colouring also read
+ * one word before the first round: whether any vertex has a key).  PageRank
+ * runs a fixed number of iterations and reads nothing.  These reads (and the tile count
  * of b2sr_count_tiles, and the batched BFS's flags) land in 64 bytes of pinned
  * host memory held per host thread, allocated on the thread's first read and
  * kept until the process ends (a read into pageable memory costs a staging

@@ -22,7 +22,7 @@ namespace b2sr {
 int column_counts(const b2sr_matrix *A, uint32_t *colsum, hipStream_t s);
 size_t lgc_workspace_bytes(const b2sr_matrix *A);
 // The products with every kernel gated on *gate == gate_val (spmv.hip); the
-// full product takes B2SR_MIN_PLUS_U32 and B2SR_OR_U64 only.
+// full product takes B2SR_MIN_PLUS_U32, B2SR_OR_U64 and B2SR_MAX_TIMES_U64.
 int spmv_bits_gated(const b2sr_matrix *A, const uint32_t *x, const uint32_t *mask, unsigned flags, void *y,
                     const uint32_t *gate, uint32_t gate_val, hipStream_t stream);
 int spmv_full_gated(const b2sr_matrix *A, int semiring, const void *x, const uint32_t *x_active, unsigned flags,
@@ -52,7 +52,10 @@ struct Carver {
 // iteration's count of found units (low half); then the next iteration's run
 // state, the iterations run, and the last two iterations' counts.
 constexpr uint32_t kRunDense = 0, kRunSparse = 1, kDone = 2;
-constexpr uint32_t kState = 4, kIters = 5, kLast = 6, kPrev = 7, kFlagWords = 8;
+constexpr uint32_t kState = 4, kIters = 5, kLast = 6, kPrev = 7, kFlagWords = 10;
+// MIS and colouring also keep: whether the next round starts a colour pass,
+// and the current colour.
+constexpr uint32_t kPass = 8, kColor = 9;
 
 // Ends a gated update kernel (every thread calls it; found_wave is this wave's
 // count, read from lane 0).  Each block adds its count and itself to the
@@ -386,10 +389,61 @@ __global__ void mis_start_kernel(uint32_t n, const uint64_t *key, const uint32_t
 }
 
 // A candidate joins when its key is at least the largest candidate key among
-// its neighbours (Y = A max-times X).
-__global__ void mis_join_kernel(uint32_t n, const uint64_t *X, const uint64_t *Y, uint32_t *joined, uint32_t *mis_bits,
-                                uint32_t *colors, uint32_t color)
+// its neighbours (Y = A max-times X); joined vertices and their neighbours
+// (nb = A OR joined) stop being candidates.
+// The gated rounds.  A round is: (colouring, when the last round ended a
+// pass) a new pass's candidates; Y = A max-times X; the joins; the joined
+// vertices' neighbours; the removals.  The removal kernel's last block sets
+// the next round's state from two per-block tallies packed into the one
+// 64-bit accumulator: blocks that still hold candidates (low 16 bits) and,
+// when colouring, blocks that hold uncoloured vertices with a key (high 16;
+// at most 1024 blocks, so neither field overflows).  No candidates left ends
+// the pass: colouring starts the next one while vertices remain uncoloured.
+__device__ bool finish_round(uint32_t *flags, uint32_t it, bool cand, bool uncol, bool colouring, uint32_t max_iters)
 {
+    __shared__ uint32_t s_found;
+    if (threadIdx.x == 0) s_found = 0;
+    __syncthreads();
+    if (lane_id() == 0 && (cand || uncol)) atomicOr(&s_found, (cand ? 1u : 0u) | (uncol ? 0x10000u : 0u));
+    __syncthreads();
+    if (threadIdx.x != 0) return false;
+    unsigned long long *acc = (unsigned long long *)flags + (it & 1);
+    const unsigned long long old = atomicAdd(acc, (1ull << 32) | s_found);
+    if ((uint32_t)(old >> 32) != gridDim.x - 1) return false;
+    const uint32_t found = (uint32_t)old + s_found;
+    atomicExch(acc, 0ull);
+    const uint32_t cand_blocks = found & 0xFFFFu, uncol_blocks = found >> 16;
+    const bool next_pass = cand_blocks == 0 && colouring && uncol_blocks != 0;
+    atomicExch(flags + kPrev, atomicExch(flags + kLast, cand_blocks));
+    atomicExch(flags + kIters, it);
+    atomicExch(flags + kPass, next_pass ? 1u : 0u);
+    if (next_pass) atomicAdd(flags + kColor, 1u);
+    atomicExch(flags + kState, ((cand_blocks == 0 && !next_pass) || it >= max_iters) ? kDone : kRunDense);
+    return true;
+}
+
+__global__ void mis_start_gated_kernel(uint32_t n, const uint64_t *key, const uint32_t *colors, uint64_t *X,
+                                       uint32_t *act, const uint32_t *flags)
+{
+    if (flags[kState] != kRunDense || !flags[kPass]) return;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
+         base += waves * 64) {
+        const uint64_t i = base + lane_id();
+        uint64_t x = 0;
+        if (i < n) {
+            x = colors[i] == kUnreached ? key[i] : 0ull;
+            X[i] = x;
+        }
+        store_pred_bits(act, base, n, x != 0);
+    }
+}
+
+__global__ void mis_join_gated_kernel(uint32_t n, const uint64_t *X, const uint64_t *Y, uint32_t *joined,
+                                      uint32_t *mis_bits, uint32_t *colors, const uint32_t *flags)
+{
+    if (flags[kState] != kRunDense) return;
+    const uint32_t color = flags[kColor];
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
     for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
          base += waves * 64) {
@@ -410,11 +464,13 @@ __global__ void mis_join_kernel(uint32_t n, const uint64_t *X, const uint64_t *Y
     }
 }
 
-// Joined vertices and their neighbours (nb = A OR joined) stop being candidates.
-__global__ void mis_remove_kernel(uint32_t n, uint64_t *X, const uint32_t *joined, const uint32_t *nb, uint32_t *act,
-                                  uint32_t *flag_now, uint32_t *flag_next)
+__global__ void mis_remove_gated_kernel(uint32_t n, uint64_t *X, const uint32_t *joined, const uint32_t *nb,
+                                        uint32_t *act, const uint64_t *key, const uint32_t *colors, uint32_t *flags,
+                                        uint32_t max_iters)
 {
-    bool any = false;
+    if (flags[kState] != kRunDense) return;
+    const uint32_t it = flags[kIters] + 1;
+    bool cand = false, uncol = false;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / B2SR_WAVE);
     for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / B2SR_WAVE) + threadIdx.x / B2SR_WAVE) * 64; base < n;
          base += waves * 64) {
@@ -426,12 +482,12 @@ __global__ void mis_remove_kernel(uint32_t n, uint64_t *X, const uint32_t *joine
                 x = 0;
                 X[i] = 0;
             }
+            if (colors) uncol |= colors[i] == kUnreached && key[i] != 0;
         }
-        any |= x != 0;
+        cand |= x != 0;
         store_pred_bits(act, base, n, x != 0);
     }
-    if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(flag_now, 1u);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *flag_next = 0;
+    finish_round(flags, it, __any(cand), __any(uncol), colors != nullptr, max_iters);
 }
 
 unsigned vgrid(uint64_t n) { return b2sr::grid_for(n, 256, 8192); }
@@ -738,40 +794,43 @@ int independent_sets(const b2sr_matrix *A, const uint64_t *key, uint32_t *mis_bi
     if (n > 0 && (!key || (!mis_bits && !colors))) return B2SR_EINVAL;
     if (mis_bits && (rc = b2sr::fill_u32(mis_bits, nw, 0, stream))) return rc;
     if (colors && (rc = b2sr::fill_u32(colors, n, kUnreached, stream))) return rc;
-    if ((rc = b2sr::fill_u32(L.flags, 2, 0, stream))) return rc;
-    uint32_t rounds = 0, color = 0, f = 0;
-    auto flags = [&](uint32_t **now, uint32_t **next) {
-        *now = L.flags + (f & 1);
-        *next = L.flags + ((f + 1) & 1);
-        ++f;
-    };
-    while (n > 0) {  // one colour per pass (a single pass for MIS)
-        uint32_t *fnow, *fnext, any = 0;
-        flags(&fnow, &fnext);
-        mis_start_kernel<<<fgrid(n), 256, 0, stream>>>(n, key, colors, L.F, L.act, fnow, fnext);
-        if ((rc = b2sr::check_launch("mis_start_kernel"))) return rc;
-        if ((rc = read_flag(fnow, &any, stream))) return rc;
-        if (!any) break;
-        // every round places at least the candidate of largest key, so a pass ends
-        for (;;) {
-            ++rounds;
-            if ((rc = spmv_bin_full(A, B2SR_MAX_TIMES_U64, L.F, nullptr, L.act, nullptr, 0, 0.0, 0.0, L.Y, nullptr,
-                                    0, stream)))
-                return rc;
-            mis_join_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.F, L.Y, L.frontier, mis_bits, colors, color);
-            if ((rc = b2sr::check_launch("mis_join_kernel"))) return rc;
-            if ((rc = spmv_bin_bin(A, L.frontier, nullptr, 0, L.next, stream))) return rc;
-            flags(&fnow, &fnext);
-            mis_remove_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.F, L.frontier, L.next, L.act, fnow, fnext);
-            if ((rc = b2sr::check_launch("mis_remove_kernel"))) return rc;
-            if ((rc = read_flag(fnow, &any, stream))) return rc;
-            if (!any) break;
-        }
-        ++color;
-        if (!colors) break;
-    }
+    if (iters) *iters = 0;
+    if (ncolors) *ncolors = 0;
+    if (n == 0) return B2SR_OK;
+    // state dense, no pass pending, colour 0; the first pass's candidates, and
+    // whether there are any (in kLast)
+    if ((rc = b2sr::fill_u32(L.flags, kFlagWords, 0, stream))) return rc;
+    mis_start_kernel<<<fgrid(n), 256, 0, stream>>>(n, key, colors, L.F, L.act, L.flags + kLast, L.flags + kPrev);
+    if ((rc = b2sr::check_launch("mis_start_kernel"))) return rc;
+    uint32_t any = 0;
+    if ((rc = read_flag(L.flags + kLast, &any, stream))) return rc;
+    if (!any) return B2SR_OK;
+    // every round places at least the candidate of largest key, so n rounds suffice
+    const uint32_t max_iters = n + 1;
+    uint32_t rounds = 0;
+    if ((rc = run_gated(L.flags, max_iters, &rounds, stream, [&](uint32_t) {
+             if (colors) {
+                 mis_start_gated_kernel<<<fgrid(n), 256, 0, stream>>>(n, key, colors, L.F, L.act, L.flags);
+                 if (int r = b2sr::check_launch("mis_start_gated_kernel")) return r;
+             }
+             if (int r = b2sr::spmv_full_gated(A, B2SR_MAX_TIMES_U64, L.F, L.act, 0, 0.0, L.Y, L.flags + kState,
+                                               kRunDense, stream))
+                 return r;
+             mis_join_gated_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.F, L.Y, L.frontier, mis_bits, colors, L.flags);
+             if (int r = b2sr::check_launch("mis_join_gated_kernel")) return r;
+             if (int r = b2sr::spmv_bits_gated(A, L.frontier, nullptr, 0, L.next, L.flags + kState, kRunDense, stream))
+                 return r;
+             mis_remove_gated_kernel<<<fgrid(n), 256, 0, stream>>>(n, L.F, L.frontier, L.next, L.act, key, colors,
+                                                                   L.flags, max_iters);
+             return b2sr::check_launch("mis_remove_gated_kernel");
+         })))
+        return rc;
     if (iters) *iters = rounds;
-    if (ncolors) *ncolors = colors ? color : 0;
+    if (ncolors && colors) {
+        uint32_t last = 0;
+        if ((rc = b2sr::read_words(L.flags + kColor, &last, 1, stream))) return rc;
+        *ncolors = last + 1;
+    }
     return B2SR_OK;
 }
 

@@ -404,6 +404,7 @@ int spmv_full_gated(const b2sr_matrix *A, int semiring, const void *x, const uin
     switch (semiring) {
     case B2SR_MIN_PLUS_U32: return dispatch<kMinU32>(A->tile, p, stream);
     case B2SR_OR_U64: return dispatch<kOr64>(A->tile, p, stream);
+    case B2SR_MAX_TIMES_U64: return dispatch<kMaxU64>(A->tile, p, stream);
     default: return B2SR_ENOTSUP;
     }
 }
