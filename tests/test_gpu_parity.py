@@ -294,6 +294,28 @@ def test_mis_and_color(gi, T):
     assert nc == exp_nc and np.array_equal(b2.as_u32(col), exp_col)
 
 
+@pytest.mark.parametrize("gi", range(len(GRAPHS)), ids=IDS)
+def test_mis_and_color_with_keyless_vertices(gi):
+    """Vertices whose key is 0 are never candidates: they stay out of the set and
+    uncoloured, and colouring still ends (a pass starts only while keyed
+    vertices are uncoloured).  All keys 0: no round, no colour."""
+    g = GRAPHS[gi]
+    A = b2sr(g, 16)
+    key = b2.mis_keys(g.n, 90 + gi).clone()
+    key[::7] = 0
+    k = b2.as_u64(key)
+    m, rounds = b2.b2sr_mis(A, key)
+    exp, exp_rounds = orc.mis(g, k)
+    assert np.array_equal(unpack_bits(b2.as_u32(m), g.n), exp) and rounds == exp_rounds
+    col, nc = b2.b2sr_color(A, key)
+    exp_col, exp_nc = orc.color(g, k)
+    assert nc == exp_nc and np.array_equal(b2.as_u32(col), exp_col)
+    zero = torch.zeros_like(key)
+    m0, r0 = b2.b2sr_mis(A, zero)
+    c0, n0 = b2.b2sr_color(A, zero)
+    assert r0 == 0 and n0 == 0 and not b2.as_u32(m0).any() and np.all(b2.as_u32(c0) == b2.UNREACHED)
+
+
 @pytest.mark.parametrize("T", TILES)
 @pytest.mark.parametrize("gi", range(len(GRAPHS)), ids=IDS)
 def test_eccentricity_and_diameter(gi, T):
