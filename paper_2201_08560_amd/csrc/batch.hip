@@ -423,7 +423,7 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (uint32_t level = 1; level <= b.max_levels; ++level) {
         if (b.stamps) stamp(b, level, 0);
-        // Waves claim kClaimItems consecutive work items at a time from this
+        // Waves claim per_claim consecutive work items at a time from this
         // level's counter, so a wave that drew light chunks takes more of them
         // (a fixed stride left the heaviest wave 30 % behind the median).  The
         // counter only grows during the product phase, so every wave leaves
@@ -438,11 +438,14 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
         const uint32_t frontier = readfirstlane(level == 1 ? b.nseeds : b.flags[(level - 1) & 1]);
         // When under 1/4 of the summary bits are set (and every item has a
         // column range), waves take items at a fixed stride instead: per_claim
-        // 0.  Most items are then dead, and a claim per item on the one counter
-        // (about 18 ns each, serialised) set the level's time whatever the
-        // work.  Level 1's summary (the seeds) is not counted: it claims.
+        // 0, and test each item against the summary.  Most items are then
+        // dead, and a claim per item on the one counter (about 18 ns each,
+        // serialised) set the level's time whatever the work.  Claimed items
+        // are not tested: at those levels almost all are live.  Level 1's
+        // summary (the seeds) is not counted: it claims.
         const uint32_t live_bits = level == 1 ? 0xFFFFFFFFu : readfirstlane(b.flags[kLiveBits + ((level - 1) & 1)]);
-        const bool few = b.ranges && (uint64_t)live_bits * B2SR_PERSIST_STRIDE_BELOW < (((uint64_t)b.n + (1u << kCoarseShift) - 1) >> kCoarseShift);
+        const uint64_t summary_bits = ((uint64_t)b.n + (1u << kCoarseShift) - 1) >> kCoarseShift;
+        const bool few = b.ranges && (uint64_t)live_bits * B2SR_PERSIST_STRIDE_BELOW < summary_bits;
         const bool small = (uint64_t)frontier < (uint64_t)b.nitems * B2SR_PERSIST_SPARSE_FACTOR;
         const uint32_t per_claim = few ? 0u : small ? B2SR_PERSIST_CLAIM_SPARSE : B2SR_PERSIST_CLAIM;
         uint32_t claims = 0, next = wave;
