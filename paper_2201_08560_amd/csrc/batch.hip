@@ -226,18 +226,21 @@ __device__ __forceinline__ bool update_group(const BatchArgs &b, uint64_t base, 
     return y != 0;
 }
 
-// The update of `level` for wave `wave` of `nwaves`: whole 1024-vertex runs
-// (16 groups of 64, one summary bit) in a grid-stride order, so that the wave
-// sets a run's summary bit once (a wave per group put an atomic per group on
-// the summary's few cache lines, and the update took 20 % longer; one
-// contiguous stretch per wave was slower still at light levels).  Returns the
-// number of vertices with new bits; with BITS, *fresh_bits receives the
-// number of summary bits this wave set first.
-template <bool BITS = false>
+// The update of `level` for wave `wave` of `nwaves`: runs of RUN groups of 64
+// vertices in a grid-stride order, so that the wave sets a run's summary bit
+// once (a wave per group put an atomic per group on the summary's few cache
+// lines, and the update took 20 % longer; one contiguous stretch per wave was
+// slower still at light levels).  The per-level kernel takes whole 1024-vertex
+// runs (one summary bit each); the persistent kernel, whose update ends at a
+// grid barrier, takes 256-vertex runs, which balance its waves better (256-graph
+// batch: 20.05 -> 19.7 ms).  Returns the number of vertices with new bits; with
+// BITS, *fresh_bits receives the number of summary bits this wave set first.
+template <bool BITS = false, uint32_t RUN = (1u << kCoarseShift) / 64>
 __device__ __forceinline__ uint32_t update_run(const BatchArgs &b, uint64_t wave, uint64_t nwaves, uint32_t level,
                                                uint32_t *fresh_bits = nullptr)
 {
-    constexpr uint32_t kRunGroups = (1u << kCoarseShift) / 64;
+    static_assert(RUN >= 1 && ((1u << kCoarseShift) / 64) % RUN == 0, "a run lies inside one summary bit");
+    constexpr uint32_t kRunGroups = RUN;
     const uint32_t groups = (uint32_t)(((uint64_t)b.n + 63) / 64);
     const uint32_t runs = (groups + kRunGroups - 1) / kRunGroups;
     uint32_t *const c = b.coarse + (level & 1) * b.coarse_words;
@@ -250,9 +253,10 @@ __device__ __forceinline__ uint32_t update_run(const BatchArgs &b, uint64_t wave
         count += found;
         uint32_t f = 0;
         if (lane_id() == 0) {
-            const uint32_t bit = 1u << (r & 31);
-            if constexpr (BITS) f = (atomicOr(c + r / 32, bit) & bit) ? 0u : 1u;
-            else atomicOr(c + r / 32, bit);
+            const uint32_t k = (uint32_t)((r * kRunGroups * 64) >> kCoarseShift);  // the run's summary bit
+            const uint32_t bit = 1u << (k & 31);
+            if constexpr (BITS) f = (atomicOr(c + k / 32, bit) & bit) ? 0u : 1u;
+            else atomicOr(c + k / 32, bit);
         }
         if constexpr (BITS) fresh += readfirstlane(f);
     }
@@ -497,7 +501,7 @@ __global__ void __launch_bounds__(kPersistThreads, persistent_waves(TMASK)) batc
         __syncthreads();
         clear_other_summary(b, level, tid, (uint64_t)gridDim.x * blockDim.x);
         uint32_t fresh = 0;
-        const uint32_t count = update_run<true>(b, wave, nwaves, level, &fresh);
+        const uint32_t count = update_run<true, 4>(b, wave, nwaves, level, &fresh);
         if (lane_id() == 0 && count) atomicAdd(&s_count, count);
         if (lane_id() == 0 && fresh) atomicAdd(&s_fresh, fresh);
         __syncthreads();
